@@ -1,0 +1,180 @@
+"""Seeded synthetic workloads: meshes, initial states, drag, region masks.
+
+Inputs only: nothing here evaluates a tendency or takes a time step.  The
+recipes (shapes, distributions, seeds) stand in for the paper's Delaware Bay
+meshes and hurricane forcing, which are not available; every random number is
+drawn from ``numpy.random.Generator(PCG64(seed))``.
+
+* ``config1``: periodic regular hexagonal mesh 32 x 32, dc = 10 km, H = 1000 m,
+  f = 1e-4, linear; inertia-gravity plane wave a = 0.1 m, wavenumber (2, 1);
+  a band of 8 full rows (start row from the seed) marked fine; M = 2.
+* ``config2``: planar periodic variable-resolution CVT, 50k cells, 2 -> 8 km
+  over a Gaussian patch, 50 Lloyd iterations; depth 4000 m minus six Gaussian
+  seamount bumps (min 50 m); nonlinear with quadratic drag; at rest with three
+  Gaussian SSH bumps; fine cells chosen from the local CFL number; M = 4.
+* ``ensemble_members``: per-member SSH perturbations and drag coefficients.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import meshgen
+
+G = 9.81
+NU_MAX_FBRK32 = 1.58   # measured gravity-wave Courant limit of FB-RK(3,2) on the hex mesh
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: meshgen.Mesh
+    h0: np.ndarray
+    u0: np.ndarray
+    fine_mask: np.ndarray
+    dt: float
+    M: int
+    linear: bool
+    cd: np.ndarray | None = None
+    steps: int = 200
+    meta: dict = field(default_factory=dict)
+
+
+def rng_for(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ----------------------------------------------------------------------------
+# configuration 1: linear inertia-gravity wave on the periodic hexagonal mesh
+# ----------------------------------------------------------------------------
+
+def igw_state(mesh, t, amp=0.1, kx_n=2, ky_n=1, H=1000.0, f=1e-4, g=G):
+    """Continuous f-plane inertia-gravity plane wave sampled on the mesh.
+
+    eta = a cos(theta), u = a/(H |k|^2) (omega cos(theta) k + f sin(theta) k_perp),
+    theta = k.x - omega t, omega^2 = f^2 + g H |k|^2; u_e = n_e . u(x_e).
+    """
+    k = np.array([2 * math.pi * kx_n / mesh.lx, 2 * math.pi * ky_n / mesh.ly])
+    kperp = np.array([-k[1], k[0]])
+    k2 = float(k @ k)
+    om = math.sqrt(f * f + g * H * k2)
+    th_c = mesh.x_cell @ k - om * t
+    th_e = mesh.x_edge @ k - om * t
+    h = H + amp * np.cos(th_c)
+    A = amp / (H * k2)
+    uvec = A * (om * np.cos(th_e)[:, None] * k[None, :] + f * np.sin(th_e)[:, None] * kperp[None, :])
+    u = np.einsum("ij,ij->i", uvec, mesh.normal_edge)
+    return h, u, om
+
+
+def band_mask(nx, ny, rows, seed):
+    j0 = int(rng_for(seed).integers(0, ny))
+    rows_idx = (j0 + np.arange(rows)) % ny
+    mask = np.zeros(nx * ny, dtype=bool)
+    for j in rows_idx:
+        mask[j * nx:(j + 1) * nx] = True
+    return mask
+
+
+def config1(M=2, dt=60.0, steps=200, seed=1):
+    mesh = meshgen.hex_periodic(32, 32, 1.0e4, f0=1e-4, depth=1000.0)
+    h0, u0, om = igw_state(mesh, 0.0)
+    mask = band_mask(32, 32, 8, seed)
+    return Workload("hex32_igw_linear", mesh, h0, u0, mask, dt, M, True, None, steps,
+                    dict(omega=om, seed=seed))
+
+
+# ----------------------------------------------------------------------------
+# configuration 2: nonlinear, variable resolution, CFL-selected fine region
+# ----------------------------------------------------------------------------
+
+def _periodic_r2(x, y, cx, cy, lx, ly):
+    dx = np.abs(x - cx); dx = np.minimum(dx, lx - dx)
+    dy = np.abs(y - cy); dy = np.minimum(dy, ly - dy)
+    return dx * dx + dy * dy
+
+
+def seamount_depth(mesh, seed=3, n_bumps=6):
+    r = rng_for(seed)
+    x, y = mesh.x_cell[:, 0], mesh.x_cell[:, 1]
+    H = np.full(mesh.n_cells, 4000.0)
+    for _ in range(n_bumps):
+        cx, cy = r.uniform(0, mesh.lx), r.uniform(0, mesh.ly)
+        amp = r.uniform(1000.0, 3950.0)
+        w = r.uniform(30e3, 120e3)
+        H -= amp * np.exp(-_periodic_r2(x, y, cx, cy, mesh.lx, mesh.ly) / (2 * w * w))
+    return np.maximum(H, 50.0)
+
+
+def ssh_bumps(mesh, seed=4, n=3, amp=0.5, width=50e3):
+    r = rng_for(seed)
+    x, y = mesh.x_cell[:, 0], mesh.x_cell[:, 1]
+    eta = np.zeros(mesh.n_cells)
+    for _ in range(n):
+        cx, cy = r.uniform(0, mesh.lx), r.uniform(0, mesh.ly)
+        eta += amp * np.exp(-_periodic_r2(x, y, cx, cy, mesh.lx, mesh.ly) / (2 * width * width))
+    return eta
+
+
+def cfl_fine_mask(mesh, M, nu=0.6 * NU_MAX_FBRK32, g=G):
+    """Fine cells: those whose gravity-wave Courant number at the coarse step exceeds nu.
+
+    dt_fine = nu * min_i(dx_i / c_i), dt_coarse = M dt_fine; c_i = sqrt(g H_i),
+    dx_i = the shortest dual edge of the cell.
+    """
+    dx = np.full(mesh.n_cells, np.inf)
+    np.minimum.at(dx, mesh.cells_on_edge[:, 0], mesh.dc_edge)
+    np.minimum.at(dx, mesh.cells_on_edge[:, 1], mesh.dc_edge)
+    c = np.sqrt(g * mesh.bottom_depth)
+    dt_f = nu * float(np.min(dx / c))
+    dt_c = M * dt_f
+    fine = c * dt_c / dx > nu
+    return fine, dt_c, dt_f
+
+
+_MESH_CACHE = {}
+
+
+def cvt_mesh(n=50000, seed=2, iters=50):
+    key = (n, seed, iters)
+    if key not in _MESH_CACHE:
+        _MESH_CACHE[key] = meshgen.cvt_planar_periodic(n, meshgen.gaussian_patch_dx, iters=iters, seed=seed)
+    return _MESH_CACHE[key]
+
+
+def config2(n=50000, M=4, steps=200, seed_mesh=2, seed_depth=3, seed_ic=4, iters=50, cd=2.5e-3):
+    base = cvt_mesh(n, seed_mesh, iters)
+    H = seamount_depth(base, seed_depth)
+    mesh = base.copy_with(bottom_depth=H)
+    h0 = H + ssh_bumps(mesh, seed_ic)
+    u0 = np.zeros(mesh.n_edges)
+    fine, dt_c, dt_f = cfl_fine_mask(mesh, M)
+    return Workload("cvt%dk_nonlinear_drag" % (n // 1000), mesh, h0, u0, fine, dt_c, M, False,
+                    np.full(mesh.n_cells, cd), steps,
+                    dict(dt_fine=dt_f, n_fine=int(fine.sum()), seeds=(seed_mesh, seed_depth, seed_ic)))
+
+
+def small_cvt(n=2000, M=4, seed=12, iters=20):
+    """A small irregular mesh with the configuration-2 recipe (fast CPU tests)."""
+    return config2(n=n, M=M, seed_mesh=seed, iters=iters)
+
+
+def ensemble_members(mesh, n_members, seed_ssh0=1000, seed_cd=8, sigma=0.05, corr=50e3,
+                     cd_range=(1e-3, 4e-3), n_modes=64):
+    """Per-member SSH perturbations (smooth random fields, std sigma) and drag coefficients."""
+    r_cd = rng_for(seed_cd)
+    cds = r_cd.uniform(cd_range[0], cd_range[1], size=n_members)
+    x, y = mesh.x_cell[:, 0], mesh.x_cell[:, 1]
+    fields = []
+    for m in range(n_members):
+        r = rng_for(seed_ssh0 + m)
+        # random Fourier features with a Gaussian spectrum of correlation length corr,
+        # restricted to wavenumbers periodic on the domain
+        kx = np.round(r.normal(0, mesh.lx / (2 * math.pi * corr), n_modes)) * 2 * math.pi / mesh.lx
+        ky = np.round(r.normal(0, mesh.ly / (2 * math.pi * corr), n_modes)) * 2 * math.pi / mesh.ly
+        ph = r.uniform(0, 2 * math.pi, n_modes)
+        fld = np.sqrt(2.0 / n_modes) * np.cos(np.outer(x, kx) + np.outer(y, ky) + ph).sum(axis=1)
+        fields.append(sigma * fld)
+    return fields, cds

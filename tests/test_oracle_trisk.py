@@ -1,0 +1,181 @@
+"""Pins of the oracle's TRiSK tendencies against identities and closed forms (CPU).
+
+None of these re-derive the oracle's formulas: they check consequences fixed
+by the mathematics -- telescoping of fluxes (Theorem 1's mechanism), the
+divergence theorem, exact values on the regular hexagonal mesh, curl(grad)=0,
+conservation of the discrete energy by the semi-discrete system, and the
+constant-PV compatibility of the vorticity flux (eq. trisk_vorticity).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import trisk
+from paper_2405_10505_amd.inputs import meshgen, workloads
+
+
+@pytest.fixture(scope="module")
+def hexm():
+    return meshgen.hex_periodic(32, 32, 1.0e4)
+
+
+@pytest.fixture(scope="module")
+def cvt():
+    w = workloads.small_cvt()
+    return w.mesh
+
+
+def _rand_state(om, seed, amp_u=0.7, amp_h=5.0):
+    r = np.random.default_rng(seed)
+    u = amp_u * r.normal(size=om.E)
+    h = om.H + amp_h * r.normal(size=om.N)
+    return u, h
+
+
+def _unwrap_rel(m, x, origin):
+    d = x - origin
+    d[..., 0] -= m.lx * np.round(d[..., 0] / m.lx)
+    d[..., 1] -= m.ly * np.round(d[..., 1] / m.ly)
+    return d
+
+
+@pytest.mark.parametrize("meshname", ["hexm", "cvt"])
+@pytest.mark.parametrize("linear", [True, False])
+def test_thickness_tendency_telescopes(meshname, linear, request):
+    m = request.getfixturevalue(meshname)
+    om = trisk.OMesh(m)
+    u, h = _rand_state(om, 1)
+    p = trisk.psi(om, u, h, trisk.Physics(linear=linear))
+    assert abs(np.sum(om.A * p)) <= 1e-14 * np.sum(np.abs(om.A * p))
+
+
+def test_divergence_theorem_on_cvt(cvt):
+    """For a linear flow U(x) sampled at Voronoi-edge midpoints, sum n l u = (a+b) A exactly."""
+    m = cvt
+    om = trisk.OMesh(m)
+    a, b, c, d = 2.0e-5, -0.7e-5, 1.3e-5, 0.4e-5
+    x0 = m.x_cell[m.cells_on_edge[:, 0]]
+    v0 = x0 + _unwrap_rel(m, m.x_vertex[m.vertices_on_edge[:, 0]], x0)
+    v1 = x0 + _unwrap_rel(m, m.x_vertex[m.vertices_on_edge[:, 1]], x0)
+    mid = 0.5 * (v0 + v1)
+    U = np.stack([a * mid[:, 0] + c * mid[:, 1], d * mid[:, 0] + b * mid[:, 1]], 1)
+    u = np.einsum("ij,ij->i", U, m.normal_edge)
+    h = np.full(om.N, 1000.0)
+    p = trisk.psi(om, u, h, trisk.Physics(linear=False))
+    L = m.lx
+    inner = np.all((m.x_cell > 0.25 * L) & (m.x_cell < 0.75 * L), axis=1)
+    assert inner.sum() > 100
+    np.testing.assert_allclose(p[inner], -1000.0 * (a + b), rtol=1e-9)
+
+
+def test_hex_flux_of_linear_thickness(hexm):
+    """Uniform U and h = h0 + alpha.x: Psi = -U.alpha (edge-mean thickness is exact on the hexagon)."""
+    m = hexm
+    om = trisk.OMesh(m)
+    U = np.array([0.8, -0.3])
+    alpha = np.array([1.0e-4, 2.5e-4])
+    L = m.lx
+    # unwrap around the domain centre; keep cells whose neighbours do not cross the seam
+    ctr = np.array([0.5 * m.lx, 0.5 * m.ly])
+    xc = ctr + _unwrap_rel(m, m.x_cell, ctr)
+    h = 1000.0 + xc @ alpha
+    u = m.normal_edge @ U
+    p = trisk.psi(om, u, h, trisk.Physics(linear=False))
+    inner = np.all(np.abs(xc - ctr) < 0.35 * np.array([m.lx, m.ly]), axis=1)
+    np.testing.assert_allclose(p[inner], -(U @ alpha), rtol=1e-9)
+
+
+def test_hex_uniform_flow_kinetic_energy_and_coriolis(hexm):
+    """Uniform flow on the hexagon: K = |U|^2/2, zeta = 0, Phi_e = n_e.(-f k x U) = f t_e.U."""
+    m = hexm
+    om = trisk.OMesh(m)
+    U = np.array([1.3, -0.6])
+    u = m.normal_edge @ U
+    np.testing.assert_allclose(trisk.kinetic_energy(om, u), 0.5 * U @ U, rtol=1e-12)
+    assert np.max(np.abs(trisk.relative_vorticity(om, u))) < 1e-18
+    f = 1e-4
+    expect = m.tangent_edge @ U * f
+    h = np.full(om.N, 1000.0)
+    for linear in (True, False):
+        got = trisk.phi(om, u, h, trisk.Physics(linear=linear))
+        np.testing.assert_allclose(got, expect, atol=1e-12 * f * np.abs(U).max())
+
+
+@pytest.mark.parametrize("meshname", ["hexm", "cvt"])
+def test_curl_of_gradient_vanishes(meshname, request):
+    m = request.getfixturevalue(meshname)
+    om = trisk.OMesh(m)
+    B = np.random.default_rng(3).normal(size=om.N)
+    g = trisk.gradient(om, B)
+    z = trisk.relative_vorticity(om, g)
+    scale = np.abs(g).max() * om.dc.max() / om.Av.min()
+    assert np.abs(z).max() < 1e-14 * scale
+
+
+def _energy(om, u, h, g):
+    """TRiSK total energy: sum_e l d h_e u^2 / 2 + sum_i A g h (h/2 - H)."""
+    he = 0.5 * (h[om.coe[:, 0]] + h[om.coe[:, 1]])
+    return np.sum(0.5 * om.dv * om.dc * he * u * u) + np.sum(om.A * g * h * (0.5 * h - om.H))
+
+
+@pytest.mark.parametrize("meshname", ["hexm", "cvt"])
+def test_semi_discrete_energy_conserved(meshname, request):
+    """dE/dt = grad E . (Phi, Psi) = 0 (complex-step directional derivative)."""
+    m = request.getfixturevalue(meshname)
+    om = trisk.OMesh(m)
+    u, h = _rand_state(om, 5)
+    ph = trisk.Physics(linear=False)
+    P = trisk.psi(om, u, h, ph)
+    F = trisk.phi(om, u, h, ph)
+    eps = 1e-30
+    dE = _energy(om, u + 1j * eps * F, h + 1j * eps * P, ph.g).imag / eps
+    # scale: the size of the individual terms of grad E . (Phi, Psi)
+    he = 0.5 * (h[om.coe[:, 0]] + h[om.coe[:, 1]])
+    scale = np.sum(np.abs(om.dv * om.dc * he * u * F)) + np.sum(np.abs(om.A * ph.g * (h - om.H) * P))
+    assert abs(dE) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("meshname", ["hexm", "cvt"])
+def test_linear_operator_is_linearisation_at_rest(meshname, request):
+    m = request.getfixturevalue(meshname)
+    om = trisk.OMesh(m)
+    r = np.random.default_rng(7)
+    du = r.normal(size=om.E)
+    deta = r.normal(size=om.N)
+    eps = 1e-30
+    nl = trisk.Physics(linear=False)
+    lin = trisk.Physics(linear=True)
+    jp = trisk.psi(om, 1j * eps * du, om.H + 1j * eps * deta, nl).imag / eps
+    jf = trisk.phi(om, 1j * eps * du, om.H + 1j * eps * deta, nl).imag / eps
+    np.testing.assert_allclose(trisk.psi(om, du, om.H + deta, lin), jp, rtol=1e-12, atol=1e-12 * np.abs(jp).max())
+    np.testing.assert_allclose(trisk.phi(om, du, om.H + deta, lin), jf, rtol=1e-12, atol=1e-12 * np.abs(jf).max())
+
+
+@pytest.mark.parametrize("meshname", ["hexm", "cvt"])
+def test_constant_pv_compatibility(meshname, request):
+    """If q_v = q0 everywhere, d(zeta_v)/dt = q0 d(h_v)/dt (PV stays uniform; eq. trisk_vorticity)."""
+    m = request.getfixturevalue(meshname)
+    om = trisk.OMesh(m)
+    u, h = _rand_state(om, 9)
+    q0 = 3.1e-7
+    zeta = trisk.relative_vorticity(om, u)
+    hv = trisk.vertex_thickness(om, h)
+    m2 = m.copy_with(f_vertex=q0 * hv - zeta)
+    om2 = trisk.OMesh(m2)
+    ph = trisk.Physics(linear=False)
+    dzeta = trisk.relative_vorticity(om2, trisk.phi(om2, u, h, ph))
+    dhv = trisk.vertex_thickness(om2, trisk.psi(om2, u, h, ph))
+    np.testing.assert_allclose(dzeta, q0 * dhv, atol=1e-12 * np.abs(q0 * dhv).max())
+
+
+def test_drag_removes_energy(cvt):
+    """Quadratic drag contributes sum_e l d F_e (-C_D |u| u / h_e) <= 0 to dE/dt (parity unpinned otherwise)."""
+    om = trisk.OMesh(cvt)
+    u, h = _rand_state(om, 11)
+    cd = np.full(om.N, 2.5e-3)
+    P = trisk.psi(om, u, h, trisk.Physics(linear=False))
+    Fd = trisk.phi(om, u, h, trisk.Physics(linear=False, cd=cd))
+    eps = 1e-30
+    dE = _energy(om, u + 1j * eps * Fd, h + 1j * eps * P, 9.81).imag / eps
+    assert dE < 0
