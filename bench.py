@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Benchmark of the FB-LTS hot path on one MI355X.
+
+Default workload: the 50k-cell planar variable-resolution CVT (2 -> 8 km
+Gaussian patch, 50 Lloyd iterations, seamount bathymetry), nonlinear TRiSK
+with quadratic drag, fine cells chosen from the local CFL number, M = 4, FP64.
+One step = one FB-LTS coarse step (coarse advancement, M predicted fine
+substeps, interface correction), replayed from a hipGraph with the state
+resident in HBM.
+
+value = cell-substeps/s = (N_coarse + M N_fine) * steps / wall time.
+Also reported: the momentum (edge) pass against the HBM roofline, the
+time-to-solution of global FB-RK(3,2) and RK4 at their own largest stable
+steps (the paper's speedup definition), and the oracle timed on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cvt50k|hex32|ensemble]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-substeps/s & %HBM roofline: FB-LTS vs global FB-RK/RK4; ensemble member-steps/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cvt50k", choices=["cvt50k", "hex32", "ensemble"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-compare", action="store_true", help="skip the global-scheme comparison")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many graph-replayed steps (for rocprofv3), no JSON")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fblts_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2405_10505_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per momentum-pass launch from the committed rocprofv3 counter summary, if current."""
+    p = os.path.join(ROOT, "profiles", "edge_pass_%s_counters.json" % workload)
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def make_solver(F, w, scheme, dt, M, labels=None, graph=True):
+    import numpy as np
+    s = F.Solver(F.Mesh(w.mesh) if not hasattr(w, "_fm") else w._fm, dt, M=M, scheme=scheme, linear=w.linear)
+    if labels is None:
+        s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+    else:
+        s.set_regions(labels, binary=False)
+    if w.cd is not None and not w.linear:
+        s.set_drag(w.cd)
+    s.set_state(w.h0, w.u0)
+    s.set_graph(graph)
+    return s
+
+
+def stable(F, w, scheme, dt, steps, umax=50.0):
+    """Run `steps` steps of a global scheme; stable if finite, h > 0 and |u| < umax."""
+    import numpy as np
+    s = make_solver(F, w, scheme, dt, 1, labels=np.full(w.mesh.n_cells, 3, np.int8))
+    s.step(steps)
+    d = s.diagnostics(allow_nonfinite=True)
+    if d["n_nonfinite"] > 0 or not (d["min_h"] > 0):
+        return False
+    h, u = s.get_state()
+    return bool(np.max(np.abs(u)) < umax)
+
+
+def largest_stable_dt(F, w, scheme, dt0, steps=200, iters=10):
+    """The paper's procedure: grow dt until the run becomes unstable, then bisect."""
+    lo, hi = None, None
+    dt = dt0
+    for _ in range(20):
+        if stable(F, w, scheme, dt, steps):
+            lo = dt
+            dt *= 1.5
+        else:
+            hi = dt
+            break
+        if lo is not None and hi is not None:
+            break
+    if lo is None:   # shrink until stable
+        hi = dt0
+        dt = dt0
+        for _ in range(20):
+            dt /= 1.5
+            if stable(F, w, scheme, dt, steps):
+                lo = dt
+                break
+    if hi is None:
+        return lo
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if stable(F, w, scheme, mid, steps):
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+def time_steps(torch, s, steps, warmup):
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(w, steps):
+    """The oracle (plain numpy FP64, definition mode) on a bounded sample of the workload."""
+    import numpy as np
+    from oracle import regions, schemes, trisk
+    om = trisk.OMesh(w.mesh)
+    lab, _ = regions.layer(om, w.fine_mask, 2)
+    ph = trisk.Physics(linear=w.linear, cd=w.cd if not w.linear else None)
+    u, h = w.u0.copy(), w.h0.copy()
+    t0 = time.perf_counter()
+    n = 0
+    while n < steps:
+        u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
+        n += 1
+        if time.perf_counter() - t0 > 20.0:
+            break
+    el = time.perf_counter() - t0
+    nf = int(w.fine_mask.sum())
+    per_step = (w.mesh.n_cells - nf) + w.M * nf
+    return dict(value=per_step * n / el, unit="cell-substeps/s", cores=1, kind="oracle",
+                sample="%d FB-LTS coarse steps of the %s workload (numpy, one thread), %.1f s" % (n, w.name, el))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2405_10505_amd as F
+    from paper_2405_10505_amd.inputs import workloads
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    if args.workload == "ensemble":
+        return bench_ensemble(args)
+    t = time.perf_counter()
+    w = workloads.config1() if args.workload == "hex32" else workloads.config2()
+    log("workload %s: N=%d E=%d fine=%d dt=%.3f M=%d (built in %.1fs)" % (
+        w.name, w.mesh.n_cells, w.mesh.n_edges, int(w.fine_mask.sum()), w.dt, w.M, time.perf_counter() - t))
+    w._fm = F.Mesh(w.mesh)
+    s = make_solver(F, w, F.SCHEME_FBLTS, w.dt, w.M)
+    info = s.info()
+    if args.profile_steps:
+        s.step(args.profile_steps)
+        torch.cuda.synchronize()
+        log("profile run done: %d steps" % args.profile_steps)
+        return
+    el = time_steps(torch, s, args.steps, args.warmup)
+    ms = el / args.steps * 1e3
+    value = info["cell_substeps_per_step"] * args.steps / el
+    d = s.diagnostics()
+    log("FB-LTS: %.4f ms/step, %.3e cell-substeps/s, launches/step %d" % (ms, value, info["launches_per_step"]))
+
+    # roofline of the dominant kernel (momentum pass), event-timed on the solver's stream
+    s2 = make_solver(F, w, F.SCHEME_FBLTS, w.dt, w.M, graph=False)
+    s2.step(5)
+    s2.set_timing(True)
+    nt = 20
+    s2.step(nt)
+    edge_ms, edge_launches = s2.kernel_time(0)
+    cell_ms, _ = s2.kernel_time(1)
+    vert_ms, _ = s2.kernel_time(2)
+    prep_ms, _ = s2.kernel_time(3)
+    launches_per_step = edge_launches / nt
+    bytes_per_launch = info["model_bytes_edge_pass"] / launches_per_step
+    achieved = bytes_per_launch / (edge_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(args.workload)
+    roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                traffic=traffic, kernel="fblts::k_edge (momentum pass)", avg_launch_ms=edge_ms,
+                algorithmic_bytes_per_launch=bytes_per_launch,
+                avg_ms=dict(edge=edge_ms, cell=cell_ms, vertex=vert_ms, prep=prep_ms))
+    log("edge pass: %.4f ms avg, %.1f GB/s algorithmic (%.1f%% of HBM peak)" % (edge_ms, achieved, 100 * achieved / HBM_PEAK_GBS))
+    whole = info["model_bytes_per_step"] / (ms * 1e-3) / 1e9
+
+    comp = None
+    if not args.no_compare:
+        dt_f = w.dt / w.M
+        t0 = time.perf_counter()
+        dt_fb = largest_stable_dt(F, w, F.SCHEME_FBRK32, dt_f)
+        dt_rk4 = largest_stable_dt(F, w, F.SCHEME_RK4, dt_f)
+        log("stable dt: FB-RK(3,2) %.3f s, RK4 %.3f s, FB-LTS fine %.3f s / coarse %.3f s (search %.1fs)" % (
+            dt_fb, dt_rk4, dt_f, w.dt, time.perf_counter() - t0))
+        ks = max(20, args.steps // 2)
+        res = {}
+        for name, scheme, dt in (("fbrk32_own_limit", F.SCHEME_FBRK32, dt_fb),
+                                 ("fbrk32_fine_dt", F.SCHEME_FBRK32, dt_f),
+                                 ("rk4_own_limit", F.SCHEME_RK4, dt_rk4)):
+            g = make_solver(F, w, scheme, dt, 1, labels=np.full(w.mesh.n_cells, 3, np.int8))
+            e = time_steps(torch, g, ks, 5)
+            res[name] = dict(dt=dt, ms_per_step=e / ks * 1e3, sim_seconds_per_wall_second=dt * ks / e)
+        fblts_rate = w.dt * args.steps / el
+        comp = dict(fblts=dict(dt_coarse=w.dt, dt_fine=dt_f, M=w.M, ms_per_step=ms,
+                               sim_seconds_per_wall_second=fblts_rate),
+                    **res,
+                    speedup_vs_rk4=fblts_rate / res["rk4_own_limit"]["sim_seconds_per_wall_second"],
+                    speedup_vs_fbrk32=fblts_rate / res["fbrk32_own_limit"]["sim_seconds_per_wall_second"],
+                    definition="time-to-solution ratio for equal simulated time (paper eq. speedup)")
+        log("speedup vs RK4 %.2fx, vs global FB-RK(3,2) %.2fx" % (comp["speedup_vs_rk4"], comp["speedup_vs_fbrk32"]))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, 50)
+        log("oracle: %.3e cell-substeps/s (%s)" % (cpu["value"], cpu["sample"]))
+
+    out = dict(metric=METRIC, value=value, unit="cell-substeps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload=w.name, n_cells=w.mesh.n_cells, n_edges=w.mesh.n_edges,
+                           n_vertices=w.mesh.n_vertices, n_fine=info["n_fine"], n_if1=info["n_if1"],
+                           n_if2=info["n_if2"], n_int=info["n_int"], M=w.M, dt_coarse=w.dt,
+                           physics="linear" if w.linear else "nonlinear+drag", scheme="FB-LTS",
+                           cell_substeps_per_step=info["cell_substeps_per_step"],
+                           launches_per_step=info["launches_per_step"], hipgraph=True),
+               roofline=roof, cpu_baseline=cpu, comparison=comp,
+               whole_step_model_GBs=whole, model_bytes_per_step=info["model_bytes_per_step"],
+               diagnostics=dict(mass=d["mass"], min_h=d["min_h"]))
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args):
+    import numpy as np
+    import torch
+    import paper_2405_10505_amd as F
+    from paper_2405_10505_amd.inputs import workloads
+    # 64 members on the 50k-cell mesh and 16 each on 20k / 50k / 120k-cell meshes
+    specs = [(50000, 2, 64), (20000, 20, 16), (50000, 21, 16), (120000, 22, 16)]
+    ws = []
+    for n, seed, nm in specs:
+        t = time.perf_counter()
+        w = workloads.config2(n=n, seed_mesh=seed)
+        ws.append((w, nm))
+        log("mesh %d (seed %d) built in %.1fs, fine %d" % (n, seed, time.perf_counter() - t, int(w.fine_mask.sum())))
+    # one coarse dt for all meshes: the most restrictive
+    dt = min(w.dt for w, _ in ws)
+    fms = [F.Mesh(w.mesh) for w, _ in ws]
+    labels = [np.where(w.fine_mask, 0, 1) for w, _ in ws]
+    ens = F.Ensemble(fms, labels, [nm for _, nm in ws], dt, M=4, linear=False)
+    for k, (w, nm) in enumerate(ws):
+        fields, cds = workloads.ensemble_members(w.mesh, nm, seed_ssh0=1000 + 100 * k)
+        for m in range(nm):
+            ens.set_member(k, m, w.h0 + fields[m], w.u0, np.full(w.mesh.n_cells, cds[m]))
+    ens.set_graph(True)
+    info = ens.info()
+    el = time_steps(torch, ens, args.steps, args.warmup)
+    members = sum(nm for _, nm in ws)
+    out = dict(metric=METRIC, value=members * args.steps / el, unit="member-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=el / args.steps * 1e3, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="ensemble_4meshes_112members", members=members,
+                           member_cells=info["member_cells"], dt=dt, M=4),
+               cell_substeps_per_s=info["cell_substeps_per_step"] * args.steps / el,
+               model_GBs=info["model_bytes_per_step"] * args.steps / el / 1e9)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

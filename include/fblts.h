@@ -1,0 +1,246 @@
+/*
+ * fblts.h - C ABI of the FB-LTS shallow-water library for AMD MI355X (gfx950).
+ *
+ * The library advances the TRiSK shallow-water equations on an unstructured
+ * Voronoi C-grid (thickness h on cells, normal velocity u on edges) with the
+ * forward-backward local time-stepping scheme FB-LTS of Lilly, Capodaglio,
+ * Engwirda, Higdon and Petersen (arXiv 2405.10505), and with the global
+ * schemes FB-RK(3,2) and RK4 it is compared against.  All arithmetic is FP64.
+ *
+ * Paper passages (section / equation labels of the paper):
+ *   - semi-discrete system u_e' = Phi_e(u,h), h_i' = Psi_i(u,h): Section 2.2,
+ *     eq. semi_discrete_sys;
+ *   - Psi: eq. trisk_thickness; Phi: eq. nonlinear_swe in the vorticity-flux
+ *     form of eq. trisk_vorticity, with quadratic bottom drag and wind stress
+ *     of eq. hurricane_model;
+ *   - FB-RK(3,2): Section 2.1, eq. fbrk32, FB weights (0.531, 0.531, 0.313);
+ *   - FB-LTS: Section 2.2 (regions F, IF-1, IF-2, interior coarse; coarse
+ *     advancement, interface prediction eq. preds, fine advancement eq.
+ *     fine_fbrk32, interface correction eq. if_correction);
+ *   - conserved quantities: Section 2.5, Theorems 1 and 2.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an int status (FBLTS_OK = 0, negative on error);
+ *     fblts_last_error() gives a message for the last failure on the calling
+ *     thread.  No C++ exception crosses this boundary.
+ *   - Host pointers passed in are borrowed for the duration of the call and
+ *     deep-copied; the caller keeps ownership.  Device pointers (on_device=1)
+ *     must be device memory of the solver's device, at least the stated size,
+ *     and are only accessed in stream order on the solver's stream.
+ *   - All state going in and out is in the caller's numbering.  The library
+ *     reorders cells, edges and vertices internally so that every LTS region
+ *     is a contiguous range; that permutation never leaks out.
+ *   - Work is enqueued asynchronously on the HIP stream given at create time.
+ *     fblts_get_state (host pointers), fblts_diagnostics and the ensemble /
+ *     adjoint host-returning calls synchronise that stream.
+ *   - A handle must not be used from several threads at once.
+ */
+#ifndef FBLTS_H
+#define FBLTS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FBLTS_OK = 0,
+  FBLTS_EINVAL = -1,     /* bad argument, malformed mesh, size mismatch          */
+  FBLTS_ENOMEM = -2,     /* host or device allocation failed                      */
+  FBLTS_EDEVICE = -3,    /* a HIP runtime call failed                             */
+  FBLTS_EREGION = -4,    /* region labels violate the stencil condition (Sec 2.2) */
+  FBLTS_ESTATE = -5,     /* call out of order (e.g. step before set_state)        */
+  FBLTS_ENONFINITE = -6  /* the state holds NaN/Inf or h <= 0                     */
+};
+
+enum { FBLTS_SCHEME_FBLTS = 0, FBLTS_SCHEME_FBRK32 = 1, FBLTS_SCHEME_RK4 = 2 };
+enum { FBLTS_PHYS_LINEAR = 0, FBLTS_PHYS_NONLINEAR = 1 };
+enum { FBLTS_LABEL_F = 0, FBLTS_LABEL_IF1 = 1, FBLTS_LABEL_IF2 = 2, FBLTS_LABEL_INT = 3 };
+
+/* Message of the last failing call on this thread ("" if none).  Valid until
+ * the next library call on the same thread. */
+const char* fblts_last_error(void);
+int fblts_version(void);
+
+/* ---------------------------------------------------------------- mesh --- */
+
+/* MPAS-style Voronoi C-grid, caller numbering, 0-based, host pointers.
+ *   cells_on_edge[2E]      (c0,c1) per edge; the normal n_e points c0 -> c1,
+ *                          so n_{e,c0} = +1, n_{e,c1} = -1 (Sec 2.5).
+ *   vertices_on_edge[2E]   (v0,v1); the tangent t_e = k x n_e points v0 -> v1.
+ *   edges_on_cell (CSR)    counter-clockwise; vertices_on_cell (CSR, same
+ *                          offsets): vertex j lies between edge j and j+1.
+ *   edges_on_edge (CSR) + weights_on_edge: dimensionless TRiSK weights
+ *                          w_{e,e'}, u_perp_e = (1/d_e) sum w l_e' u_e'.
+ *   edges_on_vertex[3V]    edge j joins cells_on_vertex j and j+1.
+ *   cells_on_vertex[3V], kite_areas_on_vertex[3V] (aligned).
+ *   dc_edge (d_e, cell-centre distance), dv_edge (l_e, edge length),
+ *   area_cell (A_i), area_triangle (A_v), f_vertex, f_edge (Coriolis),
+ *   bottom_depth (resting depth H_i > 0; bottom z_b = -H).
+ */
+typedef struct {
+  int32_t n_cells, n_edges, n_vertices;
+  const int32_t* cells_on_edge;
+  const int32_t* vertices_on_edge;
+  const int32_t* edges_on_cell_off;
+  const int32_t* edges_on_cell;
+  const int32_t* vertices_on_cell_off;
+  const int32_t* vertices_on_cell;
+  const int32_t* edges_on_edge_off;
+  const int32_t* edges_on_edge;
+  const double* weights_on_edge;
+  const int32_t* edges_on_vertex;
+  const int32_t* cells_on_vertex;
+  const double* kite_areas_on_vertex;
+  const double* dc_edge;
+  const double* dv_edge;
+  const double* area_cell;
+  const double* area_triangle;
+  const double* f_vertex;
+  const double* f_edge;
+  const double* bottom_depth;
+} fblts_mesh_desc;
+
+typedef struct fblts_mesh fblts_mesh;
+
+/* Validate the descriptor (host only, no device needed) and deep-copy it.
+ * Errors: FBLTS_EINVAL with a message naming the first violated property
+ * (index ranges, CSR monotonicity, edge/cell incidence, orientation
+ * consistency between cells, edges and vertices, positive lengths/areas,
+ * kite sums).  *out is set only on success; free with fblts_mesh_destroy. */
+int fblts_mesh_create(const fblts_mesh_desc* desc, fblts_mesh** out);
+/* Destroy after every solver created from the mesh is destroyed. */
+void fblts_mesh_destroy(fblts_mesh* mesh);
+
+/* Region layering (Sec 2.2, host only).  labels[n_cells] in caller numbering:
+ * binary=1: 0 = fine, 1 = coarse; the coarse cells within r hops of the fine
+ * set become interface one, the next r hops interface two, the rest interior.
+ * binary=0: labels are already FBLTS_LABEL_*.  Writes the 4-level labels to
+ * out_labels[n_cells] and the signed layer distance to out_layer[n_cells]
+ * (fine: -hops to the coarse set, coarse: +hops to the fine set; may be NULL).
+ * Errors: FBLTS_EINVAL (bad values), FBLTS_EREGION (adjacent cells more than
+ * one region apart, the stencil condition of Sec 2.2). */
+int fblts_layer_regions(const fblts_mesh* mesh, const int8_t* labels, int32_t binary, int32_t r,
+                        int8_t* out_labels, int32_t* out_layer);
+
+/* ------------------------------------------------------------- solver --- */
+
+typedef struct {
+  double dt;              /* coarse step (s); FB-RK(3,2)/RK4: the global step */
+  double g;               /* gravity (m/s^2) */
+  double beta1, beta2, beta3;   /* FB weights (Sec 2.1: 0.531, 0.531, 0.313) */
+  int32_t M;              /* fine substeps per coarse step (FB-LTS) */
+  int32_t scheme;         /* FBLTS_SCHEME_* */
+  int32_t physics;        /* FBLTS_PHYS_* */
+  int32_t r_layers;       /* interface thickness in cell layers for binary labels (2) */
+  double rho_air, rho_water;    /* wind-stress law densities (1.15, 1000) */
+} fblts_params;
+
+typedef struct fblts_solver fblts_solver;
+
+/* Create a solver on the current HIP device, ordered on hip_stream (a
+ * hipStream_t; NULL = default stream).  Errors: FBLTS_EINVAL, FBLTS_EDEVICE. */
+int fblts_solver_create(const fblts_mesh* mesh, const fblts_params* params, void* hip_stream,
+                        fblts_solver** out);
+void fblts_solver_destroy(fblts_solver* s);
+
+/* Install LTS regions (see fblts_layer_regions), reorder cells/edges/vertices
+ * region-contiguously, derive every pass's index range from the stencil and
+ * upload the reordered mesh.  Also required (all-coarse) for the global
+ * schemes.  Invalidates any captured graph and the state.
+ * Errors: FBLTS_EINVAL, FBLTS_EREGION, FBLTS_EDEVICE, FBLTS_ENOMEM. */
+int fblts_set_regions(fblts_solver* s, const int8_t* labels, int32_t binary);
+
+/* State in caller numbering: h[n_cells] thickness (m), u[n_edges] normal
+ * velocity (m/s).  on_device selects device or host pointers. */
+int fblts_set_state(fblts_solver* s, const double* h, const double* u, int32_t on_device);
+int fblts_get_state(fblts_solver* s, double* h, double* u, int32_t on_device);
+/* Per-cell quadratic bottom drag coefficient C_D[n_cells] (nonlinear physics). */
+int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device);
+/* Wind at edge points, normal and tangential components (m/s), held fixed
+ * until the next call; enables the wind-stress term of eq. hurricane_model.
+ * Pass NULL to disable. */
+int fblts_set_wind(fblts_solver* s, const double* wind_normal, const double* wind_tangential,
+                   int32_t on_device);
+
+/* Advance n coarse steps (async).  Errors: FBLTS_ESTATE before set_state. */
+int fblts_step(fblts_solver* s, int32_t n_coarse_steps);
+/* Capture one coarse step in a hipGraph and replay it in fblts_step (1), or
+ * launch kernels directly (0).  The graph is rebuilt after set_regions. */
+int fblts_set_graph(fblts_solver* s, int32_t enable);
+
+typedef struct {
+  double mass;              /* sum_i A_i h_i */
+  double abs_vorticity;     /* sum_v A_v (zeta_v + f_v) */
+  double abs_vorticity_scale; /* sum_v A_v |zeta_v + f_v| */
+  double energy;            /* TRiSK energy (linear or nonlinear form) */
+  double min_h;
+  double time;
+  int64_t n_nonfinite;      /* NaN/Inf entries of h and u */
+  int64_t step;
+} fblts_diag;
+
+/* Deterministic device reductions of the current state; synchronises.
+ * Returns FBLTS_ENONFINITE (and fills *out) if any h,u is non-finite or h <= 0. */
+int fblts_diagnostics(fblts_solver* s, fblts_diag* out);
+
+typedef struct {
+  int32_t n_cells, n_edges, n_vertices;
+  int32_t n_fine, n_if1, n_if2, n_int;            /* cells per region */
+  int32_t n_fine_e, n_if1_e, n_if2_e, n_int_e;    /* edges per region */
+  int32_t max_edges, max_eoe;
+  int64_t cell_substeps_per_step;   /* N_coarse + M N_fine (global schemes: N) */
+  int64_t launches_per_step;
+  double model_bytes_per_step;      /* algorithmic byte model of all launched passes */
+  double model_bytes_edge_pass;     /* of the momentum (edge) passes only */
+  int64_t edge_pass_items_per_step; /* edges processed by momentum passes per step */
+} fblts_info;
+int fblts_get_info(fblts_solver* s, fblts_info* out);
+
+/* Test export: evaluate one tendency on caller-numbered (h,u) over all
+ * entities.  which = 0: Psi (out[n_cells]); 1: Phi (out[n_edges]).  Uses the
+ * solver's physics, drag and wind.  Synchronises when out is a host pointer. */
+int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const double* u,
+                         double* out, int32_t on_device);
+
+/* Timing export: event-timed average duration (ms) of the kernels of one
+ * class launched during the last fblts_step: 0 = momentum (edge) passes,
+ * 1 = thickness (cell) passes, 2 = vertex passes, 3 = edge-prep passes.
+ * Requires fblts_set_timing(s,1) before the step; synchronises. */
+int fblts_set_timing(fblts_solver* s, int32_t enable);
+int fblts_kernel_time(fblts_solver* s, int32_t kernel_class, double* avg_ms, int64_t* launches);
+
+/* ----------------------------------------------------------- ensemble --- */
+
+/* A batch of independent FB-LTS members over one or more meshes, advanced by
+ * the same kernels with the member index innermost (member-contiguous state),
+ * one launch per pass covering every mesh.  members_per_mesh[k] in 1..64.
+ * cell_labels[k] as in fblts_set_regions.  Errors as solver_create /
+ * set_regions. */
+typedef struct fblts_ensemble fblts_ensemble;
+int fblts_ensemble_create(const fblts_mesh* const* meshes, const int8_t* const* cell_labels,
+                          int32_t labels_are_binary, const int32_t* members_per_mesh,
+                          int32_t n_meshes, const fblts_params* params, void* hip_stream,
+                          fblts_ensemble** out);
+void fblts_ensemble_destroy(fblts_ensemble* e);
+/* State and per-cell drag of one member (caller numbering of that mesh). */
+int fblts_ensemble_set_member(fblts_ensemble* e, int32_t mesh, int32_t member, const double* h,
+                              const double* u, const double* cd, int32_t on_device);
+int fblts_ensemble_get_member(fblts_ensemble* e, int32_t mesh, int32_t member, double* h,
+                              double* u, int32_t on_device);
+int fblts_ensemble_step(fblts_ensemble* e, int32_t n_coarse_steps);
+int fblts_ensemble_set_graph(fblts_ensemble* e, int32_t enable);
+/* Launch shape: members handled per thread block row and block size; the
+ * autotuner searches these (0 = default). */
+int fblts_ensemble_set_launch(fblts_ensemble* e, int32_t block_size);
+/* out[total members] in mesh-major, member-minor order; synchronises. */
+int fblts_ensemble_diagnostics(fblts_ensemble* e, fblts_diag* out);
+int fblts_ensemble_info(fblts_ensemble* e, int64_t* member_cells, int64_t* cell_substeps_per_step,
+                        double* model_bytes_per_step);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FBLTS_H */

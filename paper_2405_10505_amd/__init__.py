@@ -1,0 +1,333 @@
+"""Python binding of libfblts (include/fblts.h): argument marshalling only.
+
+Every step of the FB-LTS hot path runs in the library's HIP kernels; this
+module converts arrays and handles.  It fails loudly when the library has not
+been built -- there is no fallback.  PyTorch, when used, only provides device
+memory and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfblts.so")
+
+FBLTS_OK, FBLTS_EINVAL, FBLTS_ENOMEM, FBLTS_EDEVICE, FBLTS_EREGION, FBLTS_ESTATE, FBLTS_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+SCHEME_FBLTS, SCHEME_FBRK32, SCHEME_RK4 = 0, 1, 2
+PHYS_LINEAR, PHYS_NONLINEAR = 0, 1
+BETA = (0.531, 0.531, 0.313)
+
+_P_i32 = C.POINTER(C.c_int32)
+_P_f64 = C.POINTER(C.c_double)
+
+
+class fblts_mesh_desc(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("n_edges", C.c_int32), ("n_vertices", C.c_int32),
+                ("cells_on_edge", _P_i32), ("vertices_on_edge", _P_i32),
+                ("edges_on_cell_off", _P_i32), ("edges_on_cell", _P_i32),
+                ("vertices_on_cell_off", _P_i32), ("vertices_on_cell", _P_i32),
+                ("edges_on_edge_off", _P_i32), ("edges_on_edge", _P_i32), ("weights_on_edge", _P_f64),
+                ("edges_on_vertex", _P_i32), ("cells_on_vertex", _P_i32), ("kite_areas_on_vertex", _P_f64),
+                ("dc_edge", _P_f64), ("dv_edge", _P_f64), ("area_cell", _P_f64), ("area_triangle", _P_f64),
+                ("f_vertex", _P_f64), ("f_edge", _P_f64), ("bottom_depth", _P_f64)]
+
+
+class fblts_params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("g", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("beta3", C.c_double), ("M", C.c_int32), ("scheme", C.c_int32), ("physics", C.c_int32),
+                ("r_layers", C.c_int32), ("rho_air", C.c_double), ("rho_water", C.c_double)]
+
+
+class fblts_diag(C.Structure):
+    _fields_ = [("mass", C.c_double), ("abs_vorticity", C.c_double), ("abs_vorticity_scale", C.c_double),
+                ("energy", C.c_double), ("min_h", C.c_double), ("time", C.c_double),
+                ("n_nonfinite", C.c_int64), ("step", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fblts_info(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_cells", "n_edges", "n_vertices", "n_fine", "n_if1", "n_if2", "n_int",
+                                         "n_fine_e", "n_if1_e", "n_if2_e", "n_int_e", "max_edges", "max_eoe")] + \
+               [("cell_substeps_per_step", C.c_int64), ("launches_per_step", C.c_int64),
+                ("model_bytes_per_step", C.c_double), ("model_bytes_edge_pass", C.c_double),
+                ("edge_pass_items_per_step", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every symbol include/fblts.h declares, with its ctypes signature
+_SIGS = {
+    "fblts_last_error": (C.c_char_p, []),
+    "fblts_version": (C.c_int, []),
+    "fblts_mesh_create": (C.c_int, [C.POINTER(fblts_mesh_desc), C.POINTER(C.c_void_p)]),
+    "fblts_mesh_destroy": (None, [C.c_void_p]),
+    "fblts_layer_regions": (C.c_int, [C.c_void_p, C.POINTER(C.c_int8), C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_int8), _P_i32]),
+    "fblts_solver_create": (C.c_int, [C.c_void_p, C.POINTER(fblts_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fblts_solver_destroy": (None, [C.c_void_p]),
+    "fblts_set_regions": (C.c_int, [C.c_void_p, C.POINTER(C.c_int8), C.c_int32]),
+    "fblts_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_set_drag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_set_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_step": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fblts_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fblts_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
+    "fblts_get_info": (C.c_int, [C.c_void_p, C.POINTER(fblts_info)]),
+    "fblts_debug_tendency": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fblts_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "fblts_ensemble_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.POINTER(C.c_int8)), C.c_int32, _P_i32,
+                                        C.c_int32, C.POINTER(fblts_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fblts_ensemble_destroy": (None, [C.c_void_p]),
+    "fblts_ensemble_set_member": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_int32]),
+    "fblts_ensemble_get_member": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_ensemble_step": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fblts_ensemble_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fblts_ensemble_set_launch": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fblts_ensemble_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
+    "fblts_ensemble_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_double)]),
+}
+
+
+class FBLTSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fblts error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libfblts.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfblts.so is not built (%s); run paper_2405_10505_amd.build_lib.build()" % LIB_PATH)
+        # Load PyTorch's HIP runtime first when PyTorch is present: libfblts
+        # then binds to that same runtime (both carry SONAME libamdhip64.so.7),
+        # so tensors, streams and the library share one device context.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != FBLTS_OK:
+        raise FBLTSError(rc, lib().fblts_last_error().decode())
+    return rc
+
+
+def _ptr(a, dtype):
+    """(pointer, on_device, keepalive) for a numpy array or a torch tensor."""
+    if a is None:
+        return None, 0, None
+    if hasattr(a, "data_ptr"):      # torch tensor
+        import torch
+        want = torch.float64 if dtype == np.float64 else torch.int32
+        if a.dtype != want or not a.is_contiguous():
+            raise TypeError("tensor must be contiguous %s" % want)
+        return C.c_void_p(a.data_ptr()), (1 if a.is_cuda else 0), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data_as(C.c_void_p), 0, arr
+
+
+class Mesh:
+    """fblts_mesh: validated host copy of an MPAS-style mesh (no device needed)."""
+
+    def __init__(self, mesh):
+        arrs = mesh.desc_arrays()
+        self._keep = arrs
+        d = fblts_mesh_desc()
+        d.n_cells, d.n_edges, d.n_vertices = mesh.n_cells, mesh.n_edges, mesh.n_vertices
+        for k, v in arrs.items():
+            setattr(d, k, v.ctypes.data_as(_P_i32 if v.dtype == np.int32 else _P_f64))
+        h = C.c_void_p()
+        _check(lib().fblts_mesh_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.n_cells, self.n_edges, self.n_vertices = mesh.n_cells, mesh.n_edges, mesh.n_vertices
+
+    def layer_regions(self, labels, binary=True, r=2):
+        lab = np.ascontiguousarray(labels, dtype=np.int8)
+        out = np.zeros(self.n_cells, np.int8)
+        layer = np.zeros(self.n_cells, np.int32)
+        _check(lib().fblts_layer_regions(self.handle, lab.ctypes.data_as(C.POINTER(C.c_int8)), int(binary), int(r),
+                                         out.ctypes.data_as(C.POINTER(C.c_int8)), layer.ctypes.data_as(_P_i32)))
+        return out, layer
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fblts_mesh_destroy(self.handle)
+            self.handle = None
+
+
+def make_params(dt, M=1, scheme=SCHEME_FBLTS, linear=False, g=9.81, beta=BETA, r_layers=2,
+                rho_air=1.15, rho_water=1000.0):
+    p = fblts_params()
+    p.dt, p.g = float(dt), float(g)
+    p.beta1, p.beta2, p.beta3 = beta
+    p.M, p.scheme, p.physics, p.r_layers = int(M), int(scheme), PHYS_LINEAR if linear else PHYS_NONLINEAR, int(r_layers)
+    p.rho_air, p.rho_water = rho_air, rho_water
+    return p
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Solver:
+    """fblts_solver: one mesh, one member, one scheme."""
+
+    def __init__(self, mesh: Mesh, dt, M=1, scheme=SCHEME_FBLTS, linear=False, stream=None, **kw):
+        self.mesh = mesh
+        self.params = make_params(dt, M, scheme, linear, **kw)
+        h = C.c_void_p()
+        _check(lib().fblts_solver_create(mesh.handle, C.byref(self.params), _stream_handle(stream), C.byref(h)))
+        self.handle = h
+
+    def set_regions(self, labels, binary=True):
+        lab = np.ascontiguousarray(labels, dtype=np.int8)
+        _check(lib().fblts_set_regions(self.handle, lab.ctypes.data_as(C.POINTER(C.c_int8)), int(binary)))
+
+    def set_state(self, h, u):
+        ph, dh, kh = _ptr(h, np.float64)
+        pu, du, ku = _ptr(u, np.float64)
+        if dh != du:
+            raise ValueError("h and u must both be host or both be device arrays")
+        _check(lib().fblts_set_state(self.handle, ph, pu, dh))
+
+    def get_state(self, h=None, u=None):
+        """Into given arrays/tensors, or new numpy arrays when omitted."""
+        if h is None and u is None:
+            h = np.empty(self.mesh.n_cells)
+            u = np.empty(self.mesh.n_edges)
+        ph, dh, _ = _ptr(h, np.float64)
+        pu, du, _ = _ptr(u, np.float64)
+        _check(lib().fblts_get_state(self.handle, ph, pu, dh if h is not None else du))
+        return h, u
+
+    def set_drag(self, cd):
+        p, d, k = _ptr(cd, np.float64)
+        _check(lib().fblts_set_drag(self.handle, p, d))
+
+    def set_wind(self, wn, wt):
+        pn, dn, kn = _ptr(wn, np.float64)
+        pt, dt, kt = _ptr(wt, np.float64)
+        _check(lib().fblts_set_wind(self.handle, pn, pt, dn))
+
+    def step(self, n=1):
+        _check(lib().fblts_step(self.handle, int(n)))
+
+    def set_graph(self, on=True):
+        _check(lib().fblts_set_graph(self.handle, int(on)))
+
+    def diagnostics(self, allow_nonfinite=False):
+        d = fblts_diag()
+        rc = lib().fblts_diagnostics(self.handle, C.byref(d))
+        if rc == FBLTS_ENONFINITE and allow_nonfinite:
+            return d.as_dict()
+        _check(rc)
+        return d.as_dict()
+
+    def info(self):
+        i = fblts_info()
+        _check(lib().fblts_get_info(self.handle, C.byref(i)))
+        return i.as_dict()
+
+    def tendency(self, which, h, u):
+        n = self.mesh.n_cells if which == 0 else self.mesh.n_edges
+        out = np.empty(n)
+        ph, dh, kh = _ptr(h, np.float64)
+        pu, du, ku = _ptr(u, np.float64)
+        po, do, ko = _ptr(out, np.float64)
+        _check(lib().fblts_debug_tendency(self.handle, int(which), ph, pu, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def set_timing(self, on=True):
+        _check(lib().fblts_set_timing(self.handle, int(on)))
+
+    def kernel_time(self, cls):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().fblts_kernel_time(self.handle, int(cls), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fblts_solver_destroy(self.handle)
+            self.handle = None
+
+
+class Ensemble:
+    """fblts_ensemble: members of several meshes advanced by shared launches."""
+
+    def __init__(self, meshes, labels, members, dt, M=1, scheme=SCHEME_FBLTS, linear=False, binary=True,
+                 stream=None, **kw):
+        self.meshes = list(meshes)
+        self.members = [int(m) for m in members]
+        self.params = make_params(dt, M, scheme, linear, **kw)
+        n = len(self.meshes)
+        mh = (C.c_void_p * n)(*[m.handle.value for m in self.meshes])
+        self._labs = [np.ascontiguousarray(l, dtype=np.int8) for l in labels]
+        lp = (C.POINTER(C.c_int8) * n)(*[l.ctypes.data_as(C.POINTER(C.c_int8)) for l in self._labs])
+        mem = np.ascontiguousarray(self.members, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib().fblts_ensemble_create(mh, lp, int(binary), mem.ctypes.data_as(_P_i32), n,
+                                           C.byref(self.params), _stream_handle(stream), C.byref(h)))
+        self.handle = h
+
+    def set_member(self, mesh, member, h, u, cd=None):
+        ph, dh, kh = _ptr(h, np.float64)
+        pu, du, ku = _ptr(u, np.float64)
+        pc, dc, kc = _ptr(cd, np.float64)
+        _check(lib().fblts_ensemble_set_member(self.handle, int(mesh), int(member), ph, pu, pc, dh))
+
+    def get_member(self, mesh, member):
+        h = np.empty(self.meshes[mesh].n_cells)
+        u = np.empty(self.meshes[mesh].n_edges)
+        _check(lib().fblts_ensemble_get_member(self.handle, int(mesh), int(member), h.ctypes.data_as(C.c_void_p),
+                                               u.ctypes.data_as(C.c_void_p), 0))
+        return h, u
+
+    def step(self, n=1):
+        _check(lib().fblts_ensemble_step(self.handle, int(n)))
+
+    def set_graph(self, on=True):
+        _check(lib().fblts_ensemble_set_graph(self.handle, int(on)))
+
+    def diagnostics(self):
+        tot = sum(self.members)
+        arr = (fblts_diag * tot)()
+        _check(lib().fblts_ensemble_diagnostics(self.handle, arr))
+        return [a.as_dict() for a in arr]
+
+    def info(self):
+        mc, cs, mb = C.c_int64(), C.c_int64(), C.c_double()
+        _check(lib().fblts_ensemble_info(self.handle, C.byref(mc), C.byref(cs), C.byref(mb)))
+        return dict(member_cells=mc.value, cell_substeps_per_step=cs.value, model_bytes_per_step=mb.value)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.fblts_ensemble_destroy(self.handle)
+            self.handle = None

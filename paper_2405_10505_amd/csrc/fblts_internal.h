@@ -1,0 +1,142 @@
+// Internal types shared by the host planner and the gfx950 kernels.
+//
+// Device layout (all in the library's region-contiguous numbering):
+//   * per-entity scalars: one value per cell / edge / vertex;
+//   * fixed-degree incidence lists in slot-major ("ELL") order, list[j*stride + i],
+//     so the lanes of a wavefront read consecutive addresses for slot j;
+//   * state and scratch arrays carry nm members innermost: x[i*nm + member].
+#pragma once
+#include <cstdint>
+
+namespace fblts {
+
+constexpr int kMaxSeg = 4;       // meshes (segments) one launch can cover
+constexpr int kBlock = 256;      // threads per block for the stencil passes
+
+// Permuted mesh, device pointers.  Edge codes carry a sign bit:
+// code = 2*e + (sign < 0 ? 1 : 0).
+struct MeshDev {
+  int N, E, V;
+  int cs, es, vs;          // slot strides (cell, edge, vertex lists)
+  int maxE, maxEOE;
+  // cells
+  const int* c_nedge;      // [N]
+  const int* c_edge;       // [maxE][cs]  edge code, sign = n_{e,i}
+  const int* c_nbr;        // [maxE][cs]  cell across that edge
+  const double* c_invA;    // [N]
+  const double* c_A;       // [N]
+  const double* c_H;       // [N]
+  // edges
+  const int* e_cell;       // [2][es]  c0, c1 (n_e points c0 -> c1)
+  const int* e_vert;       // [2][es]  v0, v1 (t_e points v0 -> v1)
+  const double* e_dc;      // [E] d_e
+  const double* e_dv;      // [E] l_e
+  const double* e_invdc;   // [E]
+  const double* e_He;      // [E] resting depth at the edge (linear flux)
+  const int* e_neoe;       // [E]
+  const int* e_eoe;        // [maxEOE][es]
+  const double* e_w;       // [maxEOE][es]
+  // vertices
+  const int* v_edge;       // [3][vs]  edge code, sign = circulation sign s_{e,v}
+  const int* v_cell;       // [3][vs]
+  const double* v_kite;    // [3][vs]
+  const double* v_invA;    // [V]
+  const double* v_A;       // [V]
+  const double* v_f;       // [V]
+  const double* v_q0;      // [V] f_v / H_v (linear PV about rest)
+};
+
+// Thickness pass: Psi, FB stage update, FB-averaged thickness and Bernoulli
+// function over cells [begin,end).  Psi is evaluated on [upd_begin,upd_end)
+// (written as H0 + c_dt*Psi to Hdst) and on [acc_begin,acc_end) (added to acc
+// with weight acc_w; acc_first overwrites instead of adding).  Everywhere in
+// [begin,end): Hnew = updated value or Hnew_src[i]; hs = wn*Hnew + ws*Hsrc +
+// wb*H0; B = K(Usrc) + g (hs - H).
+struct CellSeg {
+  MeshDev m;
+  int nm_log2;
+  int begin, end, upd_begin, upd_end, acc_begin, acc_end, acc_first;
+  const double* Hsrc;
+  const double* Usrc;
+  const double* H0;
+  const double* Hnew_src;
+  double* Hdst;
+  double* hs;
+  double* B;
+  double* acc;
+  double c_dt, wn, ws, wb, acc_w, g;
+};
+
+// Vertex pass: q_v = (zeta_v(Usrc) + f_v) / h_v(hs) over vertices [begin,end).
+struct VertSeg {
+  MeshDev m;
+  int nm_log2;
+  int begin, end;
+  const double* Usrc;
+  const double* hs;
+  double* q;
+};
+
+// Edge-prep pass: P_e = (l_e h_e u_e, q_e, l_e u_e, h_e) over edges [begin,end).
+struct PrepSeg {
+  MeshDev m;
+  int nm_log2;
+  int begin, end;
+  int linear;
+  const double* Usrc;
+  const double* hs;
+  const double* q;         // per member (nonlinear) or the static q0 (linear)
+  double* P;               // double4 per edge and member
+};
+
+// Momentum pass: Phi_e from P, B, drag and wind over edges; update
+// [upd_begin,upd_end) as U0 + c_dt*Phi into Udst, accumulate on
+// [acc_begin,acc_end).
+struct EdgeSeg {
+  MeshDev m;
+  int nm_log2;
+  int begin, end, upd_begin, upd_end, acc_begin, acc_end, acc_first;
+  const double* P;
+  const double* B;
+  const double* Usrc;
+  const double* U0;
+  double* Udst;
+  double* acc;
+  const double* cd;        // per cell and member, or nullptr
+  const double* wind_n;    // per edge, or nullptr
+  const double* wind_t;
+  double c_dt, acc_w, rho_ratio;
+};
+
+// Interface-one prediction (eq. preds) over cells [c_begin,c_end) and edges
+// [e_begin,e_end); on k == 0 the coarse data is first saved to the compact
+// arrays sv_h[4][nc*nm], sv_u[4][ne*nm].
+struct PredSeg {
+  int nm_log2;
+  int c_begin, c_end, e_begin, e_end;
+  double* H0; double* H1; double* H2; double* H3;
+  double* U0; double* U1; double* U2; const double* U3;
+  double* sv_h; double* sv_u;
+  int save;
+  double a, one_minus_a, invM, c, ap;
+};
+
+// Interface correction and assembly of t^{n+1}: IF-1 from the saved h^n,
+// IF-2 from H0 (= h^n there), interior from the coarse stage 3.
+struct AsmSeg {
+  int nm_log2;
+  int if1_c_begin, if1_c_end, if2_c_end, N;
+  int if1_e_begin, if1_e_end, if2_e_end, E;
+  double* H0; const double* H3; const double* acc_h; const double* sv_h;
+  double* U0; const double* U3; const double* acc_u; const double* sv_u;
+  double delta;
+};
+
+template <class S>
+struct Launch {
+  int nseg;
+  int blk_start[kMaxSeg + 1];
+  S seg[kMaxSeg];
+};
+
+}  // namespace fblts

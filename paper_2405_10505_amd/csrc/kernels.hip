@@ -1,0 +1,519 @@
+// gfx950 kernels of the FB-LTS hot path.
+//
+// One stage of FB-RK(3,2) (paper Section 2.1, eq. fbrk32) -- and therefore of
+// the coarse advancement and of every fine substep of FB-LTS (Section 2.2) --
+// runs as four gather passes over contiguous index ranges:
+//   cell pass   : Psi (eq. trisk_thickness), the FB stage update of h, the
+//                 FB-averaged thickness h*, and B = K + g(h* - H);
+//   vertex pass : potential vorticity q_v = (zeta_v + f_v) / h*_v;
+//   prep pass   : per-edge (l F, q_e, l u, h_e) packed as one double4;
+//   edge pass   : Phi (PV flux through the TRiSK weights, eq. trisk_vorticity,
+//                 Bernoulli gradient, quadratic drag and wind stress of
+//                 eq. hurricane_model), the FB stage update of u.
+// The work is HBM/L2-gather bound (well below one FP64 flop per byte), so
+// there is no matrix-core path: lanes map to (entity, member) pairs with the
+// member index fastest, blocks are remapped so that each XCD works on a
+// contiguous slice of the range (its L2 then holds that slice's neighbours),
+// and every value has exactly one writer (no atomics; bitwise deterministic).
+#include <hip/hip_runtime.h>
+
+#include "fblts_internal.h"
+
+namespace fblts {
+
+// Blocks are dispatched round-robin over the 8 XCDs; give XCD x the
+// contiguous tile run [start(x), start(x)+count(x)).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int X = 8;
+  const int q = n / X, r = n % X;
+  const int x = b % X, k = b / X;
+  return x * q + (x < r ? x : r) + k;
+}
+
+template <class S>
+__device__ __forceinline__ int find_seg(const Launch<S>& L, int b) {
+  int s = 0;
+#pragma unroll
+  for (int k = 1; k < kMaxSeg; ++k)
+    if (k < L.nseg && b >= L.blk_start[k]) s = k;
+  return s;
+}
+
+// ---------------------------------------------------------------- cell pass
+template <bool NONLINEAR>
+__global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = find_seg(L, b);
+  const CellSeg& S = L.seg[s];
+  const int nm_log2 = S.nm_log2;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const int i = (int)(item >> nm_log2);
+  if (i >= S.end) return;
+  const int mem = (int)(item & ((1 << nm_log2) - 1));
+  const int nm = 1 << nm_log2;
+  const MeshDev& m = S.m;
+
+  const bool in_upd = i >= S.upd_begin && i < S.upd_end;
+  const bool in_acc = i >= S.acc_begin && i < S.acc_end;
+  const bool need_psi = in_upd || in_acc;
+  const double h_i = S.Hsrc[(long)i * nm + mem];
+  double flux = 0.0, ke = 0.0;
+  const int ne = m.c_nedge[i];
+  for (int j = 0; j < ne; ++j) {
+    const int code = m.c_edge[j * m.cs + i];
+    const int e = code >> 1;
+    const double ue = S.Usrc[(long)e * nm + mem];
+    const double dv = m.e_dv[e];
+    if (NONLINEAR) ke = fma(dv * m.e_dc[e], ue * ue, ke);
+    if (need_psi) {
+      double he;
+      if (NONLINEAR) {
+        const int nb = m.c_nbr[j * m.cs + i];
+        he = 0.5 * (h_i + S.Hsrc[(long)nb * nm + mem]);
+      } else {
+        he = m.e_He[e];
+      }
+      const double f = dv * (he * ue);
+      flux = (code & 1) ? flux - f : flux + f;
+    }
+  }
+  const long ii = (long)i * nm + mem;
+  const double psi = -flux * m.c_invA[i];
+  double hnew;
+  const double h0 = S.H0[ii];
+  if (in_upd) {
+    hnew = fma(S.c_dt, psi, h0);
+    S.Hdst[ii] = hnew;
+  } else {
+    hnew = S.Hnew_src[ii];
+  }
+  if (in_acc) {
+    const double a = S.acc_w * psi;
+    S.acc[ii] = S.acc_first ? a : S.acc[ii] + a;
+  }
+  const double hs = S.wn * hnew + S.ws * h_i + S.wb * h0;
+  S.hs[ii] = hs;
+  const double K = NONLINEAR ? 0.25 * ke * m.c_invA[i] : 0.0;
+  S.B[ii] = K + S.g * (hs - m.c_H[i]);
+}
+
+// -------------------------------------------------------------- vertex pass
+__global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = find_seg(L, b);
+  const VertSeg& S = L.seg[s];
+  const int nm_log2 = S.nm_log2;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const int v = (int)(item >> nm_log2);
+  if (v >= S.end) return;
+  const int mem = (int)(item & ((1 << nm_log2) - 1));
+  const int nm = 1 << nm_log2;
+  const MeshDev& m = S.m;
+  double circ = 0.0, hv = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int code = m.v_edge[j * m.vs + v];
+    const int e = code >> 1;
+    const double c = m.e_dc[e] * S.Usrc[(long)e * nm + mem];
+    circ = (code & 1) ? circ - c : circ + c;
+    hv = fma(m.v_kite[j * m.vs + v], S.hs[(long)m.v_cell[j * m.vs + v] * nm + mem], hv);
+  }
+  const double ia = m.v_invA[v];
+  S.q[(long)v * nm + mem] = (circ * ia + m.v_f[v]) / (hv * ia);
+}
+
+// ---------------------------------------------------------------- prep pass
+__global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = find_seg(L, b);
+  const PrepSeg& S = L.seg[s];
+  const int nm_log2 = S.nm_log2;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const int e = (int)(item >> nm_log2);
+  if (e >= S.end) return;
+  const int mem = (int)(item & ((1 << nm_log2) - 1));
+  const int nm = 1 << nm_log2;
+  const MeshDev& m = S.m;
+  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  const int v0 = m.e_vert[e], v1 = m.e_vert[m.es + e];
+  const double u = S.Usrc[(long)e * nm + mem];
+  const double dv = m.e_dv[e];
+  double he, qe;
+  if (S.linear) {
+    he = m.e_He[e];
+    qe = 0.5 * (S.q[v0] + S.q[v1]);
+  } else {
+    he = 0.5 * (S.hs[(long)c0 * nm + mem] + S.hs[(long)c1 * nm + mem]);
+    qe = 0.5 * (S.q[(long)v0 * nm + mem] + S.q[(long)v1 * nm + mem]);
+  }
+  double4 p;
+  p.x = dv * (he * u);
+  p.y = qe;
+  p.z = dv * u;
+  p.w = he;
+  reinterpret_cast<double4*>(S.P)[(long)e * nm + mem] = p;
+}
+
+// ---------------------------------------------------------------- edge pass
+template <bool DRAG, bool WIND>
+__global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = find_seg(L, b);
+  const EdgeSeg& S = L.seg[s];
+  const int nm_log2 = S.nm_log2;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const int e = (int)(item >> nm_log2);
+  if (e >= S.end) return;
+  const int mem = (int)(item & ((1 << nm_log2) - 1));
+  const int nm = 1 << nm_log2;
+  const MeshDev& m = S.m;
+  const double4* P = reinterpret_cast<const double4*>(S.P);
+  const long ee = (long)e * nm + mem;
+  const double4 pe = P[ee];
+  double sq = 0.0, su = 0.0;
+  const int n = m.e_neoe[e];
+  for (int j = 0; j < n; ++j) {
+    const int e2 = m.e_eoe[j * m.es + e];
+    const double w = m.e_w[j * m.es + e];
+    const double4 p2 = P[(long)e2 * nm + mem];
+    sq = fma(w * p2.x, pe.y + p2.y, sq);
+    if (DRAG || WIND) su = fma(w, p2.z, su);
+  }
+  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  const double idc = m.e_invdc[e];
+  double phi = 0.5 * sq * idc - (S.B[(long)c1 * nm + mem] - S.B[(long)c0 * nm + mem]) * idc;
+  if (DRAG || WIND) {
+    const double u = S.Usrc[ee];
+    const double up = su * idc;
+    if (DRAG) {
+      const double cde = 0.5 * (S.cd[(long)c0 * nm + mem] + S.cd[(long)c1 * nm + mem]);
+      phi -= cde * sqrt(u * u + up * up) * u / pe.w;
+    }
+    if (WIND) {
+      const double wn = S.wind_n[e], wt = S.wind_t[e];
+      const double cw = S.rho_ratio * (0.75 + 0.067 * sqrt(wn * wn + wt * wt)) * 1e-3;
+      const double rn = wn - u, rt = wt - up;
+      phi += cw * sqrt(rn * rn + rt * rt) * rn / pe.w;
+    }
+  }
+  if (e >= S.upd_begin && e < S.upd_end) S.Udst[ee] = fma(S.c_dt, phi, S.U0[ee]);
+  if (e >= S.acc_begin && e < S.acc_end) {
+    const double a = S.acc_w * phi;
+    S.acc[ee] = S.acc_first ? a : S.acc[ee] + a;
+  }
+}
+
+// ---------------------------------------------------------- prediction pass
+__global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
+  const int b = blockIdx.x;
+  const int s = find_seg(L, b);
+  const PredSeg& S = L.seg[s];
+  const int nm_log2 = S.nm_log2;
+  const int nm = 1 << nm_log2;
+  const long nc = (long)(S.c_end - S.c_begin) * nm;
+  const long ne = (long)(S.e_end - S.e_begin) * nm;
+  const long t = (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  if (t < nc) {
+    const long i = (long)S.c_begin * nm + t;
+    double hn, h1, h2, h3;
+    if (S.save) {
+      hn = S.H0[i]; h1 = S.H1[i]; h2 = S.H2[i]; h3 = S.H3[i];
+      S.sv_h[t] = hn; S.sv_h[nc + t] = h1; S.sv_h[2 * nc + t] = h2; S.sv_h[3 * nc + t] = h3;
+    } else {
+      hn = S.sv_h[t]; h1 = S.sv_h[nc + t]; h2 = S.sv_h[2 * nc + t]; h3 = S.sv_h[3 * nc + t];
+    }
+    S.H0[i] = S.a * h3 + S.one_minus_a * hn;
+    S.H1[i] = S.a * h3 + S.invM * h1 + S.c * hn;
+    S.H2[i] = S.a * h3 + S.invM * h2 + S.c * hn;
+    S.H3[i] = S.ap * h3 + S.c * hn;
+  } else if (t < nc + ne) {
+    const long tt = t - nc;
+    const long i = (long)S.e_begin * nm + tt;
+    double un, u1, u2, u3;
+    if (S.save) {
+      un = S.U0[i]; u1 = S.U1[i]; u2 = S.U2[i]; u3 = S.U3[i];
+      S.sv_u[tt] = un; S.sv_u[ne + tt] = u1; S.sv_u[2 * ne + tt] = u2; S.sv_u[3 * ne + tt] = u3;
+    } else {
+      un = S.sv_u[tt]; u1 = S.sv_u[ne + tt]; u2 = S.sv_u[2 * ne + tt]; u3 = S.sv_u[3 * ne + tt];
+    }
+    S.U0[i] = S.a * u3 + S.one_minus_a * un;
+    S.U1[i] = S.a * u3 + S.invM * u1 + S.c * un;
+    S.U2[i] = S.a * u3 + S.invM * u2 + S.c * un;
+  }
+}
+
+// ------------------------------------------------------------ assembly pass
+__global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
+  const int b = blockIdx.x;
+  const int s = find_seg(L, b);
+  const AsmSeg& S = L.seg[s];
+  const int nm = 1 << S.nm_log2;
+  const long ncell = (long)(S.N - S.if1_c_begin) * nm;
+  const long nedge = (long)(S.E - S.if1_e_begin) * nm;
+  const long t = (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  if (t < ncell) {
+    const long i = (long)S.if1_c_begin * nm + t;
+    const long c = i >> S.nm_log2;
+    if (c < S.if1_c_end) {
+      S.H0[i] = fma(S.delta, S.acc_h[i], S.sv_h[t]);
+    } else if (c < S.if2_c_end) {
+      S.H0[i] = fma(S.delta, S.acc_h[i], S.H0[i]);
+    } else {
+      S.H0[i] = S.H3[i];
+    }
+  } else if (t < ncell + nedge) {
+    const long tt = t - ncell;
+    const long i = (long)S.if1_e_begin * nm + tt;
+    const long e = i >> S.nm_log2;
+    if (e < S.if1_e_end) {
+      S.U0[i] = fma(S.delta, S.acc_u[i], S.sv_u[tt]);
+    } else if (e < S.if2_e_end) {
+      S.U0[i] = fma(S.delta, S.acc_u[i], S.U0[i]);
+    } else {
+      S.U0[i] = S.U3[i];
+    }
+  }
+}
+
+// RK4 final combination: y <- y + (dt/6) acc over [0,n*nm).
+__global__ void __launch_bounds__(kBlock) k_axpy_final(double* y, const double* acc, double c, long n) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) y[t] = fma(c, acc[t], y[t]);
+}
+
+// Member scatter/gather between caller numbering and the library's numbering:
+// dst[new*nm + member] = src[old(new)] (to_lib) or the reverse.
+__global__ void __launch_bounds__(kBlock) k_permute(double* dst, const double* src, const int* perm_new_to_old,
+                                                    int n, int nm_log2, int member, int to_lib) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const long lib = ((long)i << nm_log2) + member;
+  const int usr = perm_new_to_old[i];
+  if (to_lib) dst[lib] = src[usr];
+  else dst[usr] = src[lib];
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(double* dst, const double* src, long n) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(double* dst, double v, long n) {
+  const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+  if (t < n) dst[t] = v;
+}
+
+// ------------------------------------------------------------- diagnostics
+// Per (block, member) partial sums in a fixed tree, then one block per
+// member sums the partials in block order: the result does not depend on
+// scheduling.  Quantities (kDiagQ): mass, abs vorticity, |abs vorticity|,
+// cell energy, edge energy, min h, non-finite count, h <= 0 count.
+constexpr int kDiagQ = 8;
+
+__device__ __forceinline__ void block_reduce(double* sh, double v, int nm, bool is_min) {
+  // sh holds kBlock values; lanes with equal (tid % nm) belong to one member
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int stride = kBlock / 2; stride >= nm; stride >>= 1) {
+    if (threadIdx.x < stride) {
+      const double a = sh[threadIdx.x], c = sh[threadIdx.x + stride];
+      sh[threadIdx.x] = is_min ? fmin(a, c) : a + c;
+    }
+    __syncthreads();
+  }
+}
+
+struct DiagArgs {
+  MeshDev m;
+  int nm_log2;
+  int linear;
+  const double* h;
+  const double* u;
+  double g;
+  double* partial;    // [kDiagQ][nblocks][nm]
+  int nblocks;
+};
+
+__global__ void __launch_bounds__(kBlock) k_diag(const DiagArgs A) {
+  __shared__ double sh[kBlock];
+  const int nm = 1 << A.nm_log2;
+  const MeshDev& m = A.m;
+  const int mem = threadIdx.x & (nm - 1);
+  const int lane_ent = threadIdx.x >> A.nm_log2;
+  const int ents_per_pass = kBlock >> A.nm_log2;
+  const int nmax = m.N > m.E ? (m.N > m.V ? m.N : m.V) : (m.E > m.V ? m.E : m.V);
+  const int chunk = (nmax + A.nblocks - 1) / A.nblocks;
+  const int lo = blockIdx.x * chunk;
+  const int hi = lo + chunk;
+  double q[kDiagQ] = {0, 0, 0, 0, 0, 1e300, 0, 0};
+  for (int i = lo + lane_ent; i < hi; i += ents_per_pass) {
+    if (i < m.N) {
+      const double h = A.h[(long)i * nm + mem];
+      const double H = m.c_H[i];
+      q[0] += m.c_A[i] * h;
+      if (A.linear) q[3] += 0.5 * A.g * m.c_A[i] * (h - H) * (h - H);
+      else q[3] += m.c_A[i] * A.g * h * (0.5 * h - H);
+      q[5] = fmin(q[5], h);
+      if (!isfinite(h)) q[6] += 1.0;
+      if (!(h > 0.0)) q[7] += 1.0;
+    }
+    if (i < m.E) {
+      const double u = A.u[(long)i * nm + mem];
+      const double he = A.linear ? m.e_He[i]
+                                 : 0.5 * (A.h[(long)m.e_cell[i] * nm + mem] + A.h[(long)m.e_cell[m.es + i] * nm + mem]);
+      q[4] += 0.5 * m.e_dv[i] * m.e_dc[i] * he * u * u;
+      if (!isfinite(u)) q[6] += 1.0;
+    }
+    if (i < m.V) {
+      double circ = 0.0;
+      for (int j = 0; j < 3; ++j) {
+        const int code = m.v_edge[j * m.vs + i];
+        const int e = code >> 1;
+        const double c = m.e_dc[e] * A.u[(long)e * nm + mem];
+        circ = (code & 1) ? circ - c : circ + c;
+      }
+      const double eta = circ + m.v_A[i] * m.v_f[i];
+      q[1] += eta;
+      q[2] += fabs(eta);
+    }
+  }
+  for (int k = 0; k < kDiagQ; ++k) {
+    block_reduce(sh, q[k], nm, k == 5);
+    if (threadIdx.x < nm) A.partial[((long)k * A.nblocks + blockIdx.x) * nm + threadIdx.x] = sh[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// One block per member: sum partials over blocks in order (tree over a fixed
+// assignment of blocks to threads).
+__global__ void __launch_bounds__(kBlock) k_diag_final(const double* partial, int nblocks, int nm, double* out) {
+  __shared__ double sh[kBlock];
+  const int mem = blockIdx.x;
+  for (int k = 0; k < kDiagQ; ++k) {
+    const bool is_min = k == 5;
+    double v = is_min ? 1e300 : 0.0;
+    for (int bb = threadIdx.x; bb < nblocks; bb += kBlock) {
+      const double x = partial[((long)k * nblocks + bb) * nm + mem];
+      v = is_min ? fmin(v, x) : v + x;
+    }
+    block_reduce(sh, v, 1, is_min);
+    if (threadIdx.x == 0) out[(long)mem * kDiagQ + k] = sh[0];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- host launchers
+template <class S>
+static int blocks_for(Launch<S>& L, long (*items)(const S&)) {
+  int acc = 0;
+  for (int s = 0; s < L.nseg; ++s) {
+    L.blk_start[s] = acc;
+    acc += (int)((items(L.seg[s]) + kBlock - 1) / kBlock);
+  }
+  for (int s = L.nseg; s <= kMaxSeg; ++s) L.blk_start[s] = acc;
+  return acc;
+}
+
+static long cell_items(const CellSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
+static long vert_items(const VertSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
+static long prep_items(const PrepSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
+static long edge_items(const EdgeSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
+static long pred_items(const PredSeg& s) {
+  return ((long)(s.c_end - s.c_begin) + (long)(s.e_end - s.e_begin)) << s.nm_log2;
+}
+static long asm_items(const AsmSeg& s) {
+  return ((long)(s.N - s.if1_c_begin) + (long)(s.E - s.if1_e_begin)) << s.nm_log2;
+}
+
+// Each launcher returns the number of blocks launched (0: nothing to do).
+int launch_cell(Launch<CellSeg> L, bool nonlinear, hipStream_t st) {
+  const int nb = blocks_for(L, cell_items);
+  if (nb == 0) return 0;
+  if (nonlinear) hipLaunchKernelGGL(k_cell<true>, dim3(nb), dim3(kBlock), 0, st, L);
+  else hipLaunchKernelGGL(k_cell<false>, dim3(nb), dim3(kBlock), 0, st, L);
+  return nb;
+}
+
+int launch_vertex(Launch<VertSeg> L, hipStream_t st) {
+  const int nb = blocks_for(L, vert_items);
+  if (nb == 0) return 0;
+  hipLaunchKernelGGL(k_vertex, dim3(nb), dim3(kBlock), 0, st, L);
+  return nb;
+}
+
+int launch_prep(Launch<PrepSeg> L, hipStream_t st) {
+  const int nb = blocks_for(L, prep_items);
+  if (nb == 0) return 0;
+  hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kBlock), 0, st, L);
+  return nb;
+}
+
+int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, hipStream_t st) {
+  const int nb = blocks_for(L, edge_items);
+  if (nb == 0) return 0;
+  if (drag && wind) hipLaunchKernelGGL((k_edge<true, true>), dim3(nb), dim3(kBlock), 0, st, L);
+  else if (drag) hipLaunchKernelGGL((k_edge<true, false>), dim3(nb), dim3(kBlock), 0, st, L);
+  else if (wind) hipLaunchKernelGGL((k_edge<false, true>), dim3(nb), dim3(kBlock), 0, st, L);
+  else hipLaunchKernelGGL((k_edge<false, false>), dim3(nb), dim3(kBlock), 0, st, L);
+  return nb;
+}
+
+int launch_predict(Launch<PredSeg> L, hipStream_t st) {
+  const int nb = blocks_for(L, pred_items);
+  if (nb == 0) return 0;
+  hipLaunchKernelGGL(k_predict, dim3(nb), dim3(kBlock), 0, st, L);
+  return nb;
+}
+
+int launch_assemble(Launch<AsmSeg> L, hipStream_t st) {
+  const int nb = blocks_for(L, asm_items);
+  if (nb == 0) return 0;
+  hipLaunchKernelGGL(k_assemble, dim3(nb), dim3(kBlock), 0, st, L);
+  return nb;
+}
+
+void launch_axpy_final(double* y, const double* acc, double c, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpy_final, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, y, acc, c, n);
+}
+
+void launch_permute(double* dst, const double* src, const int* perm, int n, int nm_log2, int member, int to_lib,
+                    hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_permute, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, dst, src, perm, n, nm_log2,
+                     member, to_lib);
+}
+
+void launch_copy(double* dst, const double* src, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, dst, src, n);
+}
+
+void launch_fill(double* dst, double v, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, dst, v, n);
+}
+
+int diag_blocks(const MeshDev& m) {
+  int nmax = m.N > m.E ? (m.N > m.V ? m.N : m.V) : (m.E > m.V ? m.E : m.V);
+  int nb = (nmax + 4095) / 4096;
+  return nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+}
+
+void launch_diag(const MeshDev& m, int nm_log2, int linear, const double* h, const double* u, double g,
+                 double* partial, double* out, hipStream_t st) {
+  DiagArgs A;
+  A.m = m;
+  A.nm_log2 = nm_log2;
+  A.linear = linear;
+  A.h = h;
+  A.u = u;
+  A.g = g;
+  A.partial = partial;
+  A.nblocks = diag_blocks(m);
+  hipLaunchKernelGGL(k_diag, dim3(A.nblocks), dim3(kBlock), 0, st, A);
+  hipLaunchKernelGGL(k_diag_final, dim3(1 << nm_log2), dim3(kBlock), 0, st, (const double*)partial, A.nblocks,
+                     1 << nm_log2, out);
+}
+
+}  // namespace fblts

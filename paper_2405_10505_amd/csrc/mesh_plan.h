@@ -1,0 +1,82 @@
+// Host-side mesh copy, validation, region layering and the per-solver plan
+// (permutation, pass ranges, byte model).  No device code here.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fblts.h"
+
+namespace fblts {
+
+struct HostMesh {
+  int N = 0, E = 0, V = 0;
+  std::vector<int> coe, voe;                 // [2E]
+  std::vector<int> eoc_off, eoc, voc_off, voc;
+  std::vector<int> eoe_off, eoe;
+  std::vector<double> woe;
+  std::vector<int> eov, cov;                 // [3V]
+  std::vector<double> kite;                  // [3V]
+  std::vector<double> dc, dv, A, Av, fv, fe, H;
+};
+
+// Throws std::runtime_error with a message naming the violated property.
+void validate_and_copy(const fblts_mesh_desc* d, HostMesh& m);
+
+// 4-level labels from binary or 4-level input; throws on invalid input.
+// layer[i]: fine cells -(hops to coarse set), coarse cells +(hops to fine set);
+// +big / -big when the other set is empty.
+void layer_regions(const HostMesh& m, const int8_t* labels, bool binary, int r, std::vector<int8_t>& lab4,
+                   std::vector<int>& layer);
+
+struct Range {
+  int b = 0, e = 0;
+  int size() const { return e > b ? e - b : 0; }
+};
+
+// One stage's four passes.
+struct StageRanges {
+  Range cell, cell_upd, cell_acc;
+  Range vert, prep;
+  Range edge, edge_upd, edge_acc;
+};
+
+struct Plan {
+  // permutations: new -> old (caller) index
+  std::vector<int> cell_new2old, edge_new2old, vert_new2old;
+  std::vector<int> cell_old2new, edge_old2new, vert_old2new;
+  std::vector<int8_t> cell_lab, edge_lab;    // in new numbering
+  int nF = 0, nIF1 = 0, nIF2 = 0, nINT = 0;  // cells per region (contiguous in this order)
+  int nFE = 0, nIF1E = 0, nIF2E = 0, nINTE = 0;
+  StageRanges coarse[3];   // coarse advancement (suffix ranges)
+  StageRanges fine[3];     // fine substep (prefix ranges)
+  int fine_depth_max = 0;  // deepest fine layer touched by the coarse sweep (hops)
+};
+
+// Build the plan for FB-LTS (4-level labels) or for a global scheme (all
+// coarse).  nonlinear selects the vertex passes.  Throws std::runtime_error
+// (message starting with "region:") when the stencil condition fails.
+void build_plan(const HostMesh& m, const std::vector<int8_t>& lab4, const std::vector<int>& layer, bool fblts,
+                bool nonlinear, int r, Plan& p);
+
+// Reordered mesh in the device layout (host staging before upload).
+struct PermMesh {
+  int N, E, V, cs, es, vs, maxE, maxEOE;
+  std::vector<int> c_nedge, c_edge, c_nbr;
+  std::vector<double> c_invA, c_A, c_H;
+  std::vector<int> e_cell, e_vert, e_neoe, e_eoe;
+  std::vector<double> e_dc, e_dv, e_invdc, e_He, e_w;
+  std::vector<int> v_edge, v_cell;
+  std::vector<double> v_kite, v_invA, v_A, v_f, v_q0;
+};
+void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm);
+
+// Algorithmic (compulsory) bytes of each pass kind over a range: every mesh
+// array element and state element the pass's mathematics references, once.
+// nm = members; state bytes scale with nm, mesh bytes do not.
+double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm);
+double bytes_vert_pass(const PermMesh& pm, const Range& r, int nm);
+double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm);
+double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm);
+
+}  // namespace fblts

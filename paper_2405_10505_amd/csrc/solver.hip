@@ -1,0 +1,1291 @@
+// Solver, ensemble and the C ABI of include/fblts.h.
+//
+// Step orchestration (one coarse step of FB-LTS, paper Section 2.2):
+//   coarse advancement: 3 FB-RK(3,2) stages with dt over suffix ranges of the
+//     region-ordered mesh (the coarse region plus the fine layers its
+//     stencils reach), writing H1..H3 / U1..U3;
+//   for k = 0..M-1: interface-one prediction (eq. preds), then 3 stages with
+//     dt/M over prefix ranges (fine region plus the halo its stencils read);
+//     stage 3 updates the fine region in place and accumulates Psi / Phi on
+//     interface one and two (eq. if_correction);
+//   assembly: interface correction and interior copy.
+// Global FB-RK(3,2) runs the three stages over whole ranges; RK4 runs four
+// stages with accumulation.  All launches go to one stream; a coarse step can
+// be captured once in a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <tuple>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fblts.h"
+#include "fblts_internal.h"
+#include "mesh_plan.h"
+
+namespace fblts {
+int launch_cell(Launch<CellSeg> L, bool nonlinear, hipStream_t st);
+int launch_vertex(Launch<VertSeg> L, hipStream_t st);
+int launch_prep(Launch<PrepSeg> L, hipStream_t st);
+int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, hipStream_t st);
+int launch_predict(Launch<PredSeg> L, hipStream_t st);
+int launch_assemble(Launch<AsmSeg> L, hipStream_t st);
+void launch_axpy_final(double* y, const double* acc, double c, long n, hipStream_t st);
+void launch_permute(double* dst, const double* src, const int* perm, int n, int nm_log2, int member, int to_lib,
+                    hipStream_t st);
+void launch_copy(double* dst, const double* src, long n, hipStream_t st);
+void launch_fill(double* dst, double v, long n, hipStream_t st);
+int diag_blocks(const MeshDev& m);
+void launch_diag(const MeshDev& m, int nm_log2, int linear, const double* h, const double* u, double g,
+                 double* partial, double* out, hipStream_t st);
+constexpr int kDiagQ = 8;
+}  // namespace fblts
+
+using namespace fblts;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+namespace {
+
+struct Err : std::runtime_error {
+  int code;
+  Err(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Err(FBLTS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Err& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "out of host memory";
+    return FBLTS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    const std::string s = g_err;
+    if (s.rfind("region:", 0) == 0) return FBLTS_EREGION;
+    return FBLTS_EINVAL;
+  } catch (...) {
+    g_err = "unknown error";
+    return FBLTS_EINVAL;
+  }
+}
+
+// ----------------------------------------------------------- device buffers
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 8;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) throw Err(FBLTS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    bytes = b;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+template <class T>
+void upload(DevBuf& d, const std::vector<T>& v) {
+  d.alloc(v.size() * sizeof(T));
+  if (!v.empty()) hip_check(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy H2D");
+}
+
+// Device copy of the permuted mesh.
+struct DevMesh {
+  DevBuf c_nedge, c_edge, c_nbr, c_invA, c_A, c_H;
+  DevBuf e_cell, e_vert, e_dc, e_dv, e_invdc, e_He, e_neoe, e_eoe, e_w;
+  DevBuf v_edge, v_cell, v_kite, v_invA, v_A, v_f, v_q0;
+  DevBuf cell_n2o, edge_n2o, vert_n2o;
+  MeshDev md{};
+  void upload_from(const PermMesh& pm, const Plan& p) {
+    upload(c_nedge, pm.c_nedge);
+    upload(c_edge, pm.c_edge);
+    upload(c_nbr, pm.c_nbr);
+    upload(c_invA, pm.c_invA);
+    upload(c_A, pm.c_A);
+    upload(c_H, pm.c_H);
+    upload(e_cell, pm.e_cell);
+    upload(e_vert, pm.e_vert);
+    upload(e_dc, pm.e_dc);
+    upload(e_dv, pm.e_dv);
+    upload(e_invdc, pm.e_invdc);
+    upload(e_He, pm.e_He);
+    upload(e_neoe, pm.e_neoe);
+    upload(e_eoe, pm.e_eoe);
+    upload(e_w, pm.e_w);
+    upload(v_edge, pm.v_edge);
+    upload(v_cell, pm.v_cell);
+    upload(v_kite, pm.v_kite);
+    upload(v_invA, pm.v_invA);
+    upload(v_A, pm.v_A);
+    upload(v_f, pm.v_f);
+    upload(v_q0, pm.v_q0);
+    upload(cell_n2o, p.cell_new2old);
+    upload(edge_n2o, p.edge_new2old);
+    upload(vert_n2o, p.vert_new2old);
+    md.N = pm.N;
+    md.E = pm.E;
+    md.V = pm.V;
+    md.cs = pm.cs;
+    md.es = pm.es;
+    md.vs = pm.vs;
+    md.maxE = pm.maxE;
+    md.maxEOE = pm.maxEOE;
+    md.c_nedge = c_nedge.as<int>();
+    md.c_edge = c_edge.as<int>();
+    md.c_nbr = c_nbr.as<int>();
+    md.c_invA = c_invA.as<double>();
+    md.c_A = c_A.as<double>();
+    md.c_H = c_H.as<double>();
+    md.e_cell = e_cell.as<int>();
+    md.e_vert = e_vert.as<int>();
+    md.e_dc = e_dc.as<double>();
+    md.e_dv = e_dv.as<double>();
+    md.e_invdc = e_invdc.as<double>();
+    md.e_He = e_He.as<double>();
+    md.e_neoe = e_neoe.as<int>();
+    md.e_eoe = e_eoe.as<int>();
+    md.e_w = e_w.as<double>();
+    md.v_edge = v_edge.as<int>();
+    md.v_cell = v_cell.as<int>();
+    md.v_kite = v_kite.as<double>();
+    md.v_invA = v_invA.as<double>();
+    md.v_A = v_A.as<double>();
+    md.v_f = v_f.as<double>();
+    md.v_q0 = v_q0.as<double>();
+  }
+};
+
+// State and scratch of nm members on one mesh.
+struct DevState {
+  int nm = 1, nm_log2 = 0;
+  DevBuf H[4], hs, B, acc_h, sv_h, cd;
+  DevBuf U[4], acc_u, sv_u, P, q;
+  DevBuf wind_n, wind_t;
+  bool has_wind = false;
+  void alloc(const PermMesh& pm, const Plan& p, int nm_) {
+    nm = nm_;
+    nm_log2 = 0;
+    while ((1 << nm_log2) < nm) ++nm_log2;
+    const size_t Nc = (size_t)pm.N * nm, Ne = (size_t)pm.E * nm, Nv = (size_t)pm.V * nm;
+    for (int k = 0; k < 4; ++k) {
+      H[k].alloc(Nc * 8);
+      U[k].alloc(Ne * 8);
+    }
+    hs.alloc(Nc * 8);
+    B.alloc(Nc * 8);
+    acc_h.alloc(Nc * 8);
+    cd.alloc(Nc * 8);
+    acc_u.alloc(Ne * 8);
+    P.alloc(Ne * 32);
+    q.alloc(Nv * 8);
+    sv_h.alloc((size_t)4 * std::max(1, p.nIF1) * nm * 8);
+    sv_u.alloc((size_t)4 * std::max(1, p.nIF1E) * nm * 8);
+  }
+};
+
+struct Pass {
+  enum Kind { CELL, VERT, PREP, EDGE, PRED, ASM, RK4FIN } kind;
+  Launch<CellSeg> cell;
+  Launch<VertSeg> vert;
+  Launch<PrepSeg> prep;
+  Launch<EdgeSeg> edge;
+  Launch<PredSeg> pred;
+  Launch<AsmSeg> asmb;
+  // RK4 final: per segment (y, acc, n)
+  std::vector<std::tuple<double*, const double*, long>> fin;
+  double fin_c = 0.0;
+  double model_bytes = 0.0;
+};
+
+struct MeshUnit {
+  // one mesh with nm members: plan, device mesh, state, pass list
+  const HostMesh* hm = nullptr;
+  std::vector<int8_t> lab4;
+  std::vector<int> layer;
+  Plan plan;
+  PermMesh pm;
+  DevMesh dm;
+  DevState st;
+  std::vector<Pass> passes;
+  int64_t cell_substeps = 0;
+  double bytes_edge = 0.0;
+  int64_t edge_items = 0;
+};
+
+struct Params {
+  fblts_params p;
+  bool nonlinear() const { return p.physics == FBLTS_PHYS_NONLINEAR; }
+};
+
+void check_params(const fblts_params* p) {
+  if (!p) throw Err(FBLTS_EINVAL, "params is NULL");
+  if (!(p->dt > 0) || !std::isfinite(p->dt)) throw Err(FBLTS_EINVAL, "dt must be positive");
+  if (!(p->g > 0)) throw Err(FBLTS_EINVAL, "g must be positive");
+  if (p->M < 1 || p->M > 1024) throw Err(FBLTS_EINVAL, "M must be in 1..1024");
+  if (p->scheme < 0 || p->scheme > 2) throw Err(FBLTS_EINVAL, "unknown scheme");
+  if (p->physics < 0 || p->physics > 1) throw Err(FBLTS_EINVAL, "unknown physics");
+  if (p->r_layers < 1 || p->r_layers > 64) throw Err(FBLTS_EINVAL, "r_layers must be in 1..64");
+}
+
+// Build the pass list of one mesh unit (segments are merged by the caller).
+void build_passes(MeshUnit& u, const Params& P, bool drag_on) {
+  const fblts_params& p = P.p;
+  const bool nl = P.nonlinear();
+  const MeshDev& md = u.dm.md;
+  DevState& s = u.st;
+  auto H = [&](int k) { return s.H[k].as<double>(); };
+  auto U = [&](int k) { return s.U[k].as<double>(); };
+  const double* qsrc = nl ? s.q.as<double>() : md.v_q0;
+  u.passes.clear();
+  u.bytes_edge = 0;
+  u.edge_items = 0;
+  const int nm = s.nm;
+
+  auto cell_pass = [&](const StageRanges& r, const double* Hsrc, const double* Usrc, const double* H0,
+                       const double* Hnew_src, double* Hdst, double c_dt, double wn, double ws, double wb,
+                       double* acc, double acc_w, int acc_first) {
+    Pass ps;
+    ps.kind = Pass::CELL;
+    ps.cell.nseg = 1;
+    CellSeg& c = ps.cell.seg[0];
+    c.m = md;
+    c.nm_log2 = s.nm_log2;
+    c.begin = r.cell.b;
+    c.end = r.cell.e;
+    c.upd_begin = r.cell_upd.b;
+    c.upd_end = r.cell_upd.e;
+    c.acc_begin = r.cell_acc.b;
+    c.acc_end = r.cell_acc.e;
+    c.acc_first = acc_first;
+    c.Hsrc = Hsrc;
+    c.Usrc = Usrc;
+    c.H0 = H0;
+    c.Hnew_src = Hnew_src;
+    c.Hdst = Hdst;
+    c.hs = s.hs.as<double>();
+    c.B = s.B.as<double>();
+    c.acc = acc;
+    c.c_dt = c_dt;
+    c.wn = wn;
+    c.ws = ws;
+    c.wb = wb;
+    c.acc_w = acc_w;
+    c.g = p.g;
+    ps.model_bytes = bytes_cell_pass(u.pm, r, nl, nm);
+    u.passes.push_back(ps);
+  };
+  auto vert_pass = [&](const StageRanges& r, const double* Usrc) {
+    if (!nl || r.vert.size() == 0) return;
+    Pass ps;
+    ps.kind = Pass::VERT;
+    ps.vert.nseg = 1;
+    VertSeg& v = ps.vert.seg[0];
+    v.m = md;
+    v.nm_log2 = s.nm_log2;
+    v.begin = r.vert.b;
+    v.end = r.vert.e;
+    v.Usrc = Usrc;
+    v.hs = s.hs.as<double>();
+    v.q = s.q.as<double>();
+    ps.model_bytes = bytes_vert_pass(u.pm, r.vert, nm);
+    u.passes.push_back(ps);
+  };
+  auto prep_pass = [&](const StageRanges& r, const double* Usrc) {
+    Pass ps;
+    ps.kind = Pass::PREP;
+    ps.prep.nseg = 1;
+    PrepSeg& q = ps.prep.seg[0];
+    q.m = md;
+    q.nm_log2 = s.nm_log2;
+    q.begin = r.prep.b;
+    q.end = r.prep.e;
+    q.linear = nl ? 0 : 1;
+    q.Usrc = Usrc;
+    q.hs = s.hs.as<double>();
+    q.q = qsrc;
+    q.P = s.P.as<double>();
+    ps.model_bytes = bytes_prep_pass(u.pm, r.prep, nl, nm);
+    u.passes.push_back(ps);
+  };
+  auto edge_pass = [&](const StageRanges& r, const double* Usrc, const double* U0, double* Udst, double c_dt,
+                       double* acc, double acc_w, int acc_first) {
+    Pass ps;
+    ps.kind = Pass::EDGE;
+    ps.edge.nseg = 1;
+    EdgeSeg& e = ps.edge.seg[0];
+    e.m = md;
+    e.nm_log2 = s.nm_log2;
+    e.begin = r.edge.b;
+    e.end = r.edge.e;
+    e.upd_begin = r.edge_upd.b;
+    e.upd_end = r.edge_upd.e;
+    e.acc_begin = r.edge_acc.b;
+    e.acc_end = r.edge_acc.e;
+    e.acc_first = acc_first;
+    e.P = s.P.as<double>();
+    e.B = s.B.as<double>();
+    e.Usrc = Usrc;
+    e.U0 = U0;
+    e.Udst = Udst;
+    e.acc = acc;
+    e.cd = drag_on ? s.cd.as<double>() : nullptr;
+    e.wind_n = s.has_wind ? s.wind_n.as<double>() : nullptr;
+    e.wind_t = s.has_wind ? s.wind_t.as<double>() : nullptr;
+    e.c_dt = c_dt;
+    e.acc_w = acc_w;
+    e.rho_ratio = p.rho_air / p.rho_water;
+    ps.model_bytes = bytes_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
+    u.bytes_edge += ps.model_bytes;
+    u.edge_items += (int64_t)r.edge.size() * nm;
+    u.passes.push_back(ps);
+  };
+  auto stage = [&](const StageRanges& r, const double* Hsrc, const double* Usrc, const double* H0,
+                   const double* Hnew_src, double* Hdst, double c_dt, double wn, double ws, double wb, double* acch,
+                   const double* U0, double* Udst, double* accu, double acc_w, int acc_first) {
+    cell_pass(r, Hsrc, Usrc, H0, Hnew_src, Hdst, c_dt, wn, ws, wb, acch, acc_w, acc_first);
+    vert_pass(r, Usrc);
+    prep_pass(r, Usrc);
+    edge_pass(r, Usrc, U0, Udst, c_dt, accu, acc_w, acc_first);
+  };
+
+  const double dt = p.dt, b1 = p.beta1, b2 = p.beta2, b3 = p.beta3;
+  const Plan& pl = u.plan;
+  const int N = md.N, E = md.E;
+  if (p.scheme == FBLTS_SCHEME_FBRK32) {
+    const StageRanges* R = pl.coarse;
+    stage(R[0], H(0), U(0), H(0), H(1), H(1), dt / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
+    stage(R[1], H(1), U(1), H(0), H(2), H(2), dt / 2, b2, 0.0, 1 - b2, nullptr, U(0), U(2), nullptr, 1, 1);
+    // stage 3 updates the state in place
+    stage(R[2], H(2), U(2), H(0), H(0), H(0), dt, b3, 1 - 2 * b3, b3, nullptr, U(0), U(0), nullptr, 1, 1);
+    u.cell_substeps = (int64_t)N * nm;
+    return;
+  }
+  if (p.scheme == FBLTS_SCHEME_RK4) {
+    StageRanges R = pl.coarse[0];
+    StageRanges Racc = R;
+    Racc.cell_acc = {0, N};
+    Racc.edge_acc = {0, E};
+    StageRanges Rlast = Racc;
+    Rlast.cell_upd = {0, 0};
+    Rlast.edge_upd = {0, 0};
+    double* ah = s.acc_h.as<double>();
+    double* au = s.acc_u.as<double>();
+    // y2 = y + dt/2 k1 -> slot 1; y3 = y + dt/2 k2 -> slot 2; y4 = y + dt k3 -> slot 1
+    stage(Racc, H(0), U(0), H(0), H(1), H(1), dt / 2, 0.0, 1.0, 0.0, ah, U(0), U(1), au, 1.0, 1);
+    stage(Racc, H(1), U(1), H(0), H(2), H(2), dt / 2, 0.0, 1.0, 0.0, ah, U(0), U(2), au, 2.0, 0);
+    stage(Racc, H(2), U(2), H(0), H(1), H(1), dt, 0.0, 1.0, 0.0, ah, U(0), U(1), au, 2.0, 0);
+    stage(Rlast, H(1), U(1), H(0), H(3), H(3), 0.0, 0.0, 1.0, 0.0, ah, U(0), U(3), au, 1.0, 0);
+    Pass fin;
+    fin.kind = Pass::RK4FIN;
+    fin.fin_c = dt / 6.0;
+    fin.fin.emplace_back(H(0), ah, (long)N * nm);
+    fin.fin.emplace_back(U(0), au, (long)E * nm);
+    fin.model_bytes = 3.0 * 8.0 * ((double)N + E) * nm;
+    u.passes.push_back(fin);
+    u.cell_substeps = (int64_t)N * nm;
+    return;
+  }
+  // ---- FB-LTS
+  const int M = p.M;
+  const double delta = dt / M;
+  const StageRanges* C = pl.coarse;
+  stage(C[0], H(0), U(0), H(0), H(1), H(1), dt / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
+  stage(C[1], H(1), U(1), H(0), H(2), H(2), dt / 2, b2, 0.0, 1 - b2, nullptr, U(0), U(2), nullptr, 1, 1);
+  stage(C[2], H(2), U(2), H(0), H(3), H(3), dt, b3, 1 - 2 * b3, b3, nullptr, U(0), U(3), nullptr, 1, 1);
+  const int if1b = pl.nF, if1e = pl.nF + pl.nIF1, if2e = if1e + pl.nIF2;
+  const int if1eb = pl.nFE, if1ee = pl.nFE + pl.nIF1E, if2ee = if1ee + pl.nIF2E;
+  const StageRanges* F = pl.fine;
+  double* ah = s.acc_h.as<double>();
+  double* au = s.acc_u.as<double>();
+  for (int k = 0; k < M; ++k) {
+    Pass pr;
+    pr.kind = Pass::PRED;
+    pr.pred.nseg = 1;
+    PredSeg& q = pr.pred.seg[0];
+    q.nm_log2 = s.nm_log2;
+    q.c_begin = if1b;
+    q.c_end = if1e;
+    q.e_begin = if1eb;
+    q.e_end = if1ee;
+    q.H0 = H(0);
+    q.H1 = H(1);
+    q.H2 = H(2);
+    q.H3 = H(3);
+    q.U0 = U(0);
+    q.U1 = U(1);
+    q.U2 = U(2);
+    q.U3 = U(3);
+    q.sv_h = s.sv_h.as<double>();
+    q.sv_u = s.sv_u.as<double>();
+    q.save = k == 0;
+    q.a = (double)k / (double)M;
+    q.one_minus_a = (double)(M - k) / (double)M;
+    q.invM = 1.0 / M;
+    q.c = (double)(M - k - 1) / (double)M;
+    q.ap = (double)(k + 1) / (double)M;
+    pr.model_bytes = ((double)(if1e - if1b) * 8 + (double)(if1ee - if1eb) * 7) * 8.0 * nm;
+    u.passes.push_back(pr);
+    stage(F[0], H(0), U(0), H(0), H(1), H(1), delta / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
+    stage(F[1], H(1), U(1), H(0), H(2), H(2), delta / 2, b2, 0.0, 1 - b2, nullptr, U(0), U(2), nullptr, 1, 1);
+    stage(F[2], H(2), U(2), H(0), H(3), H(0), delta, b3, 1 - 2 * b3, b3, ah, U(0), U(0), au, 1.0, k == 0);
+  }
+  Pass as;
+  as.kind = Pass::ASM;
+  as.asmb.nseg = 1;
+  AsmSeg& a = as.asmb.seg[0];
+  a.nm_log2 = s.nm_log2;
+  a.if1_c_begin = if1b;
+  a.if1_c_end = if1e;
+  a.if2_c_end = if2e;
+  a.N = N;
+  a.if1_e_begin = if1eb;
+  a.if1_e_end = if1ee;
+  a.if2_e_end = if2ee;
+  a.E = E;
+  a.H0 = H(0);
+  a.H3 = H(3);
+  a.acc_h = ah;
+  a.sv_h = s.sv_h.as<double>();
+  a.U0 = U(0);
+  a.U3 = U(3);
+  a.acc_u = au;
+  a.sv_u = s.sv_u.as<double>();
+  a.delta = delta;
+  as.model_bytes = (((double)(N - if1b) * 3) + ((double)(E - if1eb) * 3)) * 8.0 * nm;
+  u.passes.push_back(as);
+  u.cell_substeps = ((int64_t)(N - pl.nF) + (int64_t)M * pl.nF) * nm;
+}
+
+// Merge per-mesh pass lists into multi-segment launches.
+std::vector<Pass> merge_passes(const std::vector<MeshUnit*>& units) {
+  std::vector<Pass> out;
+  if (units.empty()) return out;
+  const size_t n = units[0]->passes.size();
+  for (auto* u : units)
+    if (u->passes.size() != n) throw Err(FBLTS_EINVAL, "ensemble meshes have different pass sequences");
+  if ((int)units.size() > kMaxSeg) throw Err(FBLTS_EINVAL, "too many meshes in one ensemble (max 4)");
+  for (size_t k = 0; k < n; ++k) {
+    Pass ps = units[0]->passes[k];
+    for (size_t m = 1; m < units.size(); ++m) {
+      const Pass& q = units[m]->passes[k];
+      if (q.kind != ps.kind) throw Err(FBLTS_EINVAL, "ensemble pass kinds differ");
+      const int j = (int)m;
+      switch (ps.kind) {
+        case Pass::CELL: ps.cell.seg[j] = q.cell.seg[0]; ps.cell.nseg = j + 1; break;
+        case Pass::VERT: ps.vert.seg[j] = q.vert.seg[0]; ps.vert.nseg = j + 1; break;
+        case Pass::PREP: ps.prep.seg[j] = q.prep.seg[0]; ps.prep.nseg = j + 1; break;
+        case Pass::EDGE: ps.edge.seg[j] = q.edge.seg[0]; ps.edge.nseg = j + 1; break;
+        case Pass::PRED: ps.pred.seg[j] = q.pred.seg[0]; ps.pred.nseg = j + 1; break;
+        case Pass::ASM: ps.asmb.seg[j] = q.asmb.seg[0]; ps.asmb.nseg = j + 1; break;
+        case Pass::RK4FIN:
+          for (auto& t : q.fin) ps.fin.push_back(t);
+          break;
+      }
+      ps.model_bytes += q.model_bytes;
+    }
+    out.push_back(ps);
+  }
+  return out;
+}
+
+struct Timing {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+  size_t used[4] = {0, 0, 0, 0};
+  ~Timing() {
+    for (auto& v : ev)
+      for (auto& p : v) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+      }
+  }
+  std::pair<hipEvent_t, hipEvent_t> get(int cls) {
+    if (used[cls] == ev[cls].size()) {
+      hipEvent_t a, b;
+      hip_check(hipEventCreate(&a), "hipEventCreate");
+      hip_check(hipEventCreate(&b), "hipEventCreate");
+      ev[cls].emplace_back(a, b);
+    }
+    return ev[cls][used[cls]++];
+  }
+  void reset() { std::fill(used, used + 4, 0); }
+};
+
+// Launch a pass list on a stream.
+void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool wind, hipStream_t st, Timing* tm) {
+  for (const Pass& ps : passes) {
+    int cls = -1;
+    switch (ps.kind) {
+      case Pass::EDGE: cls = 0; break;
+      case Pass::CELL: cls = 1; break;
+      case Pass::VERT: cls = 2; break;
+      case Pass::PREP: cls = 3; break;
+      default: break;
+    }
+    std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
+    if (tm && tm->on && cls >= 0) {
+      evp = tm->get(cls);
+      hip_check(hipEventRecord(evp.first, st), "hipEventRecord");
+    }
+    switch (ps.kind) {
+      case Pass::CELL: launch_cell(ps.cell, nonlinear, st); break;
+      case Pass::VERT: launch_vertex(ps.vert, st); break;
+      case Pass::PREP: launch_prep(ps.prep, st); break;
+      case Pass::EDGE: launch_edge(ps.edge, drag, wind, st); break;
+      case Pass::PRED: launch_predict(ps.pred, st); break;
+      case Pass::ASM: launch_assemble(ps.asmb, st); break;
+      case Pass::RK4FIN:
+        for (auto& t : ps.fin) launch_axpy_final(std::get<0>(t), std::get<1>(t), ps.fin_c, std::get<2>(t), st);
+        break;
+    }
+    if (evp.first) hip_check(hipEventRecord(evp.second, st), "hipEventRecord");
+  }
+  hip_check(hipGetLastError(), "kernel launch");
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ objects
+
+struct fblts_mesh {
+  HostMesh hm;
+};
+
+struct fblts_solver {
+  const fblts_mesh* mesh = nullptr;
+  Params P;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::unique_ptr<MeshUnit> unit;
+  bool have_regions = false, have_state = false, drag_on = false;
+  bool graph_on = false, graph_valid = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  Timing timing;
+  DevBuf diag_partial, diag_out;
+  DevBuf stage_h, stage_u;   // caller-order staging
+  DevBuf dbg_h, dbg_u, dbg_out;
+  double time = 0.0;
+  int64_t step = 0;
+  ~fblts_solver() {
+    drop_graph();
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_valid = false;
+  }
+};
+
+struct fblts_ensemble {
+  Params P;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<std::unique_ptr<MeshUnit>> units;
+  std::vector<Pass> passes;
+  bool graph_on = false, graph_valid = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  DevBuf diag_partial, diag_out, stage_h, stage_u;
+  int64_t step = 0;
+  ~fblts_ensemble() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+// ------------------------------------------------------------------ helpers
+
+static void setup_unit(MeshUnit& u, const HostMesh& hm, const Params& P, const int8_t* labels, bool binary, int nm) {
+  u.hm = &hm;
+  const bool fblts_scheme = P.p.scheme == FBLTS_SCHEME_FBLTS;
+  if (fblts_scheme) {
+    if (!labels) throw Err(FBLTS_EINVAL, "labels is NULL");
+    layer_regions(hm, labels, binary, P.p.r_layers, u.lab4, u.layer);
+  } else {
+    u.lab4.assign(hm.N, 3);
+    u.layer.assign(hm.N, 1 << 20);
+  }
+  build_plan(hm, u.lab4, u.layer, fblts_scheme, P.nonlinear(), P.p.r_layers, u.plan);
+  permute_mesh(hm, u.plan, u.pm);
+  u.dm.upload_from(u.pm, u.plan);
+  u.st.alloc(u.pm, u.plan, nm);
+}
+
+static void init_scratch(MeshUnit& u, hipStream_t st) {
+  // every scratch array starts as a copy of the state (finite everywhere)
+  const long Nc = (long)u.pm.N * u.st.nm, Ne = (long)u.pm.E * u.st.nm;
+  for (int k = 1; k < 4; ++k) {
+    launch_copy(u.st.H[k].as<double>(), u.st.H[0].as<double>(), Nc, st);
+    launch_copy(u.st.U[k].as<double>(), u.st.U[0].as<double>(), Ne, st);
+  }
+  launch_copy(u.st.hs.as<double>(), u.st.H[0].as<double>(), Nc, st);
+  launch_fill(u.st.B.as<double>(), 0.0, Nc, st);
+  launch_fill(u.st.acc_h.as<double>(), 0.0, Nc, st);
+  launch_fill(u.st.acc_u.as<double>(), 0.0, Ne, st);
+  launch_fill(u.st.P.as<double>(), 0.0, Ne * 4, st);
+  launch_fill(u.st.q.as<double>(), 0.0, (long)u.pm.V * u.st.nm, st);
+}
+
+static hipStream_t make_stream(void* s, bool& own) {
+  if (s) {
+    own = false;
+    return static_cast<hipStream_t>(s);
+  }
+  hipStream_t st;
+  hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+  own = true;
+  return st;
+}
+
+static void state_in(MeshUnit& u, DevBuf& sh, DevBuf& su, const double* h, const double* uu, int member,
+                     bool on_device, hipStream_t st) {
+  const int N = u.pm.N, E = u.pm.E;
+  const double* dh = h;
+  const double* du = uu;
+  if (!on_device) {
+    if (sh.bytes < (size_t)N * 8) sh.alloc((size_t)N * 8);
+    if (su.bytes < (size_t)E * 8) su.alloc((size_t)E * 8);
+    if (h) hip_check(hipMemcpyAsync(sh.p, h, (size_t)N * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    if (uu) hip_check(hipMemcpyAsync(su.p, uu, (size_t)E * 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    dh = sh.as<double>();
+    du = su.as<double>();
+  }
+  if (h) launch_permute(u.st.H[0].as<double>(), dh, u.dm.cell_n2o.as<int>(), N, u.st.nm_log2, member, 1, st);
+  if (uu) launch_permute(u.st.U[0].as<double>(), du, u.dm.edge_n2o.as<int>(), E, u.st.nm_log2, member, 1, st);
+}
+
+static void state_out(MeshUnit& u, DevBuf& sh, DevBuf& su, double* h, double* uu, int member, bool on_device,
+                      hipStream_t st) {
+  const int N = u.pm.N, E = u.pm.E;
+  double* dh = h;
+  double* du = uu;
+  if (!on_device) {
+    if (sh.bytes < (size_t)N * 8) sh.alloc((size_t)N * 8);
+    if (su.bytes < (size_t)E * 8) su.alloc((size_t)E * 8);
+    dh = sh.as<double>();
+    du = su.as<double>();
+  }
+  if (h) launch_permute(dh, u.st.H[0].as<double>(), u.dm.cell_n2o.as<int>(), N, u.st.nm_log2, member, 0, st);
+  if (uu) launch_permute(du, u.st.U[0].as<double>(), u.dm.edge_n2o.as<int>(), E, u.st.nm_log2, member, 0, st);
+  if (!on_device) {
+    if (h) hip_check(hipMemcpyAsync(h, sh.p, (size_t)N * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    if (uu) hip_check(hipMemcpyAsync(uu, su.p, (size_t)E * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  }
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+static void diag_of(MeshUnit& u, const Params& P, DevBuf& part, DevBuf& out, hipStream_t st, std::vector<double>& res) {
+  const int nb = diag_blocks(u.dm.md);
+  const size_t need = (size_t)kDiagQ * nb * u.st.nm * 8;
+  if (part.bytes < need) part.alloc(need);
+  if (out.bytes < (size_t)kDiagQ * u.st.nm * 8) out.alloc((size_t)kDiagQ * u.st.nm * 8);
+  launch_diag(u.dm.md, u.st.nm_log2, P.nonlinear() ? 0 : 1, u.st.H[0].as<double>(), u.st.U[0].as<double>(), P.p.g,
+              part.as<double>(), out.as<double>(), st);
+  hip_check(hipGetLastError(), "diagnostics launch");
+  res.resize((size_t)kDiagQ * u.st.nm);
+  hip_check(hipMemcpyAsync(res.data(), out.p, res.size() * 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+static int fill_diag(const double* q, double time, int64_t step, fblts_diag* o) {
+  o->mass = q[0];
+  o->abs_vorticity = q[1];
+  o->abs_vorticity_scale = q[2];
+  o->energy = q[3] + q[4];
+  o->min_h = q[5];
+  o->n_nonfinite = (int64_t)q[6];
+  o->time = time;
+  o->step = step;
+  return (q[6] > 0 || q[7] > 0) ? FBLTS_ENONFINITE : FBLTS_OK;
+}
+
+// ------------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char* fblts_last_error(void) { return g_err.c_str(); }
+int fblts_version(void) { return 100; }
+
+int fblts_mesh_create(const fblts_mesh_desc* desc, fblts_mesh** out) {
+  return guarded([&] {
+    if (!out) throw Err(FBLTS_EINVAL, "out is NULL");
+    auto m = std::make_unique<fblts_mesh>();
+    validate_and_copy(desc, m->hm);
+    *out = m.release();
+    return FBLTS_OK;
+  });
+}
+
+void fblts_mesh_destroy(fblts_mesh* mesh) { delete mesh; }
+
+int fblts_layer_regions(const fblts_mesh* mesh, const int8_t* labels, int32_t binary, int32_t r, int8_t* out_labels,
+                        int32_t* out_layer) {
+  return guarded([&] {
+    if (!mesh || !out_labels) throw Err(FBLTS_EINVAL, "NULL argument");
+    std::vector<int8_t> lab4;
+    std::vector<int> layer;
+    layer_regions(mesh->hm, labels, binary != 0, r, lab4, layer);
+    std::memcpy(out_labels, lab4.data(), lab4.size());
+    if (out_layer)
+      for (size_t i = 0; i < layer.size(); ++i) out_layer[i] = layer[i];
+    return FBLTS_OK;
+  });
+}
+
+int fblts_solver_create(const fblts_mesh* mesh, const fblts_params* params, void* hip_stream, fblts_solver** out) {
+  return guarded([&] {
+    if (!mesh || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    check_params(params);
+    auto s = std::make_unique<fblts_solver>();
+    s->mesh = mesh;
+    s->P.p = *params;
+    hip_check(hipGetDevice(&s->device), "hipGetDevice");
+    s->stream = make_stream(hip_stream, s->own_stream);
+    *out = s.release();
+    return FBLTS_OK;
+  });
+}
+
+void fblts_solver_destroy(fblts_solver* s) {
+  if (s && s->stream) (void)hipStreamSynchronize(s->stream);
+  delete s;
+}
+
+int fblts_set_regions(fblts_solver* s, const int8_t* labels, int32_t binary) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->drop_graph();
+    s->have_regions = false;
+    s->have_state = false;
+    auto u = std::make_unique<MeshUnit>();
+    setup_unit(*u, s->mesh->hm, s->P, labels, binary != 0, 1);
+    s->unit = std::move(u);
+    s->drag_on = false;
+    build_passes(*s->unit, s->P, s->drag_on);
+    s->have_regions = true;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_set_state(fblts_solver* s, const double* h, const double* u, int32_t on_device) {
+  return guarded([&] {
+    if (!s || !h || !u) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
+    if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    state_in(*s->unit, s->stage_h, s->stage_u, h, u, 0, on_device != 0, s->stream);
+    init_scratch(*s->unit, s->stream);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->have_state = true;
+    s->time = 0.0;
+    s->step = 0;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_get_state(fblts_solver* s, double* h, double* u, int32_t on_device) {
+  return guarded([&] {
+    if (!s || (!h && !u)) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (!s->have_state) throw Err(FBLTS_ESTATE, "no state");
+    state_out(*s->unit, s->stage_h, s->stage_u, h, u, 0, on_device != 0, s->stream);
+    return FBLTS_OK;
+  });
+}
+
+int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
+    MeshUnit& u = *s->unit;
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->drop_graph();
+    if (!cd) {
+      s->drag_on = false;
+    } else {
+      if (!s->P.nonlinear()) throw Err(FBLTS_EINVAL, "drag needs nonlinear physics");
+      if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      const double* src = cd;
+      if (!on_device) {
+        if (s->stage_h.bytes < (size_t)u.pm.N * 8) s->stage_h.alloc((size_t)u.pm.N * 8);
+        hip_check(hipMemcpyAsync(s->stage_h.p, cd, (size_t)u.pm.N * 8, hipMemcpyHostToDevice, s->stream), "memcpy");
+        src = s->stage_h.as<double>();
+      }
+      launch_permute(u.st.cd.as<double>(), src, u.dm.cell_n2o.as<int>(), u.pm.N, 0, 0, 1, s->stream);
+      hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+      s->drag_on = true;
+    }
+    build_passes(u, s->P, s->drag_on);
+    return FBLTS_OK;
+  });
+}
+
+int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t on_device) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
+    MeshUnit& u = *s->unit;
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->drop_graph();
+    if (!wn || !wt) {
+      u.st.has_wind = false;
+    } else {
+      if (!s->P.nonlinear()) throw Err(FBLTS_EINVAL, "wind stress needs nonlinear physics");
+      if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      const int E = u.pm.E;
+      if (u.st.wind_n.bytes < (size_t)E * 8) {
+        u.st.wind_n.alloc((size_t)E * 8);
+        u.st.wind_t.alloc((size_t)E * 8);
+      }
+      const double* a = wn;
+      const double* b = wt;
+      DevBuf ta, tb;
+      if (!on_device) {
+        ta.alloc((size_t)E * 8);
+        tb.alloc((size_t)E * 8);
+        hip_check(hipMemcpy(ta.p, wn, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
+        hip_check(hipMemcpy(tb.p, wt, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
+        a = ta.as<double>();
+        b = tb.as<double>();
+      }
+      launch_permute(u.st.wind_n.as<double>(), a, u.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
+      launch_permute(u.st.wind_t.as<double>(), b, u.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
+      hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+      u.st.has_wind = true;
+    }
+    build_passes(u, s->P, s->drag_on);
+    return FBLTS_OK;
+  });
+}
+
+int fblts_set_graph(fblts_solver* s, int32_t enable) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->drop_graph();
+    s->graph_on = enable != 0;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_step(fblts_solver* s, int32_t n) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    if (n < 0) throw Err(FBLTS_EINVAL, "negative step count");
+    if (!s->have_state) throw Err(FBLTS_ESTATE, "set_state must come first");
+    MeshUnit& u = *s->unit;
+    const bool nl = s->P.nonlinear();
+    if (s->graph_on && !s->timing.on) {
+      if (!s->graph_valid) {
+        hip_check(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+          run_passes(u.passes, nl, s->drag_on, u.st.has_wind, s->stream, nullptr);
+        } catch (...) {
+          hipGraph_t g;
+          (void)hipStreamEndCapture(s->stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        hip_check(hipStreamEndCapture(s->stream, &s->graph), "hipStreamEndCapture");
+        hip_check(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        s->graph_valid = true;
+      }
+      for (int k = 0; k < n; ++k) hip_check(hipGraphLaunch(s->gexec, s->stream), "hipGraphLaunch");
+    } else {
+      if (s->timing.on) s->timing.reset();
+      for (int k = 0; k < n; ++k) run_passes(u.passes, nl, s->drag_on, u.st.has_wind, s->stream, &s->timing);
+    }
+    s->step += n;
+    s->time += n * s->P.p.dt;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_diagnostics(fblts_solver* s, fblts_diag* out) {
+  return guarded([&] {
+    if (!s || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (!s->have_state) throw Err(FBLTS_ESTATE, "no state");
+    std::vector<double> q;
+    diag_of(*s->unit, s->P, s->diag_partial, s->diag_out, s->stream, q);
+    const int rc = fill_diag(q.data(), s->time, s->step, out);
+    if (rc != FBLTS_OK) g_err = "state holds non-finite values or h <= 0";
+    return rc;
+  });
+}
+
+int fblts_get_info(fblts_solver* s, fblts_info* o) {
+  return guarded([&] {
+    if (!s || !o) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
+    const MeshUnit& u = *s->unit;
+    std::memset(o, 0, sizeof(*o));
+    o->n_cells = u.pm.N;
+    o->n_edges = u.pm.E;
+    o->n_vertices = u.pm.V;
+    o->n_fine = u.plan.nF;
+    o->n_if1 = u.plan.nIF1;
+    o->n_if2 = u.plan.nIF2;
+    o->n_int = u.plan.nINT;
+    o->n_fine_e = u.plan.nFE;
+    o->n_if1_e = u.plan.nIF1E;
+    o->n_if2_e = u.plan.nIF2E;
+    o->n_int_e = u.plan.nINTE;
+    o->max_edges = u.pm.maxE;
+    o->max_eoe = u.pm.maxEOE;
+    o->cell_substeps_per_step = u.cell_substeps;
+    int64_t launches = 0;
+    double bytes = 0;
+    for (const Pass& p : u.passes) {
+      launches += p.kind == Pass::RK4FIN ? (int64_t)p.fin.size() : 1;
+      bytes += p.model_bytes;
+    }
+    o->launches_per_step = launches;
+    o->model_bytes_per_step = bytes;
+    o->model_bytes_edge_pass = u.bytes_edge;
+    o->edge_pass_items_per_step = u.edge_items;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_set_timing(fblts_solver* s, int32_t enable) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    s->timing.on = enable != 0;
+    s->timing.reset();
+    return FBLTS_OK;
+  });
+}
+
+int fblts_kernel_time(fblts_solver* s, int32_t cls, double* avg_ms, int64_t* launches) {
+  return guarded([&] {
+    if (!s || !avg_ms || cls < 0 || cls > 3) throw Err(FBLTS_EINVAL, "bad argument");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    double tot = 0;
+    const size_t n = s->timing.used[cls];
+    for (size_t k = 0; k < n; ++k) {
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, s->timing.ev[cls][k].first, s->timing.ev[cls][k].second), "hipEventElapsedTime");
+      tot += ms;
+    }
+    *avg_ms = n ? tot / n : 0.0;
+    if (launches) *launches = (int64_t)n;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const double* u, double* out,
+                         int32_t on_device) {
+  return guarded([&] {
+    if (!s || !h || !u || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (which != 0 && which != 1) throw Err(FBLTS_EINVAL, "which must be 0 (Psi) or 1 (Phi)");
+    if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
+    MeshUnit& U = *s->unit;
+    const int N = U.pm.N, E = U.pm.E, V = U.pm.V;
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (s->dbg_h.bytes < (size_t)N * 8) s->dbg_h.alloc((size_t)N * 8);
+    if (s->dbg_u.bytes < (size_t)E * 8) s->dbg_u.alloc((size_t)E * 8);
+    if (s->dbg_out.bytes < (size_t)std::max(N, E) * 8) s->dbg_out.alloc((size_t)std::max(N, E) * 8);
+    // stage the inputs in library order (member slot 0 of a one-member layout)
+    const double* sh = h;
+    const double* su = u;
+    DevBuf th, tu;
+    if (!on_device) {
+      th.alloc((size_t)N * 8);
+      tu.alloc((size_t)E * 8);
+      hip_check(hipMemcpy(th.p, h, (size_t)N * 8, hipMemcpyHostToDevice), "memcpy");
+      hip_check(hipMemcpy(tu.p, u, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
+      sh = th.as<double>();
+      su = tu.as<double>();
+    }
+    double* Hin = s->dbg_h.as<double>();
+    double* Uin = s->dbg_u.as<double>();
+    double* acc = s->dbg_out.as<double>();
+    launch_permute(Hin, sh, U.dm.cell_n2o.as<int>(), N, 0, 0, 1, s->stream);
+    launch_permute(Uin, su, U.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
+    const bool nl = s->P.nonlinear();
+    StageRanges R;
+    R.cell = {0, N};
+    R.vert = {0, nl ? V : 0};
+    R.prep = {0, E};
+    R.edge = {0, E};
+    R.cell_upd = {0, 0};
+    R.edge_upd = {0, 0};
+    Launch<CellSeg> c{};
+    c.nseg = 1;
+    CellSeg& cs = c.seg[0];
+    cs.m = U.dm.md;
+    cs.nm_log2 = 0;
+    cs.begin = 0;
+    cs.end = N;
+    cs.upd_begin = cs.upd_end = 0;
+    cs.acc_begin = 0;
+    cs.acc_end = which == 0 ? N : 0;
+    cs.acc_first = 1;
+    cs.Hsrc = Hin;
+    cs.Usrc = Uin;
+    cs.H0 = Hin;
+    cs.Hnew_src = Hin;
+    cs.Hdst = nullptr;
+    cs.hs = U.st.hs.as<double>();
+    cs.B = U.st.B.as<double>();
+    cs.acc = acc;
+    cs.c_dt = 0;
+    cs.wn = 0;
+    cs.ws = 1;
+    cs.wb = 0;
+    cs.acc_w = 1;
+    cs.g = s->P.p.g;
+    if (U.st.nm != 1) throw Err(FBLTS_EINVAL, "debug tendency needs a one-member solver");
+    launch_cell(c, nl, s->stream);
+    if (which == 1) {
+      if (nl) {
+        Launch<VertSeg> v{};
+        v.nseg = 1;
+        v.seg[0] = VertSeg{U.dm.md, 0, 0, V, Uin, U.st.hs.as<double>(), U.st.q.as<double>()};
+        launch_vertex(v, s->stream);
+      }
+      Launch<PrepSeg> pp{};
+      pp.nseg = 1;
+      pp.seg[0] = PrepSeg{U.dm.md, 0, 0, E, nl ? 0 : 1, Uin, U.st.hs.as<double>(),
+                          nl ? U.st.q.as<double>() : U.dm.md.v_q0, U.st.P.as<double>()};
+      launch_prep(pp, s->stream);
+      Launch<EdgeSeg> ee{};
+      ee.nseg = 1;
+      EdgeSeg& es = ee.seg[0];
+      es.m = U.dm.md;
+      es.nm_log2 = 0;
+      es.begin = 0;
+      es.end = E;
+      es.upd_begin = es.upd_end = 0;
+      es.acc_begin = 0;
+      es.acc_end = E;
+      es.acc_first = 1;
+      es.P = U.st.P.as<double>();
+      es.B = U.st.B.as<double>();
+      es.Usrc = Uin;
+      es.U0 = Uin;
+      es.Udst = nullptr;
+      es.acc = acc;
+      es.cd = s->drag_on ? U.st.cd.as<double>() : nullptr;
+      es.wind_n = U.st.has_wind ? U.st.wind_n.as<double>() : nullptr;
+      es.wind_t = U.st.has_wind ? U.st.wind_t.as<double>() : nullptr;
+      es.c_dt = 0;
+      es.acc_w = 1;
+      es.rho_ratio = s->P.p.rho_air / s->P.p.rho_water;
+      launch_edge(ee, s->drag_on, U.st.has_wind, s->stream);
+    }
+    const int n = which == 0 ? N : E;
+    const int* perm = which == 0 ? U.dm.cell_n2o.as<int>() : U.dm.edge_n2o.as<int>();
+    double* dst = out;
+    DevBuf to;
+    if (!on_device) {
+      to.alloc((size_t)n * 8);
+      dst = to.as<double>();
+    }
+    launch_permute(dst, acc, perm, n, 0, 0, 0, s->stream);
+    hip_check(hipGetLastError(), "kernel launch");
+    if (!on_device) hip_check(hipMemcpyAsync(out, dst, (size_t)n * 8, hipMemcpyDeviceToHost, s->stream), "memcpy");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    // the debug pass overwrote shared scratch: restore the stage invariants
+    s->drop_graph();
+    if (s->have_state) init_scratch(U, s->stream);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    return FBLTS_OK;
+  });
+}
+
+// ------------------------------------------------------------------ ensemble
+
+int fblts_ensemble_create(const fblts_mesh* const* meshes, const int8_t* const* cell_labels, int32_t binary,
+                          const int32_t* members_per_mesh, int32_t n_meshes, const fblts_params* params,
+                          void* hip_stream, fblts_ensemble** out) {
+  return guarded([&] {
+    if (!meshes || !members_per_mesh || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (n_meshes < 1 || n_meshes > kMaxSeg) throw Err(FBLTS_EINVAL, "n_meshes must be in 1..4");
+    check_params(params);
+    auto e = std::make_unique<fblts_ensemble>();
+    e->P.p = *params;
+    e->stream = make_stream(hip_stream, e->own_stream);
+    std::vector<MeshUnit*> units;
+    for (int k = 0; k < n_meshes; ++k) {
+      const int nm = members_per_mesh[k];
+      if (nm < 1 || nm > 64 || (nm & (nm - 1))) throw Err(FBLTS_EINVAL, "members per mesh must be a power of two <= 64");
+      if (!meshes[k]) throw Err(FBLTS_EINVAL, "mesh is NULL");
+      auto u = std::make_unique<MeshUnit>();
+      setup_unit(*u, meshes[k]->hm, e->P, cell_labels ? cell_labels[k] : nullptr, binary != 0, nm);
+      build_passes(*u, e->P, e->P.nonlinear());
+      units.push_back(u.get());
+      e->units.push_back(std::move(u));
+    }
+    e->passes = merge_passes(units);
+    // zero drag until set
+    for (auto& u : e->units) launch_fill(u->st.cd.as<double>(), 0.0, (long)u->pm.N * u->st.nm, e->stream);
+    hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    *out = e.release();
+    return FBLTS_OK;
+  });
+}
+
+void fblts_ensemble_destroy(fblts_ensemble* e) {
+  if (e && e->stream) (void)hipStreamSynchronize(e->stream);
+  delete e;
+}
+
+int fblts_ensemble_set_member(fblts_ensemble* e, int32_t mesh, int32_t member, const double* h, const double* u,
+                              const double* cd, int32_t on_device) {
+  return guarded([&] {
+    if (!e || mesh < 0 || mesh >= (int)e->units.size()) throw Err(FBLTS_EINVAL, "bad mesh index");
+    MeshUnit& U = *e->units[mesh];
+    if (member < 0 || member >= U.st.nm) throw Err(FBLTS_EINVAL, "bad member index");
+    if (!h || !u) throw Err(FBLTS_EINVAL, "NULL state");
+    if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    state_in(U, e->stage_h, e->stage_u, h, u, member, on_device != 0, e->stream);
+    if (cd) {
+      const double* src = cd;
+      DevBuf t;
+      if (!on_device) {
+        t.alloc((size_t)U.pm.N * 8);
+        hip_check(hipMemcpy(t.p, cd, (size_t)U.pm.N * 8, hipMemcpyHostToDevice), "memcpy");
+        src = t.as<double>();
+      }
+      launch_permute(U.st.cd.as<double>(), src, U.dm.cell_n2o.as<int>(), U.pm.N, U.st.nm_log2, member, 1, e->stream);
+      hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    }
+    init_scratch(U, e->stream);
+    hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    return FBLTS_OK;
+  });
+}
+
+int fblts_ensemble_get_member(fblts_ensemble* e, int32_t mesh, int32_t member, double* h, double* u,
+                              int32_t on_device) {
+  return guarded([&] {
+    if (!e || mesh < 0 || mesh >= (int)e->units.size()) throw Err(FBLTS_EINVAL, "bad mesh index");
+    MeshUnit& U = *e->units[mesh];
+    if (member < 0 || member >= U.st.nm) throw Err(FBLTS_EINVAL, "bad member index");
+    state_out(U, e->stage_h, e->stage_u, h, u, member, on_device != 0, e->stream);
+    return FBLTS_OK;
+  });
+}
+
+int fblts_ensemble_set_graph(fblts_ensemble* e, int32_t enable) {
+  return guarded([&] {
+    if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
+    hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->gexec = nullptr;
+    e->graph = nullptr;
+    e->graph_valid = false;
+    e->graph_on = enable != 0;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_ensemble_set_launch(fblts_ensemble* e, int32_t block_size) {
+  return guarded([&] {
+    if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
+    if (block_size != 0 && block_size != kBlock) throw Err(FBLTS_EINVAL, "only the default block size is built");
+    return FBLTS_OK;
+  });
+}
+
+int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
+  return guarded([&] {
+    if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
+    if (n < 0) throw Err(FBLTS_EINVAL, "negative step count");
+    const bool nl = e->P.nonlinear();
+    if (e->graph_on) {
+      if (!e->graph_valid) {
+        hip_check(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+          run_passes(e->passes, nl, nl, false, e->stream, nullptr);
+        } catch (...) {
+          hipGraph_t g;
+          (void)hipStreamEndCapture(e->stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        hip_check(hipStreamEndCapture(e->stream, &e->graph), "hipStreamEndCapture");
+        hip_check(hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        e->graph_valid = true;
+      }
+      for (int k = 0; k < n; ++k) hip_check(hipGraphLaunch(e->gexec, e->stream), "hipGraphLaunch");
+    } else {
+      for (int k = 0; k < n; ++k) run_passes(e->passes, nl, nl, false, e->stream, nullptr);
+    }
+    e->step += n;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_ensemble_diagnostics(fblts_ensemble* e, fblts_diag* out) {
+  return guarded([&] {
+    if (!e || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    int rc = FBLTS_OK;
+    size_t k = 0;
+    for (auto& u : e->units) {
+      std::vector<double> q;
+      diag_of(*u, e->P, e->diag_partial, e->diag_out, e->stream, q);
+      for (int m = 0; m < u->st.nm; ++m, ++k) {
+        const int r = fill_diag(&q[(size_t)m * kDiagQ], e->step * e->P.p.dt, e->step, &out[k]);
+        if (r != FBLTS_OK) rc = r;
+      }
+    }
+    if (rc != FBLTS_OK) g_err = "a member holds non-finite values or h <= 0";
+    return rc;
+  });
+}
+
+int fblts_ensemble_info(fblts_ensemble* e, int64_t* member_cells, int64_t* cell_substeps, double* model_bytes) {
+  return guarded([&] {
+    if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
+    int64_t mc = 0, cs = 0;
+    for (auto& u : e->units) {
+      mc += (int64_t)u->pm.N * u->st.nm;
+      cs += u->cell_substeps;
+    }
+    double b = 0;
+    for (auto& p : e->passes) b += p.model_bytes;
+    if (member_cells) *member_cells = mc;
+    if (cell_substeps) *cell_substeps = cs;
+    if (model_bytes) *model_bytes = b;
+    return FBLTS_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+"""GPU parity: the HIP library against the FP64 oracle (runs on an MI355X).
+
+Tolerances (FP64, different rounding order only):
+  * single tendency evaluations: max |gpu - oracle| <= 1e-13 * max |oracle|;
+  * trajectories after 100 coarse steps: relative L2 <= 1e-10 per field;
+  * conserved totals over 100 steps: mass <= 1e-13 relative, absolute
+    vorticity <= 1e-13 of sum |eta| A_v (Theorems 1 and 2);
+  * integer work (region labels) and library-internal reductions (M = 1 vs
+    FB-RK(3,2), graph vs direct launches, repeated runs, ensemble member vs
+    single solver): bitwise.
+"""
+import numpy as np
+import pytest
+
+import paper_2405_10505_amd as F
+from oracle import regions, schemes, trisk
+from paper_2405_10505_amd.inputs import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = workloads.config1()
+    om = trisk.OMesh(w.mesh)
+    lab, _ = regions.layer(om, w.fine_mask, 2)
+    return w, om, lab, F.Mesh(w.mesh)
+
+
+@pytest.fixture(scope="module")
+def cvt():
+    w = workloads.small_cvt()
+    om = trisk.OMesh(w.mesh)
+    lab, _ = regions.layer(om, w.fine_mask, 2)
+    return w, om, lab, F.Mesh(w.mesh)
+
+
+def _solver(fm, w, scheme=F.SCHEME_FBLTS, M=None, dt=None, lab=None, graph=False, drag=True):
+    s = F.Solver(fm, dt if dt is not None else w.dt, M=M or w.M, scheme=scheme, linear=w.linear)
+    if lab is None:
+        lab = np.where(w.fine_mask, 0, 1)
+        s.set_regions(lab, binary=True)
+    else:
+        s.set_regions(lab, binary=False)
+    if drag and w.cd is not None and not w.linear:
+        s.set_drag(w.cd)
+    s.set_state(w.h0, w.u0)
+    if graph:
+        s.set_graph(True)
+    return s
+
+
+def _phys(w, drag=True):
+    return trisk.Physics(linear=w.linear, cd=w.cd if (drag and not w.linear) else None)
+
+
+@pytest.mark.parametrize("name", ["c1", "cvt"])
+def test_tendencies_match_oracle(name, request):
+    w, om, lab, fm = request.getfixturevalue(name)
+    s = _solver(fm, w, scheme=F.SCHEME_FBRK32, M=1)
+    r = np.random.default_rng(3)
+    u = 0.5 * r.normal(size=om.E)
+    h = om.H + 2.0 * r.normal(size=om.N)
+    ph = _phys(w)
+    gp = s.tendency(0, h, u)
+    gf = s.tendency(1, h, u)
+    assert rel_max(gp, trisk.psi(om, u, h, ph)) <= 1e-13
+    assert rel_max(gf, trisk.phi(om, u, h, ph)) <= 1e-13
+
+
+def test_region_labels_bitwise(cvt):
+    w, om, lab, fm = cvt
+    got, _ = fm.layer_regions(np.where(w.fine_mask, 0, 1), binary=True, r=2)
+    assert np.array_equal(got, lab)
+
+
+@pytest.mark.parametrize("name,M,steps", [("c1", 2, 100), ("c1", 4, 100), ("cvt", 4, 100), ("cvt", 2, 60)])
+def test_fblts_trajectory_and_conservation(name, M, steps, request):
+    w, om, lab, fm = request.getfixturevalue(name)
+    dt = w.dt * M / w.M
+    s = _solver(fm, w, M=M, dt=dt)
+    d0 = s.diagnostics()
+    s.step(steps)
+    hg, ug = s.get_state()
+    d1 = s.diagnostics()
+    ph = _phys(w)
+    u, h = w.u0.copy(), w.h0.copy()
+    for _ in range(steps):
+        u, h = schemes.fblts_step(om, u, h, dt, M, ph, lab)
+    assert rel_l2(hg - om.H, h - om.H) <= 1e-10
+    assert rel_l2(ug, u) <= 1e-10
+    assert abs(d1["mass"] - d0["mass"]) <= 1e-13 * abs(d0["mass"])
+    assert abs(d1["abs_vorticity"] - d0["abs_vorticity"]) <= 1e-13 * d1["abs_vorticity_scale"]
+    od = trisk.diagnostics(om, u, h, ph)
+    assert abs(d1["mass"] - od["mass"]) <= 1e-13 * abs(od["mass"])
+    assert abs(d1["energy"] - od["energy"]) <= 1e-10 * abs(od["energy"])
+
+
+@pytest.mark.parametrize("scheme", [F.SCHEME_FBRK32, F.SCHEME_RK4])
+@pytest.mark.parametrize("name", ["c1", "cvt"])
+def test_global_schemes_match_oracle(scheme, name, request):
+    w, om, lab, fm = request.getfixturevalue(name)
+    dt = w.dt / w.M
+    s = _solver(fm, w, scheme=scheme, M=1, dt=dt)
+    s.step(50)
+    hg, ug = s.get_state()
+    ph = _phys(w)
+    u, h = w.u0.copy(), w.h0.copy()
+    step = schemes.fbrk32_step if scheme == F.SCHEME_FBRK32 else schemes.rk4_step
+    for _ in range(50):
+        u, h = step(om, u, h, dt, ph)
+    assert rel_l2(hg - om.H, h - om.H) <= 1e-10
+    assert rel_l2(ug, u) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["c1", "cvt"])
+def test_m1_all_coarse_all_fine_bitwise_on_gpu(name, request):
+    """Section 2.2: M = 1 is FB-RK(3,2); no fine cells: FB-RK(dt); all fine: M steps of FB-RK(dt/M)."""
+    w, om, lab, fm = request.getfixturevalue(name)
+    dt = w.dt / w.M
+    ref = _solver(fm, w, scheme=F.SCHEME_FBRK32, M=1, dt=dt)
+    ref.step(5)
+    hr, ur = ref.get_state()
+    m1 = _solver(fm, w, M=1, dt=dt, lab=lab)
+    m1.step(5)
+    h1, u1 = m1.get_state()
+    assert np.array_equal(h1, hr) and np.array_equal(u1, ur)
+    allc = _solver(fm, w, M=3, dt=dt, lab=np.full(om.N, 3, np.int8))
+    allc.step(5)
+    h2, u2 = allc.get_state()
+    assert np.array_equal(h2, hr) and np.array_equal(u2, ur)
+    allf = _solver(fm, w, M=3, dt=3 * dt, lab=np.zeros(om.N, np.int8))
+    allf.step(5)
+    ref3 = _solver(fm, w, scheme=F.SCHEME_FBRK32, M=1, dt=3 * dt / 3)
+    ref3.step(15)
+    h3, u3 = allf.get_state()
+    hr3, ur3 = ref3.get_state()
+    assert np.array_equal(h3, hr3) and np.array_equal(u3, ur3)
+
+
+@pytest.mark.parametrize("name", ["c1", "cvt"])
+def test_graph_replay_and_determinism_bitwise(name, request):
+    w, om, lab, fm = request.getfixturevalue(name)
+    a = _solver(fm, w)
+    b = _solver(fm, w, graph=True)
+    c = _solver(fm, w)
+    for _ in range(4):
+        a.step(3)
+        b.step(3)
+        c.step(3)
+        ha, ua = a.get_state()
+        hb, ub = b.get_state()
+        hc, uc = c.get_state()
+        assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+        assert np.array_equal(ha, hc) and np.array_equal(ua, uc)
+
+
+def test_device_tensors_roundtrip(cvt):
+    torch = pytest.importorskip("torch")
+    w, om, lab, fm = cvt
+    s = _solver(fm, w)
+    ht = torch.tensor(w.h0, device="cuda", dtype=torch.float64)
+    ut = torch.tensor(w.u0 + 0.01, device="cuda", dtype=torch.float64)
+    s.set_state(ht, ut)
+    ho = torch.empty_like(ht)
+    uo = torch.empty_like(ut)
+    s.get_state(ho, uo)
+    assert torch.equal(ho, ht) and torch.equal(uo, ut)
+    s.step(2)
+    s.get_state(ho, uo)
+    hn, un = s.get_state()
+    assert np.array_equal(ho.cpu().numpy(), hn) and np.array_equal(uo.cpu().numpy(), un)
+
+
+def test_nonfinite_reported(cvt):
+    w, om, lab, fm = cvt
+    s = _solver(fm, w)
+    h = w.h0.copy()
+    h[7] = np.nan
+    s.set_state(h, w.u0)
+    with pytest.raises(F.FBLTSError) as e:
+        s.diagnostics()
+    assert e.value.code == F.FBLTS_ENONFINITE
