@@ -170,6 +170,16 @@ int fblts_step(fblts_solver* s, int32_t n_coarse_steps);
  * launch kernels directly (0).  The graph is rebuilt after set_regions. */
 int fblts_set_graph(fblts_solver* s, int32_t enable);
 
+/* Tuning options (same results bit for bit, different launch structure);
+ * each drops any captured graph:
+ *   FBLTS_OPT_FUSE_VERTEX: 1 (default) evaluates the vertex PV q_v inside the
+ *     per-edge prep pass, one launch fewer per stage; 0 runs a vertex pass.
+ *   FBLTS_OPT_BLOCK: threads per block of the stencil passes, 64/128/256
+ *     (default 256).
+ * Errors: FBLTS_EINVAL for an unknown option or value. */
+enum { FBLTS_OPT_FUSE_VERTEX = 1, FBLTS_OPT_BLOCK = 2 };
+int fblts_set_option(fblts_solver* s, int32_t option, int32_t value);
+
 typedef struct {
   double mass;              /* sum_i A_i h_i */
   double abs_vorticity;     /* sum_v A_v (zeta_v + f_v) */
@@ -210,6 +220,11 @@ int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const 
  * Requires fblts_set_timing(s,1) before the step; synchronises. */
 int fblts_set_timing(fblts_solver* s, int32_t enable);
 int fblts_kernel_time(fblts_solver* s, int32_t kernel_class, double* avg_ms, int64_t* launches);
+/* Timing export: launch every pass of one class of the current step program
+ * `repeats` times back to back between two events and return the mean
+ * duration per launch (ms).  The passes overwrite state and scratch: use a
+ * solver whose state is disposable.  Synchronises. */
+int fblts_time_kernels(fblts_solver* s, int32_t kernel_class, int32_t repeats, double* avg_ms, int64_t* launches);
 
 /* ----------------------------------------------------------- ensemble --- */
 
@@ -231,9 +246,8 @@ int fblts_ensemble_get_member(fblts_ensemble* e, int32_t mesh, int32_t member, d
                               double* u, int32_t on_device);
 int fblts_ensemble_step(fblts_ensemble* e, int32_t n_coarse_steps);
 int fblts_ensemble_set_graph(fblts_ensemble* e, int32_t enable);
-/* Launch shape: members handled per thread block row and block size; the
- * autotuner searches these (0 = default). */
-int fblts_ensemble_set_launch(fblts_ensemble* e, int32_t block_size);
+/* Tuning option of the ensemble's passes (see fblts_set_option). */
+int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value);
 /* out[total members] in mesh-major, member-minor order; synchronises. */
 int fblts_ensemble_diagnostics(fblts_ensemble* e, fblts_diag* out);
 int fblts_ensemble_info(fblts_ensemble* e, int64_t* member_cells, int64_t* cell_substeps_per_step,

@@ -19,6 +19,7 @@ FBLTS_OK, FBLTS_EINVAL, FBLTS_ENOMEM, FBLTS_EDEVICE, FBLTS_EREGION, FBLTS_ESTATE
 SCHEME_FBLTS, SCHEME_FBRK32, SCHEME_RK4 = 0, 1, 2
 PHYS_LINEAR, PHYS_NONLINEAR = 0, 1
 BETA = (0.531, 0.531, 0.313)
+OPT_FUSE_VERTEX, OPT_BLOCK = 1, 2
 
 _P_i32 = C.POINTER(C.c_int32)
 _P_f64 = C.POINTER(C.c_double)
@@ -83,6 +84,8 @@ _SIGS = {
     "fblts_debug_tendency": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "fblts_time_kernels": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int64)]),
     "fblts_ensemble_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.POINTER(C.c_int8)), C.c_int32, _P_i32,
                                         C.c_int32, C.POINTER(fblts_params), C.c_void_p, C.POINTER(C.c_void_p)]),
     "fblts_ensemble_destroy": (None, [C.c_void_p]),
@@ -91,7 +94,8 @@ _SIGS = {
     "fblts_ensemble_get_member": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_ensemble_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_ensemble_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
-    "fblts_ensemble_set_launch": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fblts_ensemble_set_option": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "fblts_set_option": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "fblts_ensemble_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
     "fblts_ensemble_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double)]),
@@ -242,6 +246,9 @@ class Solver:
     def set_graph(self, on=True):
         _check(lib().fblts_set_graph(self.handle, int(on)))
 
+    def set_option(self, option, value):
+        _check(lib().fblts_set_option(self.handle, int(option), int(value)))
+
     def diagnostics(self, allow_nonfinite=False):
         d = fblts_diag()
         rc = lib().fblts_diagnostics(self.handle, C.byref(d))
@@ -266,6 +273,13 @@ class Solver:
 
     def set_timing(self, on=True):
         _check(lib().fblts_set_timing(self.handle, int(on)))
+
+    def time_kernels(self, cls, repeats=20):
+        """Mean duration (ms) per launch of one pass class replayed back to back (disposable state)."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().fblts_time_kernels(self.handle, int(cls), int(repeats), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def kernel_time(self, cls):
         ms = C.c_double()
@@ -315,6 +329,9 @@ class Ensemble:
 
     def set_graph(self, on=True):
         _check(lib().fblts_ensemble_set_graph(self.handle, int(on)))
+
+    def set_option(self, option, value):
+        _check(lib().fblts_ensemble_set_option(self.handle, int(option), int(value)))
 
     def diagnostics(self):
         tot = sum(self.members)

@@ -12,6 +12,10 @@ namespace fblts {
 
 constexpr int kMaxSeg = 4;       // meshes (segments) one launch can cover
 constexpr int kBlock = 256;      // threads per block for the stencil passes
+// Gather loops issue the first slots' loads together (no loop-carried
+// address dependence): cells unroll 6 edge slots, edges 10 edges_on_edge slots.
+constexpr int kUnrollCell = 6;
+constexpr int kUnrollEOE = 10;
 
 // Permuted mesh, device pointers.  Edge codes carry a sign bit:
 // code = 2*e + (sign < 0 ? 1 : 0).

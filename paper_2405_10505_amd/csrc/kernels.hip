@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   const int s = find_seg(L, b);
   const CellSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
   const int i = (int)(item >> nm_log2);
   if (i >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -59,24 +59,48 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   const double h_i = S.Hsrc[(long)i * nm + mem];
   double flux = 0.0, ke = 0.0;
   const int ne = m.c_nedge[i];
-  for (int j = 0; j < ne; ++j) {
-    const int code = m.c_edge[j * m.cs + i];
-    const int e = code >> 1;
-    const double ue = S.Usrc[(long)e * nm + mem];
-    const double dv = m.e_dv[e];
-    if (NONLINEAR) ke = fma(dv * m.e_dc[e], ue * ue, ke);
-    if (need_psi) {
-      double he;
-      if (NONLINEAR) {
-        const int nb = m.c_nbr[j * m.cs + i];
-        he = 0.5 * (h_i + S.Hsrc[(long)nb * nm + mem]);
-      } else {
-        he = m.e_He[e];
-      }
-      const double f = dv * (he * ue);
-      flux = (code & 1) ? flux - f : flux + f;
+  // Phase 1: the first kUnrollCell slots exist for every cell (padded lists),
+  // so all their index loads issue together; phase 2 issues every value
+  // gather; phase 3 accumulates with padded slots masked out.  The flux is
+  // formed for every cell (it is only used where Psi is needed) so that no
+  // branch separates the loads.
+  int code[kUnrollCell], nb[kUnrollCell];
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j) {
+    code[j] = m.c_edge[j * m.cs + i];
+    nb[j] = m.c_nbr[j * m.cs + i];
+  }
+  double ue[kUnrollCell], dv[kUnrollCell], dc[kUnrollCell], hx[kUnrollCell];
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j) {
+    const int e = code[j] >> 1;
+    ue[j] = S.Usrc[(long)e * nm + mem];
+    dv[j] = m.e_dv[e];
+    if (NONLINEAR) {
+      dc[j] = m.e_dc[e];
+      hx[j] = S.Hsrc[(long)nb[j] * nm + mem];
+    } else {
+      hx[j] = m.e_He[e];
     }
   }
+  // one slot: flux term n_{e,i} l_e h_e u_e, kinetic-energy term l_e d_e u_e^2
+  auto acc_slot = [&](int c, double u, double l, double d, double hnb, bool valid) {
+    const double he = NONLINEAR ? 0.5 * (h_i + hnb) : hnb;
+    double f = l * (he * u);
+    f = (c & 1) ? -f : f;
+    flux += valid ? f : 0.0;
+    if (NONLINEAR) ke += valid ? l * d * (u * u) : 0.0;
+  };
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j) acc_slot(code[j], ue[j], dv[j], dc[j], hx[j], j < ne);
+  for (int j = kUnrollCell; j < ne; ++j) {
+    const int c = m.c_edge[j * m.cs + i];
+    const int e = c >> 1;
+    const double u = S.Usrc[(long)e * nm + mem];
+    const double hnb = NONLINEAR ? S.Hsrc[(long)m.c_nbr[j * m.cs + i] * nm + mem] : m.e_He[e];
+    acc_slot(c, u, m.e_dv[e], NONLINEAR ? m.e_dc[e] : 0.0, hnb, true);
+  }
+  (void)need_psi;
   const long ii = (long)i * nm + mem;
   const double psi = -flux * m.c_invA[i];
   double hnew;
@@ -98,37 +122,53 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
 }
 
 // -------------------------------------------------------------- vertex pass
+// q_v = (zeta_v + f_v) / h_v with zeta_v = (1/A_v) sum s_{e,v} d_e u_e and
+// h_v = (1/A_v) sum kite_{i,v} h*_i.  Shared by the vertex pass and the fused
+// prep pass, so both produce the same bits.
+__device__ __forceinline__ double vertex_q(const MeshDev& m, int v, const double* __restrict__ Usrc,
+                                           const double* __restrict__ hs, int nm, int mem) {
+  int code[3], cell[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    code[j] = m.v_edge[j * m.vs + v];
+    cell[j] = m.v_cell[j * m.vs + v];
+  }
+  double circ = 0.0, hv = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int e = code[j] >> 1;
+    const double c = m.e_dc[e] * Usrc[(long)e * nm + mem];
+    circ = (code[j] & 1) ? circ - c : circ + c;
+    hv = fma(m.v_kite[j * m.vs + v], hs[(long)cell[j] * nm + mem], hv);
+  }
+  const double ia = m.v_invA[v];
+  return (circ * ia + m.v_f[v]) / (hv * ia);
+}
+
 __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg(L, b);
   const VertSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
   const int v = (int)(item >> nm_log2);
   if (v >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
   const int nm = 1 << nm_log2;
-  const MeshDev& m = S.m;
-  double circ = 0.0, hv = 0.0;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int code = m.v_edge[j * m.vs + v];
-    const int e = code >> 1;
-    const double c = m.e_dc[e] * S.Usrc[(long)e * nm + mem];
-    circ = (code & 1) ? circ - c : circ + c;
-    hv = fma(m.v_kite[j * m.vs + v], S.hs[(long)m.v_cell[j * m.vs + v] * nm + mem], hv);
-  }
-  const double ia = m.v_invA[v];
-  S.q[(long)v * nm + mem] = (circ * ia + m.v_f[v]) / (hv * ia);
+  S.q[(long)v * nm + mem] = vertex_q(S.m, v, S.Usrc, S.hs, nm, mem);
 }
 
 // ---------------------------------------------------------------- prep pass
+// FUSE_Q: evaluate q at the edge's two vertices here instead of reading the
+// vertex pass's output (one launch fewer per stage, each vertex evaluated by
+// its three edges).
+template <bool FUSE_Q>
 __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg(L, b);
   const PrepSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -144,7 +184,11 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
     qe = 0.5 * (S.q[v0] + S.q[v1]);
   } else {
     he = 0.5 * (S.hs[(long)c0 * nm + mem] + S.hs[(long)c1 * nm + mem]);
-    qe = 0.5 * (S.q[(long)v0 * nm + mem] + S.q[(long)v1 * nm + mem]);
+    if (FUSE_Q) {
+      qe = 0.5 * (vertex_q(m, v0, S.Usrc, S.hs, nm, mem) + vertex_q(m, v1, S.Usrc, S.hs, nm, mem));
+    } else {
+      qe = 0.5 * (S.q[(long)v0 * nm + mem] + S.q[(long)v1 * nm + mem]);
+    }
   }
   double4 p;
   p.x = dv * (he * u);
@@ -161,7 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int s = find_seg(L, b);
   const EdgeSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -172,13 +216,18 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const double4 pe = P[ee];
   double sq = 0.0, su = 0.0;
   const int n = m.e_neoe[e];
-  for (int j = 0; j < n; ++j) {
+  auto slot = [&](int j) {
     const int e2 = m.e_eoe[j * m.es + e];
     const double w = m.e_w[j * m.es + e];
     const double4 p2 = P[(long)e2 * nm + mem];
     sq = fma(w * p2.x, pe.y + p2.y, sq);
     if (DRAG || WIND) su = fma(w, p2.z, su);
-  }
+  };
+  // the first kUnrollEOE slots exist for every edge (padded with the edge
+  // itself at weight 0, an exact no-op): their loads issue together
+#pragma unroll
+  for (int j = 0; j < kUnrollEOE; ++j) slot(j);
+  for (int j = kUnrollEOE; j < n; ++j) slot(j);
   const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
   const double idc = m.e_invdc[e];
   double phi = 0.5 * sq * idc - (S.B[(long)c1 * nm + mem] - S.B[(long)c0 * nm + mem]) * idc;
@@ -212,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
   const int nm = 1 << nm_log2;
   const long nc = (long)(S.c_end - S.c_begin) * nm;
   const long ne = (long)(S.e_end - S.e_begin) * nm;
-  const long t = (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const long t = (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
   if (t < nc) {
     const long i = (long)S.c_begin * nm + t;
     double hn, h1, h2, h3;
@@ -250,7 +299,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
   const int nm = 1 << S.nm_log2;
   const long ncell = (long)(S.N - S.if1_c_begin) * nm;
   const long nedge = (long)(S.E - S.if1_e_begin) * nm;
-  const long t = (long)(b - L.blk_start[s]) * kBlock + threadIdx.x;
+  const long t = (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
   if (t < ncell) {
     const long i = (long)S.if1_c_begin * nm + t;
     const long c = i >> S.nm_log2;
@@ -404,11 +453,11 @@ __global__ void __launch_bounds__(kBlock) k_diag_final(const double* partial, in
 
 // ------------------------------------------------------------- host launchers
 template <class S>
-static int blocks_for(Launch<S>& L, long (*items)(const S&)) {
+static int blocks_for(Launch<S>& L, long (*items)(const S&), int bs) {
   int acc = 0;
   for (int s = 0; s < L.nseg; ++s) {
     L.blk_start[s] = acc;
-    acc += (int)((items(L.seg[s]) + kBlock - 1) / kBlock);
+    acc += (int)((items(L.seg[s]) + bs - 1) / bs);
   }
   for (int s = L.nseg; s <= kMaxSeg; ++s) L.blk_start[s] = acc;
   return acc;
@@ -426,47 +475,48 @@ static long asm_items(const AsmSeg& s) {
 }
 
 // Each launcher returns the number of blocks launched (0: nothing to do).
-int launch_cell(Launch<CellSeg> L, bool nonlinear, hipStream_t st) {
-  const int nb = blocks_for(L, cell_items);
+int launch_cell(Launch<CellSeg> L, bool nonlinear, int bs, hipStream_t st) {
+  const int nb = blocks_for(L, cell_items, bs);
   if (nb == 0) return 0;
-  if (nonlinear) hipLaunchKernelGGL(k_cell<true>, dim3(nb), dim3(kBlock), 0, st, L);
-  else hipLaunchKernelGGL(k_cell<false>, dim3(nb), dim3(kBlock), 0, st, L);
+  if (nonlinear) hipLaunchKernelGGL(k_cell<true>, dim3(nb), dim3(bs), 0, st, L);
+  else hipLaunchKernelGGL(k_cell<false>, dim3(nb), dim3(bs), 0, st, L);
   return nb;
 }
 
-int launch_vertex(Launch<VertSeg> L, hipStream_t st) {
-  const int nb = blocks_for(L, vert_items);
+int launch_vertex(Launch<VertSeg> L, int bs, hipStream_t st) {
+  const int nb = blocks_for(L, vert_items, bs);
   if (nb == 0) return 0;
-  hipLaunchKernelGGL(k_vertex, dim3(nb), dim3(kBlock), 0, st, L);
+  hipLaunchKernelGGL(k_vertex, dim3(nb), dim3(bs), 0, st, L);
   return nb;
 }
 
-int launch_prep(Launch<PrepSeg> L, hipStream_t st) {
-  const int nb = blocks_for(L, prep_items);
+int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st) {
+  const int nb = blocks_for(L, prep_items, bs);
   if (nb == 0) return 0;
-  hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kBlock), 0, st, L);
+  if (fuse_q) hipLaunchKernelGGL(k_prep<true>, dim3(nb), dim3(bs), 0, st, L);
+  else hipLaunchKernelGGL(k_prep<false>, dim3(nb), dim3(bs), 0, st, L);
   return nb;
 }
 
-int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, hipStream_t st) {
-  const int nb = blocks_for(L, edge_items);
+int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st) {
+  const int nb = blocks_for(L, edge_items, bs);
   if (nb == 0) return 0;
-  if (drag && wind) hipLaunchKernelGGL((k_edge<true, true>), dim3(nb), dim3(kBlock), 0, st, L);
-  else if (drag) hipLaunchKernelGGL((k_edge<true, false>), dim3(nb), dim3(kBlock), 0, st, L);
-  else if (wind) hipLaunchKernelGGL((k_edge<false, true>), dim3(nb), dim3(kBlock), 0, st, L);
-  else hipLaunchKernelGGL((k_edge<false, false>), dim3(nb), dim3(kBlock), 0, st, L);
+  if (drag && wind) hipLaunchKernelGGL((k_edge<true, true>), dim3(nb), dim3(bs), 0, st, L);
+  else if (drag) hipLaunchKernelGGL((k_edge<true, false>), dim3(nb), dim3(bs), 0, st, L);
+  else if (wind) hipLaunchKernelGGL((k_edge<false, true>), dim3(nb), dim3(bs), 0, st, L);
+  else hipLaunchKernelGGL((k_edge<false, false>), dim3(nb), dim3(bs), 0, st, L);
   return nb;
 }
 
 int launch_predict(Launch<PredSeg> L, hipStream_t st) {
-  const int nb = blocks_for(L, pred_items);
+  const int nb = blocks_for(L, pred_items, kBlock);
   if (nb == 0) return 0;
   hipLaunchKernelGGL(k_predict, dim3(nb), dim3(kBlock), 0, st, L);
   return nb;
 }
 
 int launch_assemble(Launch<AsmSeg> L, hipStream_t st) {
-  const int nb = blocks_for(L, asm_items);
+  const int nb = blocks_for(L, asm_items, kBlock);
   if (nb == 0) return 0;
   hipLaunchKernelGGL(k_assemble, dim3(nb), dim3(kBlock), 0, st, L);
   return nb;

@@ -1,6 +1,7 @@
 // Host-side mesh validation, region layering (paper Section 2.2), the
 // region-contiguous reordering and the dependency-closure pass ranges.
 #include "mesh_plan.h"
+#include "fblts_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -573,6 +574,10 @@ void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm) {
   int maxE = 0, maxEOE = 0;
   for (int i = 0; i < N; ++i) maxE = std::max(maxE, m.eoc_off[i + 1] - m.eoc_off[i]);
   for (int e = 0; e < E; ++e) maxEOE = std::max(maxEOE, m.eoe_off[e + 1] - m.eoe_off[e]);
+  // the gather kernels unroll the first kUnrollCell / kUnrollEOE slots with no
+  // bounds test: pad the lists to at least that width with harmless entries
+  maxE = std::max(maxE, kUnrollCell);
+  maxEOE = std::max(maxEOE, kUnrollEOE);
   pm.maxE = maxE;
   pm.maxEOE = maxEOE;
   pm.c_nedge.assign(N, 0);
@@ -585,6 +590,12 @@ void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm) {
     const int io = p.cell_new2old[in];
     const int b = m.eoc_off[io], n = m.eoc_off[io + 1] - b;
     pm.c_nedge[in] = n;
+    for (int j = n; j < maxE; ++j) {   // padding repeats slot 0; the kernel masks it out
+      const int eo = m.eoc[b];
+      const bool outward = m.coe[2 * eo] == io;
+      pm.c_edge[(size_t)j * pm.cs + in] = 2 * p.edge_old2new[eo] + (outward ? 0 : 1);
+      pm.c_nbr[(size_t)j * pm.cs + in] = p.cell_old2new[outward ? m.coe[2 * eo + 1] : m.coe[2 * eo]];
+    }
     for (int j = 0; j < n; ++j) {
       const int eo = m.eoc[b + j];
       const int en = p.edge_old2new[eo];
@@ -618,6 +629,10 @@ void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm) {
     pm.e_He[en] = 0.5 * (m.H[m.coe[2 * eo]] + m.H[m.coe[2 * eo + 1]]);
     const int b = m.eoe_off[eo], n = m.eoe_off[eo + 1] - b;
     pm.e_neoe[en] = n;
+    for (int j = n; j < maxEOE; ++j) {   // padding: the edge itself with weight 0
+      pm.e_eoe[(size_t)j * pm.es + en] = en;
+      pm.e_w[(size_t)j * pm.es + en] = 0.0;
+    }
     for (int j = 0; j < n; ++j) {
       pm.e_eoe[(size_t)j * pm.es + en] = p.edge_old2new[m.eoe[b + j]];
       pm.e_w[(size_t)j * pm.es + en] = m.woe[b + j];
@@ -710,18 +725,38 @@ double bytes_vert_pass(const PermMesh& pm, const Range& r, int nm) {
   return b;
 }
 
-double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm) {
+double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm, bool fuse_q) {
   const double S = 8.0 * nm;
   double b = 0;
-  Stamp sc(pm.N), sv(pm.V);
+  Stamp sc(pm.N), sv(pm.V), se(pm.E);
   sc.next();
   sv.next();
+  se.next();
   for (int e = r.b; e < r.e; ++e) {
     b += 8 + 8 + 8 + S + 4 * S;   // cells, vertices, l_e, u, P write
     if (!nonlinear) b += 8;       // H_e
+    if (fuse_q) se.mark(e);
     for (int j = 0; j < 2; ++j) {
-      if (nonlinear && sc.mark(pm.e_cell[(size_t)j * pm.es + e])) b += S;
-      if (sv.mark(pm.e_vert[(size_t)j * pm.es + e])) b += nonlinear ? S : 8;
+      const int c = pm.e_cell[(size_t)j * pm.es + e];
+      if (nonlinear && sc.mark(c)) b += S;
+      const int v = pm.e_vert[(size_t)j * pm.es + e];
+      if (sv.mark(v)) {
+        if (!nonlinear) {
+          b += 8;   // static q0
+        } else if (!fuse_q) {
+          b += S;   // q from the vertex pass
+        } else {
+          // the vertex's own data: codes, cells, kites, 1/A_v, f_v; and its
+          // edges' d_e, u and cells' h* when not already counted
+          b += 3 * (4 + 4 + 8) + 8 + 8;
+          for (int t = 0; t < 3; ++t) {
+            const int e2 = pm.v_edge[(size_t)t * pm.vs + v] >> 1;
+            if (se.mark(e2)) b += 8 + S;
+            else b += 8;                   // d_e of an edge in the range
+            if (sc.mark(pm.v_cell[(size_t)t * pm.vs + v])) b += S;
+          }
+        }
+      }
     }
   }
   return b;

@@ -76,7 +76,7 @@ void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm);
 // nm = members; state bytes scale with nm, mesh bytes do not.
 double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm);
 double bytes_vert_pass(const PermMesh& pm, const Range& r, int nm);
-double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm);
+double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm, bool fuse_q = false);
 double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm);
 
 }  // namespace fblts

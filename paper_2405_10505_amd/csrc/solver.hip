@@ -28,10 +28,10 @@
 #include "mesh_plan.h"
 
 namespace fblts {
-int launch_cell(Launch<CellSeg> L, bool nonlinear, hipStream_t st);
-int launch_vertex(Launch<VertSeg> L, hipStream_t st);
-int launch_prep(Launch<PrepSeg> L, hipStream_t st);
-int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, hipStream_t st);
+int launch_cell(Launch<CellSeg> L, bool nonlinear, int bs, hipStream_t st);
+int launch_vertex(Launch<VertSeg> L, int bs, hipStream_t st);
+int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st);
+int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st);
 int launch_predict(Launch<PredSeg> L, hipStream_t st);
 int launch_assemble(Launch<AsmSeg> L, hipStream_t st);
 void launch_axpy_final(double* y, const double* acc, double c, long n, hipStream_t st);
@@ -223,6 +223,8 @@ struct Pass {
   std::vector<std::tuple<double*, const double*, long>> fin;
   double fin_c = 0.0;
   double model_bytes = 0.0;
+  bool fuse_q = false;   // PREP: evaluate q_v in the prep pass (no vertex pass)
+  int bs = kBlock;       // threads per block of the stencil passes
 };
 
 struct MeshUnit {
@@ -256,7 +258,7 @@ void check_params(const fblts_params* p) {
 }
 
 // Build the pass list of one mesh unit (segments are merged by the caller).
-void build_passes(MeshUnit& u, const Params& P, bool drag_on) {
+void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) {
   const fblts_params& p = P.p;
   const bool nl = P.nonlinear();
   const MeshDev& md = u.dm.md;
@@ -303,7 +305,7 @@ void build_passes(MeshUnit& u, const Params& P, bool drag_on) {
     u.passes.push_back(ps);
   };
   auto vert_pass = [&](const StageRanges& r, const double* Usrc) {
-    if (!nl || r.vert.size() == 0) return;
+    if (!nl || fuse_q || r.vert.size() == 0) return;
     Pass ps;
     ps.kind = Pass::VERT;
     ps.vert.nseg = 1;
@@ -332,7 +334,8 @@ void build_passes(MeshUnit& u, const Params& P, bool drag_on) {
     q.hs = s.hs.as<double>();
     q.q = qsrc;
     q.P = s.P.as<double>();
-    ps.model_bytes = bytes_prep_pass(u.pm, r.prep, nl, nm);
+    ps.fuse_q = nl && fuse_q;
+    ps.model_bytes = bytes_prep_pass(u.pm, r.prep, nl, nm, ps.fuse_q);
     u.passes.push_back(ps);
   };
   auto edge_pass = [&](const StageRanges& r, const double* Usrc, const double* U0, double* Udst, double c_dt,
@@ -484,6 +487,11 @@ void build_passes(MeshUnit& u, const Params& P, bool drag_on) {
   u.cell_substeps = ((int64_t)(N - pl.nF) + (int64_t)M * pl.nF) * nm;
 }
 
+void build_passes(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, int bs) {
+  build_passes_impl(u, P, drag_on, fuse_q);
+  for (Pass& p : u.passes) p.bs = bs;
+}
+
 // Merge per-mesh pass lists into multi-segment launches.
 std::vector<Pass> merge_passes(const std::vector<MeshUnit*>& units) {
   std::vector<Pass> out;
@@ -556,10 +564,10 @@ void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool
       hip_check(hipEventRecord(evp.first, st), "hipEventRecord");
     }
     switch (ps.kind) {
-      case Pass::CELL: launch_cell(ps.cell, nonlinear, st); break;
-      case Pass::VERT: launch_vertex(ps.vert, st); break;
-      case Pass::PREP: launch_prep(ps.prep, st); break;
-      case Pass::EDGE: launch_edge(ps.edge, drag, wind, st); break;
+      case Pass::CELL: launch_cell(ps.cell, nonlinear, ps.bs, st); break;
+      case Pass::VERT: launch_vertex(ps.vert, ps.bs, st); break;
+      case Pass::PREP: launch_prep(ps.prep, ps.fuse_q, ps.bs, st); break;
+      case Pass::EDGE: launch_edge(ps.edge, drag, wind, ps.bs, st); break;
       case Pass::PRED: launch_predict(ps.pred, st); break;
       case Pass::ASM: launch_assemble(ps.asmb, st); break;
       case Pass::RK4FIN:
@@ -587,6 +595,8 @@ struct fblts_solver {
   int device = 0;
   std::unique_ptr<MeshUnit> unit;
   bool have_regions = false, have_state = false, drag_on = false;
+  bool fuse_q = true;
+  int block = kBlock;
   bool graph_on = false, graph_valid = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -611,6 +621,8 @@ struct fblts_solver {
 
 struct fblts_ensemble {
   Params P;
+  bool fuse_q = true;
+  int block = kBlock;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<std::unique_ptr<MeshUnit>> units;
@@ -796,7 +808,7 @@ int fblts_set_regions(fblts_solver* s, const int8_t* labels, int32_t binary) {
     setup_unit(*u, s->mesh->hm, s->P, labels, binary != 0, 1);
     s->unit = std::move(u);
     s->drag_on = false;
-    build_passes(*s->unit, s->P, s->drag_on);
+    build_passes(*s->unit, s->P, s->drag_on, s->fuse_q, s->block);
     s->have_regions = true;
     return FBLTS_OK;
   });
@@ -848,7 +860,7 @@ int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device) {
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
       s->drag_on = true;
     }
-    build_passes(u, s->P, s->drag_on);
+    build_passes(u, s->P, s->drag_on, s->fuse_q, s->block);
     return FBLTS_OK;
   });
 }
@@ -886,7 +898,25 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
       u.st.has_wind = true;
     }
-    build_passes(u, s->P, s->drag_on);
+    build_passes(u, s->P, s->drag_on, s->fuse_q, s->block);
+    return FBLTS_OK;
+  });
+}
+
+int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->drop_graph();
+    if (option == FBLTS_OPT_FUSE_VERTEX) {
+      s->fuse_q = value != 0;
+    } else if (option == FBLTS_OPT_BLOCK) {
+      if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
+      s->block = value;
+    } else {
+      throw Err(FBLTS_EINVAL, "unknown option");
+    }
+    if (s->have_regions) build_passes(*s->unit, s->P, s->drag_on, s->fuse_q, s->block);
     return FBLTS_OK;
   });
 }
@@ -1006,6 +1036,39 @@ int fblts_kernel_time(fblts_solver* s, int32_t cls, double* avg_ms, int64_t* lau
   });
 }
 
+int fblts_time_kernels(fblts_solver* s, int32_t cls, int32_t repeats, double* avg_ms, int64_t* launches) {
+  return guarded([&] {
+    if (!s || !avg_ms || cls < 0 || cls > 3 || repeats < 1) throw Err(FBLTS_EINVAL, "bad argument");
+    if (!s->have_state) throw Err(FBLTS_ESTATE, "set_state must come first");
+    MeshUnit& u = *s->unit;
+    const Pass::Kind kinds[4] = {Pass::EDGE, Pass::CELL, Pass::VERT, Pass::PREP};
+    std::vector<Pass> sel;
+    for (const Pass& p : u.passes)
+      if (p.kind == kinds[cls]) sel.push_back(p);
+    if (launches) *launches = (int64_t)sel.size() * repeats;
+    *avg_ms = 0.0;
+    if (sel.empty()) return FBLTS_OK;
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "hipEventCreate");
+    hip_check(hipEventCreate(&b), "hipEventCreate");
+    std::vector<Pass> one(1);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    hip_check(hipEventRecord(a, s->stream), "hipEventRecord");
+    for (const Pass& p : sel) {
+      one[0] = p;
+      for (int r = 0; r < repeats; ++r) run_passes(one, s->P.nonlinear(), s->drag_on, u.st.has_wind, s->stream, nullptr);
+    }
+    hip_check(hipEventRecord(b, s->stream), "hipEventRecord");
+    hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+    float ms = 0;
+    hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *avg_ms = ms / ((double)sel.size() * repeats);
+    return FBLTS_OK;
+  });
+}
+
 int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const double* u, double* out,
                          int32_t on_device) {
   return guarded([&] {
@@ -1070,19 +1133,19 @@ int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const 
     cs.acc_w = 1;
     cs.g = s->P.p.g;
     if (U.st.nm != 1) throw Err(FBLTS_EINVAL, "debug tendency needs a one-member solver");
-    launch_cell(c, nl, s->stream);
+    launch_cell(c, nl, kBlock, s->stream);
     if (which == 1) {
       if (nl) {
         Launch<VertSeg> v{};
         v.nseg = 1;
         v.seg[0] = VertSeg{U.dm.md, 0, 0, V, Uin, U.st.hs.as<double>(), U.st.q.as<double>()};
-        launch_vertex(v, s->stream);
+        launch_vertex(v, kBlock, s->stream);
       }
       Launch<PrepSeg> pp{};
       pp.nseg = 1;
       pp.seg[0] = PrepSeg{U.dm.md, 0, 0, E, nl ? 0 : 1, Uin, U.st.hs.as<double>(),
                           nl ? U.st.q.as<double>() : U.dm.md.v_q0, U.st.P.as<double>()};
-      launch_prep(pp, s->stream);
+      launch_prep(pp, false, kBlock, s->stream);
       Launch<EdgeSeg> ee{};
       ee.nseg = 1;
       EdgeSeg& es = ee.seg[0];
@@ -1106,7 +1169,7 @@ int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const 
       es.c_dt = 0;
       es.acc_w = 1;
       es.rho_ratio = s->P.p.rho_air / s->P.p.rho_water;
-      launch_edge(ee, s->drag_on, U.st.has_wind, s->stream);
+      launch_edge(ee, s->drag_on, U.st.has_wind, kBlock, s->stream);
     }
     const int n = which == 0 ? N : E;
     const int* perm = which == 0 ? U.dm.cell_n2o.as<int>() : U.dm.edge_n2o.as<int>();
@@ -1147,7 +1210,7 @@ int fblts_ensemble_create(const fblts_mesh* const* meshes, const int8_t* const* 
       if (!meshes[k]) throw Err(FBLTS_EINVAL, "mesh is NULL");
       auto u = std::make_unique<MeshUnit>();
       setup_unit(*u, meshes[k]->hm, e->P, cell_labels ? cell_labels[k] : nullptr, binary != 0, nm);
-      build_passes(*u, e->P, e->P.nonlinear());
+      build_passes(*u, e->P, e->P.nonlinear(), e->fuse_q, e->block);
       units.push_back(u.get());
       e->units.push_back(std::move(u));
     }
@@ -1216,10 +1279,29 @@ int fblts_ensemble_set_graph(fblts_ensemble* e, int32_t enable) {
   });
 }
 
-int fblts_ensemble_set_launch(fblts_ensemble* e, int32_t block_size) {
+int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) {
   return guarded([&] {
     if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
-    if (block_size != 0 && block_size != kBlock) throw Err(FBLTS_EINVAL, "only the default block size is built");
+    hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    if (option == FBLTS_OPT_FUSE_VERTEX) {
+      e->fuse_q = value != 0;
+    } else if (option == FBLTS_OPT_BLOCK) {
+      if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
+      e->block = value;
+    } else {
+      throw Err(FBLTS_EINVAL, "unknown option");
+    }
+    std::vector<MeshUnit*> units;
+    for (auto& u : e->units) {
+      build_passes(*u, e->P, e->P.nonlinear(), e->fuse_q, e->block);
+      units.push_back(u.get());
+    }
+    e->passes = merge_passes(units);
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->gexec = nullptr;
+    e->graph = nullptr;
+    e->graph_valid = false;
     return FBLTS_OK;
   });
 }

@@ -189,3 +189,34 @@ def test_nonfinite_reported(cvt):
     with pytest.raises(F.FBLTSError) as e:
         s.diagnostics()
     assert e.value.code == F.FBLTS_ENONFINITE
+
+
+@pytest.mark.parametrize("fuse,bs", [(0, 256), (1, 64), (0, 128), (1, 128)])
+@pytest.mark.parametrize("name", ["c1", "cvt"])
+def test_launch_options_bitwise(name, fuse, bs, request):
+    """Tuning options change the launch structure only: results are bitwise equal."""
+    w, om, lab, fm = request.getfixturevalue(name)
+    ref = _solver(fm, w)
+    ref.step(4)
+    s = _solver(fm, w)
+    s.set_option(F.OPT_FUSE_VERTEX, fuse)
+    s.set_option(F.OPT_BLOCK, bs)
+    s.step(4)
+    hr, ur = ref.get_state()
+    hs, us = s.get_state()
+    assert np.array_equal(hr, hs) and np.array_equal(ur, us)
+
+
+def test_autotuner_restores_state_and_picks_a_candidate(cvt, tmp_path):
+    from paper_2405_10505_amd import autotune
+    w, om, lab, fm = cvt
+    s = _solver(fm, w)
+    s.step(3)
+    h0, u0 = s.get_state()
+    choice = autotune.autotune(s, steps=5, repeats=1, cache_path=str(tmp_path / "tune.json"))
+    assert (choice["fuse_vertex"], choice["block"]) in autotune.CANDIDATES
+    h1, u1 = s.get_state()
+    assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
+    # cached: a second call returns the same choice without timing
+    again = autotune.autotune(s, cache_path=str(tmp_path / "tune.json"))
+    assert (again["fuse_vertex"], again["block"]) == (choice["fuse_vertex"], choice["block"])
