@@ -226,6 +226,36 @@ int fblts_kernel_time(fblts_solver* s, int32_t kernel_class, double* avg_ms, int
  * solver whose state is disposable.  Synchronises. */
 int fblts_time_kernels(fblts_solver* s, int32_t kernel_class, int32_t repeats, double* avg_ms, int64_t* launches);
 
+/* ------------------------------------------------------------ adjoint --- */
+
+/* Reverse mode of the FB-LTS step (Sec. 2.2) for one-member nonlinear or
+ * linear solvers without wind stress.
+ *
+ * fblts_adjoint_forward: advance n_steps coarse steps from the current state
+ * (as fblts_step does), keeping a checkpoint of (h, u) every ckpt_every steps
+ * on the device (n_steps/ckpt_every states).  Synchronises.
+ *
+ * fblts_adjoint_backward: given the cotangent of the final state (gh_final
+ * [n_cells], gu_final [n_edges], caller numbering), return the gradient with
+ * respect to the initial state (gh0, gu0) and to the per-cell drag
+ * coefficient C_D (gcd [n_cells]); any output may be NULL.  Each segment of
+ * ckpt_every steps is recomputed from its checkpoint in definition mode (the
+ * coarse advancement over every cell and edge), taped, and swept backwards
+ * with gather-only transposed kernels (deterministic, no atomics).  The
+ * solver is left at the final state.  Device memory: about
+ * ckpt_every * ((4+4M) n_cells + (4+3M) n_edges) doubles of tape.
+ * Errors: FBLTS_ESTATE without a preceding forward, FBLTS_EINVAL for other
+ * schemes or when wind stress is set.  Synchronises. */
+int fblts_adjoint_forward(fblts_solver* s, int32_t n_steps, int32_t ckpt_every);
+int fblts_adjoint_backward(fblts_solver* s, const double* gh_final, const double* gu_final, double* gh0,
+                           double* gu0, double* gcd, int32_t on_device);
+/* Test export: transposed tendency at the point (h, u) (host arrays, caller
+ * numbering).  which = 0: cot[n_cells] is a cotangent of Psi(u, h);
+ * which = 1: cot[n_edges] of Phi(u, h) (h taken as the FB-averaged thickness).
+ * Writes hbar[n_cells], ubar[n_edges] and, for Phi with drag, cdbar[n_cells]. */
+int fblts_debug_vjp(fblts_solver* s, int32_t which, const double* h, const double* u, const double* cot,
+                    double* hbar, double* ubar, double* cdbar);
+
 /* ----------------------------------------------------------- ensemble --- */
 
 /* A batch of independent FB-LTS members over one or more meshes, advanced by

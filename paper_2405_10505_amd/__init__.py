@@ -86,6 +86,11 @@ _SIGS = {
     "fblts_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fblts_time_kernels": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]),
+    "fblts_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "fblts_adjoint_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_int32]),
+    "fblts_debug_vjp": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p]),
     "fblts_ensemble_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.POINTER(C.c_int8)), C.c_int32, _P_i32,
                                         C.c_int32, C.POINTER(fblts_params), C.c_void_p, C.POINTER(C.c_void_p)]),
     "fblts_ensemble_destroy": (None, [C.c_void_p]),
@@ -271,6 +276,38 @@ class Solver:
         _check(lib().fblts_debug_tendency(self.handle, int(which), ph, pu, out.ctypes.data_as(C.c_void_p), 0))
         return out
 
+    def vjp(self, which, h, u, cot):
+        """Transposed tendency at (h, u): returns (hbar, ubar, cdbar)."""
+        hb = np.empty(self.mesh.n_cells)
+        ub = np.empty(self.mesh.n_edges)
+        cb = np.empty(self.mesh.n_cells)
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (h, u, cot)]
+        _check(lib().fblts_debug_vjp(self.handle, int(which), *[x.ctypes.data_as(C.c_void_p) for x in a],
+                                     hb.ctypes.data_as(C.c_void_p), ub.ctypes.data_as(C.c_void_p),
+                                     cb.ctypes.data_as(C.c_void_p)))
+        return hb, ub, cb
+
+    def adjoint_forward(self, n_steps, ckpt_every):
+        _check(lib().fblts_adjoint_forward(self.handle, int(n_steps), int(ckpt_every)))
+
+    def adjoint_backward(self, gh_final, gu_final, out=None):
+        """Gradients (gh0, gu0, gcd) from the final-state cotangent.
+
+        Host (numpy) seeds give numpy results; CUDA tensors give tensors."""
+        ph, dh, kh = _ptr(gh_final, np.float64)
+        pu, du, ku = _ptr(gu_final, np.float64)
+        if dh:
+            import torch
+            gh0 = torch.empty(self.mesh.n_cells, dtype=torch.float64, device=gh_final.device)
+            gu0 = torch.empty(self.mesh.n_edges, dtype=torch.float64, device=gh_final.device)
+            gcd = torch.empty(self.mesh.n_cells, dtype=torch.float64, device=gh_final.device)
+            ptrs = [C.c_void_p(t.data_ptr()) for t in (gh0, gu0, gcd)]
+        else:
+            gh0, gu0, gcd = np.empty(self.mesh.n_cells), np.empty(self.mesh.n_edges), np.empty(self.mesh.n_cells)
+            ptrs = [t.ctypes.data_as(C.c_void_p) for t in (gh0, gu0, gcd)]
+        _check(lib().fblts_adjoint_backward(self.handle, ph, pu, *ptrs, dh))
+        return gh0, gu0, gcd
+
     def set_timing(self, on=True):
         _check(lib().fblts_set_timing(self.handle, int(on)))
 
@@ -348,3 +385,39 @@ class Ensemble:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.fblts_ensemble_destroy(self.handle)
             self.handle = None
+
+
+def fblts_function():
+    """torch.autograd.Function running n FB-LTS coarse steps on a Solver.
+
+    forward(h0, u0, cd, solver, n_steps, ckpt_every) -> (h_N, u_N); backward
+    returns the gradients with respect to h0, u0 and the per-cell drag cd
+    through the library's hand-written adjoint (checkpoint every ckpt_every
+    steps).  Tensors are float64 CUDA tensors in the caller's numbering.
+    """
+    import torch
+
+    class FBLTSSteps(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, h0, u0, cd, solver, n_steps, ckpt_every):
+            solver.set_drag(cd.detach().contiguous())
+            solver.set_state(h0.detach().contiguous(), u0.detach().contiguous())
+            solver.adjoint_forward(n_steps, ckpt_every)
+            hN = torch.empty_like(h0)
+            uN = torch.empty_like(u0)
+            solver.get_state(hN, uN)
+            ctx.solver = solver
+            ctx.shapes = (h0.shape, u0.shape, h0.device)
+            return hN, uN
+
+        @staticmethod
+        def backward(ctx, ghN, guN):
+            hs, us, dev = ctx.shapes
+            if ghN is None:
+                ghN = torch.zeros(hs, dtype=torch.float64, device=dev)
+            if guN is None:
+                guN = torch.zeros(us, dtype=torch.float64, device=dev)
+            gh0, gu0, gcd = ctx.solver.adjoint_backward(ghN.contiguous(), guN.contiguous())
+            return gh0, gu0, gcd, None, None, None
+
+    return FBLTSSteps

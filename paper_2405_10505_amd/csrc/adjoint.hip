@@ -1,0 +1,228 @@
+// Reverse-mode (adjoint) kernels of the TRiSK tendencies, gfx950.
+//
+// For a tendency evaluated at a point (u, h) and a cotangent on its output,
+// these kernels accumulate the cotangents of the inputs (vector-Jacobian
+// products).  Every transpose is written as a gather, so each output has one
+// writer: no atomics, and the result is bitwise reproducible.
+//   * cellsOnEdge <-> edgesOnCell, verticesOnEdge <-> edgesOnVertex and
+//     cellsOnVertex <-> verticesOnCell are each other's transposes;
+//   * edgesOnEdge is a symmetric relation, and the transposed weight w_{e',e}
+//     is stored beside w_{e,e'} (exact, no reliance on antisymmetry rounding).
+// Thickness tendency (eq. trisk_thickness): Psi_i = -(1/A_i) sum n_{e,i} l_e F_e,
+// F_e = h_e u_e.  Momentum tendency (eq. trisk_vorticity with eq.
+// nonlinear_swe and the quadratic drag of eq. hurricane_model):
+// Phi_e = (1/d_e) sum w_{e,e'} (lF)_e' (q_e+q_e')/2 - (B_c1-B_c0)/d_e - C_D |u| u / h_e.
+// Intermediates at the point (q_v, and the edge record (lF, q_e, l u, h_e))
+// come from the forward vertex / prep passes.
+#include <hip/hip_runtime.h>
+
+#include "fblts_internal.h"
+
+namespace fblts {
+
+namespace {
+__device__ __forceinline__ int tid_global() { return blockIdx.x * blockDim.x + threadIdx.x; }
+}  // namespace
+
+// y[i] = b*y[i] + a0*x0[i] + a1*x1[i] + a2*x2[i] over [begin,end) (null inputs skipped).
+__global__ void __launch_bounds__(kBlock) k_lincomb(double* y, double b, const double* x0, double a0,
+                                                    const double* x1, double a1, const double* x2, double a2,
+                                                    int begin, int end) {
+  const int i = begin + tid_global();
+  if (i >= end) return;
+  // plain multiply-add in a fixed order (matches the forward passes' FB averages)
+  double v = b == 0.0 ? 0.0 : b * y[i];
+  if (x0) v = v + a0 * x0[i];
+  if (x1) v = v + a1 * x1[i];
+  if (x2) v = v + a2 * x2[i];
+  y[i] = v;
+}
+
+// ------------------------------------------------------------ Psi transpose
+// Fbar_e = l_e (-pb_c0/A_c0 + pb_c1/A_c1); ub_e += Fbar_e h_e; T_e = Fbar_e u_e.
+__global__ void __launch_bounds__(kBlock) k_psi_vjp_edge(MeshDev m, int linear, const double* u, const double* h,
+                                                         const double* pb, double* ub, double* T) {
+  const int e = tid_global();
+  if (e >= m.E) return;
+  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  const double fb = m.e_dv[e] * (pb[c1] * m.c_invA[c1] - pb[c0] * m.c_invA[c0]);
+  const double he = linear ? m.e_He[e] : 0.5 * (h[c0] + h[c1]);
+  ub[e] = fma(fb, he, ub[e]);
+  if (!linear) T[e] = fb * u[e];
+}
+
+// hb_i += (1/2) sum_{e in E_i} T_e.
+__global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, const double* T, double* hb) {
+  const int i = tid_global();
+  if (i >= m.N) return;
+  const int n = m.c_nedge[i];
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) s += T[m.c_edge[j * m.cs + i] >> 1];
+  hb[i] = fma(0.5, s, hb[i]);
+}
+
+// ------------------------------------------------------------ Phi transpose
+// Pass 1 (edges): G_e = fb_e/d_e; drag terms of d/du_e, d/du_perp_e, d/dh_e, d/dC_D.
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int drag, const double* u, const double* P,
+                                                       const double* cd, const double* fb, double* G, double* R,
+                                                       double* HD, double* CDB, double* ub) {
+  const int e = tid_global();
+  if (e >= m.E) return;
+  const double g = fb[e] * m.e_invdc[e];
+  G[e] = g;
+  if (!drag) return;
+  const double4* P4 = reinterpret_cast<const double4*>(P);
+  const int n = m.e_neoe[e];
+  double su = 0.0;
+  for (int j = 0; j < n; ++j) su = fma(m.e_w[j * m.es + e], P4[m.e_eoe[j * m.es + e]].z, su);
+  const double up = su * m.e_invdc[e];
+  const double ue = u[e];
+  const double he = P4[e].w;
+  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  const double cde = 0.5 * (cd[c0] + cd[c1]);
+  const double sp = sqrt(ue * ue + up * up);
+  // D = C_D |u| u / h_e, Phi -= D; |u| u is C^1 with zero derivative at |u| = 0
+  const double dDdu = sp > 0.0 ? cde * (sp + ue * ue / sp) / he : 0.0;
+  const double dDdup = sp > 0.0 ? cde * ue * up / (sp * he) : 0.0;
+  ub[e] = fma(-fb[e], dDdu, ub[e]);
+  R[e] = -fb[e] * dDdup * m.e_invdc[e];
+  HD[e] = fb[e] * cde * sp * ue / (he * he);
+  CDB[e] = -fb[e] * sp * ue / he;
+}
+
+// Pass 2 (cells): Bbar_i = sum n_{e,i} G_e; hsb_i += g Bbar_i.
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, double g, const double* G, double* BB,
+                                                       double* hsb) {
+  const int i = tid_global();
+  if (i >= m.N) return;
+  const int n = m.c_nedge[i];
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int code = m.c_edge[j * m.cs + i];
+    const double x = G[code >> 1];
+    s = (code & 1) ? s - x : s + x;
+  }
+  BB[i] = s;
+  hsb[i] = fma(g, s, hsb[i]);
+}
+
+// Pass 3 (edges, edges_on_edge gathers): PV-flux transpose, drag perp transpose,
+// kinetic-energy transpose; writes qbar_e, and h_e's cotangent HE_e.
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int linear, int drag, const double* u,
+                                                       const double* P, const double* G, const double* R,
+                                                       const double* HD, const double* BB, double* QB, double* HE,
+                                                       double* ub) {
+  const int e = tid_global();
+  if (e >= m.E) return;
+  const double4* P4 = reinterpret_cast<const double4*>(P);
+  const double4 pe = P4[e];
+  const int n = m.e_neoe[e];
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int e2 = m.e_eoe[j * m.es + e];
+    const double wT = m.e_wT[j * m.es + e];
+    const double w = m.e_w[j * m.es + e];
+    const double4 p2 = P4[e2];
+    const double g2 = G[e2];
+    s1 = fma(wT * g2, p2.y + pe.y, s1);   // d/d(lF)_e of the neighbours' Q_perp
+    s2 = fma(w, p2.x, s2);                 // d Q_perp_e / d q_e (own sum)
+    s3 = fma(wT, g2, s3);                  // d Q_perp_e2 / d q_e (neighbours)
+    if (drag) s4 = fma(wT, R[e2], s4);     // neighbours' |u| through u_perp
+  }
+  const double lFb = 0.5 * s1;
+  const double ue = u[e];
+  const double le = m.e_dv[e];
+  const double Fb = le * lFb;
+  double acc = ub[e];
+  if (!linear) {
+    QB[e] = 0.5 * (G[e] * s2 + pe.x * s3);
+    acc = fma(Fb, pe.w, acc);                                  // F = h_e u
+    HE[e] = Fb * ue + (drag ? HD[e] : 0.0);                    // h_e's cotangent
+    const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+    const double kb = BB[c0] * m.c_invA[c0] + BB[c1] * m.c_invA[c1];
+    acc = fma(0.5 * le * m.e_dc[e] * ue, kb, acc);             // K_i = (1/A_i) sum l d u^2 / 4
+    if (drag) acc = fma(le, s4, acc);
+  } else {
+    acc = fma(Fb, m.e_He[e], acc);                             // F = H_e u
+  }
+  ub[e] = acc;
+}
+
+// Pass 4 (vertices): qbar_v = (1/2) sum_{e in E_v} QB_e; zeta and h_v cotangents
+// (scaled by 1/A_v): ZA_v = qbar_v / (h_v A_v), HV_v = -qbar_v q_v / (h_v A_v).
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_v1(MeshDev m, const double* hs, const double* q,
+                                                       const double* QB, double* ZA, double* HV) {
+  const int v = tid_global();
+  if (v >= m.V) return;
+  double qb = 0.0, hv = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    qb += QB[m.v_edge[j * m.vs + v] >> 1];
+    hv = fma(m.v_kite[j * m.vs + v], hs[m.v_cell[j * m.vs + v]], hv);
+  }
+  qb *= 0.5;
+  const double ia = m.v_invA[v];
+  const double hvv = hv * ia;   // h_v
+  ZA[v] = qb / hvv * ia;
+  HV[v] = -qb * q[v] / hvv * ia;
+}
+
+// Pass 5 (edges): ub_e += d_e (ZA_{v1} - ZA_{v0})  (circulation sign +1 at v1).
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_e3(MeshDev m, const double* ZA, double* ub) {
+  const int e = tid_global();
+  if (e >= m.E) return;
+  const int v0 = m.e_vert[e], v1 = m.e_vert[m.es + e];
+  ub[e] = fma(m.e_dc[e], ZA[v1] - ZA[v0], ub[e]);
+}
+
+// Pass 6 (cells): hsb_i += (1/2) sum_{e in E_i} HE_e + sum_{v in V_i} kite_{i,v} HV_v;
+// cdb_i += (1/2) sum_{e in E_i} CDB_e.
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_c2(MeshDev m, int drag, const double* HE, const double* HV,
+                                                       const double* CDB, double* hsb, double* cdb) {
+  const int i = tid_global();
+  if (i >= m.N) return;
+  const int n = m.c_nedge[i];
+  double se = 0.0, sv = 0.0, sc = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int e = m.c_edge[j * m.cs + i] >> 1;
+    se += HE[e];
+    sv = fma(m.c_kite[j * m.cs + i], HV[m.c_vert[j * m.cs + i]], sv);
+    if (drag) sc += CDB[e];
+  }
+  hsb[i] = hsb[i] + 0.5 * se + sv;
+  if (drag) cdb[i] = fma(0.5, sc, cdb[i]);
+}
+
+// ----------------------------------------------------------------- launchers
+static dim3 grid_for(long n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+void launch_lincomb(double* y, double b, const double* x0, double a0, const double* x1, double a1, const double* x2,
+                    double a2, int begin, int end, hipStream_t st) {
+  if (end <= begin) return;
+  hipLaunchKernelGGL(k_lincomb, grid_for(end - begin), dim3(kBlock), 0, st, y, b, x0, a0, x1, a1, x2, a2, begin, end);
+}
+
+void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
+                    double* hb, double* T, hipStream_t st) {
+  hipLaunchKernelGGL(k_psi_vjp_edge, grid_for(m.E), dim3(kBlock), 0, st, m, linear, u, h, pb, ub, T);
+  if (!linear) hipLaunchKernelGGL(k_psi_vjp_cell, grid_for(m.N), dim3(kBlock), 0, st, m, (const double*)T, hb);
+}
+
+// Scratch: G, R, HD, CDB, HE, QB (edges), BB (cells), ZA, HV (vertices).
+void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
+                    const double* P, const double* q, const double* cd, const double* fb, double* ub, double* hsb,
+                    double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
+                    double* ZA, double* HV, hipStream_t st) {
+  hipLaunchKernelGGL(k_phi_vjp_e1, grid_for(m.E), dim3(kBlock), 0, st, m, drag, u, P, cd, fb, G, R, HD, CDB, ub);
+  hipLaunchKernelGGL(k_phi_vjp_c1, grid_for(m.N), dim3(kBlock), 0, st, m, g, (const double*)G, BB, hsb);
+  hipLaunchKernelGGL(k_phi_vjp_e2, grid_for(m.E), dim3(kBlock), 0, st, m, linear, drag, u, P, (const double*)G,
+                     (const double*)R, (const double*)HD, (const double*)BB, QB, HE, ub);
+  if (!linear) {
+    hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(m.V), dim3(kBlock), 0, st, m, hs, q, (const double*)QB, ZA, HV);
+    hipLaunchKernelGGL(k_phi_vjp_e3, grid_for(m.E), dim3(kBlock), 0, st, m, (const double*)ZA, ub);
+    hipLaunchKernelGGL(k_phi_vjp_c2, grid_for(m.N), dim3(kBlock), 0, st, m, drag, (const double*)HE,
+                       (const double*)HV, (const double*)CDB, hsb, cdb);
+  }
+}
+
+}  // namespace fblts

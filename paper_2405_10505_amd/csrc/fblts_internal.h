@@ -48,6 +48,10 @@ struct MeshDev {
   const double* v_A;       // [V]
   const double* v_f;       // [V]
   const double* v_q0;      // [V] f_v / H_v (linear PV about rest)
+  // transposes used by the adjoint kernels
+  const double* e_wT;      // [maxEOE][es]  w_{e2,e} for e2 = e_eoe[j][e] (0 on padding)
+  const int* c_vert;       // [maxE][cs]    vertices of the cell (ccw; padding repeats slot 0)
+  const double* c_kite;    // [maxE][cs]    kite area of the cell at that vertex (0 on padding)
 };
 
 // Thickness pass: Psi, FB stage update, FB-averaged thickness and Bernoulli

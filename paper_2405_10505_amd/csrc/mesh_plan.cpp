@@ -378,7 +378,7 @@ Aux aux_for_edges(const NewAdj& a, int eb, int ee, bool nonlinear) {
 }  // namespace
 
 void build_plan(const HostMesh& m, const std::vector<int8_t>& lab4, const std::vector<int>& layer, bool fblts,
-                bool nonlinear, int r, Plan& p) {
+                bool nonlinear, int r, Plan& p, bool full_coarse) {
   const int N = m.N, E = m.E, V = m.V;
   // ---- cell order: region, then hop distance to the other region (clamped so
   // deep cells keep the caller's locality order), then caller index.
@@ -552,6 +552,16 @@ void build_plan(const HostMesh& m, const std::vector<int8_t>& lab4, const std::v
     cell_min_next = std::min(need_c, rd.min_cell);
     edge_min_next = std::min(need_e, rd.min_edge);
   }
+  // definition mode (used by the adjoint's recording forward): the coarse
+  // advancement is evaluated on every cell, edge and vertex
+  if (full_coarse)
+    for (int s = 0; s < 3; ++s) {
+      StageRanges& R = p.coarse[s];
+      R.cell = R.cell_upd = {0, N};
+      R.vert = {0, nonlinear ? V : 0};
+      R.prep = {0, E};
+      R.edge = R.edge_upd = {0, E};
+    }
   // deepest fine layer reached by the coarse sweep (for reporting against F^5)
   int deepest = 0;
   for (int i = p.coarse[0].cell.b; i < p.nF; ++i)
@@ -636,6 +646,48 @@ void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm) {
     for (int j = 0; j < n; ++j) {
       pm.e_eoe[(size_t)j * pm.es + en] = p.edge_old2new[m.eoe[b + j]];
       pm.e_w[(size_t)j * pm.es + en] = m.woe[b + j];
+    }
+  }
+  // transposed weights: w_{e2,e} where e2 is slot j of e's list
+  pm.e_wT.assign((size_t)maxEOE * pm.es, 0.0);
+  {
+    std::vector<std::pair<long, double>> wl;   // key e*E+e2 -> w_{e,e2}
+    wl.reserve(m.eoe.size());
+    for (int eo = 0; eo < E; ++eo)
+      for (int t = m.eoe_off[eo]; t < m.eoe_off[eo + 1]; ++t) wl.push_back({(long)eo * E + m.eoe[t], m.woe[t]});
+    std::sort(wl.begin(), wl.end());
+    for (int en = 0; en < E; ++en) {
+      const int eo = p.edge_new2old[en];
+      for (int j = 0; j < pm.e_neoe[en]; ++j) {
+        const int e2o = m.eoe[m.eoe_off[eo] + j];
+        const long key = (long)e2o * E + eo;
+        auto it = std::lower_bound(wl.begin(), wl.end(), std::make_pair(key, -1e300));
+        if (it == wl.end() || it->first != key) fail("mesh: edges_on_edge is not symmetric (needed by the adjoint)");
+        pm.e_wT[(size_t)j * pm.es + en] = it->second;
+      }
+    }
+  }
+  // cell -> vertex list with the cell's kite at each vertex
+  pm.c_vert.assign((size_t)maxE * pm.cs, 0);
+  pm.c_kite.assign((size_t)maxE * pm.cs, 0.0);
+  {
+    std::vector<std::pair<long, double>> kl;   // key cell*V+vertex -> kite
+    kl.reserve(3 * (size_t)V);
+    for (int v = 0; v < V; ++v)
+      for (int j = 0; j < 3; ++j) kl.push_back({(long)m.cov[3 * v + j] * V + v, m.kite[3 * v + j]});
+    std::sort(kl.begin(), kl.end());
+    for (int in = 0; in < N; ++in) {
+      const int io = p.cell_new2old[in];
+      const int b = m.voc_off[io], n = m.voc_off[io + 1] - b;
+      for (int j = 0; j < maxE; ++j) {
+        const int vo = m.voc[b + (j < n ? j : 0)];
+        pm.c_vert[(size_t)j * pm.cs + in] = p.vert_old2new[vo];
+        if (j < n) {
+          const long key = (long)io * V + vo;
+          auto it = std::lower_bound(kl.begin(), kl.end(), std::make_pair(key, -1e300));
+          pm.c_kite[(size_t)j * pm.cs + in] = it->second;
+        }
+      }
     }
   }
   pm.v_edge.assign(3 * (size_t)pm.vs, 0);

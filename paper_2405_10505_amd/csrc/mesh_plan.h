@@ -57,7 +57,7 @@ struct Plan {
 // coarse).  nonlinear selects the vertex passes.  Throws std::runtime_error
 // (message starting with "region:") when the stencil condition fails.
 void build_plan(const HostMesh& m, const std::vector<int8_t>& lab4, const std::vector<int>& layer, bool fblts,
-                bool nonlinear, int r, Plan& p);
+                bool nonlinear, int r, Plan& p, bool full_coarse = false);
 
 // Reordered mesh in the device layout (host staging before upload).
 struct PermMesh {
@@ -68,6 +68,8 @@ struct PermMesh {
   std::vector<double> e_dc, e_dv, e_invdc, e_He, e_w;
   std::vector<int> v_edge, v_cell;
   std::vector<double> v_kite, v_invA, v_A, v_f, v_q0;
+  std::vector<double> e_wT, c_kite;
+  std::vector<int> c_vert;
 };
 void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm);
 

@@ -122,6 +122,7 @@ struct DevMesh {
   DevBuf c_nedge, c_edge, c_nbr, c_invA, c_A, c_H;
   DevBuf e_cell, e_vert, e_dc, e_dv, e_invdc, e_He, e_neoe, e_eoe, e_w;
   DevBuf v_edge, v_cell, v_kite, v_invA, v_A, v_f, v_q0;
+  DevBuf e_wT, c_vert, c_kite;
   DevBuf cell_n2o, edge_n2o, vert_n2o;
   MeshDev md{};
   void upload_from(const PermMesh& pm, const Plan& p) {
@@ -147,6 +148,9 @@ struct DevMesh {
     upload(v_A, pm.v_A);
     upload(v_f, pm.v_f);
     upload(v_q0, pm.v_q0);
+    upload(e_wT, pm.e_wT);
+    upload(c_vert, pm.c_vert);
+    upload(c_kite, pm.c_kite);
     upload(cell_n2o, p.cell_new2old);
     upload(edge_n2o, p.edge_new2old);
     upload(vert_n2o, p.vert_new2old);
@@ -180,6 +184,9 @@ struct DevMesh {
     md.v_A = v_A.as<double>();
     md.v_f = v_f.as<double>();
     md.v_q0 = v_q0.as<double>();
+    md.e_wT = e_wT.as<double>();
+    md.c_vert = c_vert.as<int>();
+    md.c_kite = c_kite.as<double>();
   }
 };
 
@@ -212,7 +219,13 @@ struct DevState {
 };
 
 struct Pass {
-  enum Kind { CELL, VERT, PREP, EDGE, PRED, ASM, RK4FIN } kind;
+  enum Kind { CELL, VERT, PREP, EDGE, PRED, ASM, RK4FIN, COPY } kind;
+  // position in the step: 100*phase + 10*substep + stage (phase 0 coarse, 1 fine,
+  // 2 prediction, 3 assembly); used to place the adjoint's tape snapshots
+  int tag = 0;
+  double* cdst = nullptr;          // COPY
+  const double* csrc = nullptr;
+  long cn = 0;
   Launch<CellSeg> cell;
   Launch<VertSeg> vert;
   Launch<PrepSeg> prep;
@@ -258,7 +271,7 @@ void check_params(const fblts_params* p) {
 }
 
 // Build the pass list of one mesh unit (segments are merged by the caller).
-void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) {
+void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, const Plan* plan = nullptr) {
   const fblts_params& p = P.p;
   const bool nl = P.nonlinear();
   const MeshDev& md = u.dm.md;
@@ -267,6 +280,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
   auto U = [&](int k) { return s.U[k].as<double>(); };
   const double* qsrc = nl ? s.q.as<double>() : md.v_q0;
   u.passes.clear();
+  int cur_tag = 0;
   u.bytes_edge = 0;
   u.edge_items = 0;
   const int nm = s.nm;
@@ -302,6 +316,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
     c.acc_w = acc_w;
     c.g = p.g;
     ps.model_bytes = bytes_cell_pass(u.pm, r, nl, nm);
+    ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
   auto vert_pass = [&](const StageRanges& r, const double* Usrc) {
@@ -318,6 +333,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
     v.hs = s.hs.as<double>();
     v.q = s.q.as<double>();
     ps.model_bytes = bytes_vert_pass(u.pm, r.vert, nm);
+    ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
   auto prep_pass = [&](const StageRanges& r, const double* Usrc) {
@@ -336,6 +352,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
     q.P = s.P.as<double>();
     ps.fuse_q = nl && fuse_q;
     ps.model_bytes = bytes_prep_pass(u.pm, r.prep, nl, nm, ps.fuse_q);
+    ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
   auto edge_pass = [&](const StageRanges& r, const double* Usrc, const double* U0, double* Udst, double c_dt,
@@ -368,6 +385,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
     ps.model_bytes = bytes_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
     u.bytes_edge += ps.model_bytes;
     u.edge_items += (int64_t)r.edge.size() * nm;
+    ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
   auto stage = [&](const StageRanges& r, const double* Hsrc, const double* Usrc, const double* H0,
@@ -380,7 +398,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
   };
 
   const double dt = p.dt, b1 = p.beta1, b2 = p.beta2, b3 = p.beta3;
-  const Plan& pl = u.plan;
+  const Plan& pl = plan ? *plan : u.plan;
   const int N = md.N, E = md.E;
   if (p.scheme == FBLTS_SCHEME_FBRK32) {
     const StageRanges* R = pl.coarse;
@@ -420,8 +438,11 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
   const int M = p.M;
   const double delta = dt / M;
   const StageRanges* C = pl.coarse;
+  cur_tag = 1;
   stage(C[0], H(0), U(0), H(0), H(1), H(1), dt / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
+  cur_tag = 2;
   stage(C[1], H(1), U(1), H(0), H(2), H(2), dt / 2, b2, 0.0, 1 - b2, nullptr, U(0), U(2), nullptr, 1, 1);
+  cur_tag = 3;
   stage(C[2], H(2), U(2), H(0), H(3), H(3), dt, b3, 1 - 2 * b3, b3, nullptr, U(0), U(3), nullptr, 1, 1);
   const int if1b = pl.nF, if1e = pl.nF + pl.nIF1, if2e = if1e + pl.nIF2;
   const int if1eb = pl.nFE, if1ee = pl.nFE + pl.nIF1E, if2ee = if1ee + pl.nIF2E;
@@ -455,9 +476,13 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
     q.c = (double)(M - k - 1) / (double)M;
     q.ap = (double)(k + 1) / (double)M;
     pr.model_bytes = ((double)(if1e - if1b) * 8 + (double)(if1ee - if1eb) * 7) * 8.0 * nm;
+    pr.tag = 200 + 10 * k;
     u.passes.push_back(pr);
+    cur_tag = 100 + 10 * k + 1;
     stage(F[0], H(0), U(0), H(0), H(1), H(1), delta / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
+    cur_tag = 100 + 10 * k + 2;
     stage(F[1], H(1), U(1), H(0), H(2), H(2), delta / 2, b2, 0.0, 1 - b2, nullptr, U(0), U(2), nullptr, 1, 1);
+    cur_tag = 100 + 10 * k + 3;
     stage(F[2], H(2), U(2), H(0), H(3), H(0), delta, b3, 1 - 2 * b3, b3, ah, U(0), U(0), au, 1.0, k == 0);
   }
   Pass as;
@@ -483,6 +508,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q) 
   a.sv_u = s.sv_u.as<double>();
   a.delta = delta;
   as.model_bytes = (((double)(N - if1b) * 3) + ((double)(E - if1eb) * 3)) * 8.0 * nm;
+  as.tag = 300;
   u.passes.push_back(as);
   u.cell_substeps = ((int64_t)(N - pl.nF) + (int64_t)M * pl.nF) * nm;
 }
@@ -516,6 +542,7 @@ std::vector<Pass> merge_passes(const std::vector<MeshUnit*>& units) {
         case Pass::RK4FIN:
           for (auto& t : q.fin) ps.fin.push_back(t);
           break;
+        case Pass::COPY: break;
       }
       ps.model_bytes += q.model_bytes;
     }
@@ -573,11 +600,238 @@ void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool
       case Pass::RK4FIN:
         for (auto& t : ps.fin) launch_axpy_final(std::get<0>(t), std::get<1>(t), ps.fin_c, std::get<2>(t), st);
         break;
+      case Pass::COPY: launch_copy(ps.cdst, ps.csrc, ps.cn, st); break;
     }
     if (evp.first) hip_check(hipEventRecord(evp.second, st), "hipEventRecord");
   }
   hip_check(hipGetLastError(), "kernel launch");
 }
+
+}  // namespace
+
+// ------------------------------------------------------------------ adjoint
+//
+// Reverse mode of the FB-LTS step (paper Section 2.2) in definition mode: the
+// recording forward evaluates the coarse advancement on every cell and edge
+// (so every primal value the transposed operators read is valid), the fine
+// substeps as usual, and snapshots the stage arrays into a per-step tape.  The
+// reverse sweep then walks the step backwards, statement by statement, using
+// the transposed tendency kernels.  Checkpoints of (h, u) every K steps bound
+// the tape to K steps.
+
+namespace fblts {
+void launch_lincomb(double* y, double b, const double* x0, double a0, const double* x1, double a1, const double* x2,
+                    double a2, int begin, int end, hipStream_t st);
+void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
+                    double* hb, double* T, hipStream_t st);
+void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
+                    const double* P, const double* q, const double* cd, const double* fb, double* ub, double* hsb,
+                    double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
+                    double* ZA, double* HV, hipStream_t st);
+}  // namespace fblts
+
+namespace {
+
+enum CellArr { hNb, hb, h1b, h2b, h3b, H0b, H1b, H2b, H3b, ahb, pb, hsb, hspt, BBa, cdb, kNCellArr };
+enum EdgeArr { uNb, ub, u1b, u2b, u3b, U0b, U1b, U2b, U3Fb, aub, fb, Ta, Ga, Ra, HDa, CDBa, HEa, QBa, kNEdgeArr };
+
+}  // namespace
+
+struct AdjointState {
+  int n_steps = 0, ckpt_every = 0, M = 0;
+  bool recorded = false;
+  Plan plan_full;
+  size_t tape_c = 0, tape_e = 0;   // doubles per step of the cell / edge tape
+  DevBuf ckpt, final_state, step_tape, seg_tape;
+  DevBuf cells, edges, verts, Pf;
+  std::vector<Pass> rec;
+};
+
+namespace {
+
+struct Rev {
+  // views of one solver's arrays for the reverse sweep
+  const MeshDev* m;
+  int N, E, V, nF, if1e, if2e, nFE, if1ee, if2ee, M;
+  double dt, b1, b2, b3, g;
+  bool linear, drag;
+  const double* cd;
+  double* C[kNCellArr];
+  double* Ed[kNEdgeArr];
+  double* ZA;
+  double* HV;
+  double* qf;
+  double* P;
+  hipStream_t st;
+  void lin(double* y, double b, const double* x0, double a0, const double* x1, double a1, const double* x2, double a2,
+           int lo, int hi) {
+    launch_lincomb(y, b, x0, a0, x1, a1, x2, a2, lo, hi, st);
+  }
+  void zero(double* y, int lo, int hi) { lin(y, 0.0, nullptr, 0, nullptr, 0, nullptr, 0, lo, hi); }
+  void set(double* y, double a, const double* x, int lo, int hi) { lin(y, 0.0, x, a, nullptr, 0, nullptr, 0, lo, hi); }
+  void axpy(double* y, double a, const double* x, int lo, int hi) { lin(y, 1.0, x, a, nullptr, 0, nullptr, 0, lo, hi); }
+  void psi_vjp(const double* u, const double* h, const double* pbar, double* ubar, double* hbar) {
+    launch_psi_vjp(*m, linear ? 1 : 0, u, h, pbar, ubar, hbar, Ed[Ta], st);
+  }
+  // cotangent fbar of Phi(u, hs) -> ubar (accumulated), hsbar (overwritten), C_D (accumulated)
+  void phi_vjp(const double* u, const double* hs, const double* fbar, double* ubar, double* hsbar) {
+    // forward intermediates at the point: q_v and the edge record
+    if (!linear) {
+      Launch<VertSeg> v{};
+      v.nseg = 1;
+      v.seg[0] = VertSeg{*m, 0, 0, V, u, hs, qf};
+      launch_vertex(v, kBlock, st);
+    }
+    Launch<PrepSeg> pp{};
+    pp.nseg = 1;
+    pp.seg[0] = PrepSeg{*m, 0, 0, E, linear ? 1 : 0, u, hs, linear ? m->v_q0 : qf, P};
+    launch_prep(pp, false, kBlock, st);
+    zero(hsbar, 0, N);
+    launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, linear ? m->v_q0 : qf, cd, fbar, ubar, hsbar,
+                   C[cdb], Ed[Ga], Ed[Ra], Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, st);
+  }
+  // One reverse step: (hNb, uNb) = cotangent of the step's output -> (hb, ub)
+  // = cotangent of its input; C_D's cotangent accumulates.  tc / te: tape.
+  void step(const double* tc, const double* te) {
+    auto TC = [&](int slot) { return tc + (size_t)slot * N; };
+    auto TE = [&](int slot) { return te + (size_t)slot * E; };
+    const double* h = TC(0);
+    const double* h1 = TC(1);
+    const double* h2 = TC(2);
+    const double* h3 = TC(3);
+    const double* u = TE(0);
+    const double* u1 = TE(1);
+    const double* u2 = TE(2);
+    const double* u3 = TE(3);
+    double** c = C;
+    double** e = Ed;
+    for (int k : {hb, h1b, h2b, h3b, H0b, H1b, H2b, H3b, ahb}) zero(c[k], 0, N);
+    for (int k : {ub, u1b, u2b, u3b, U0b, U1b, U2b, U3Fb, aub}) zero(e[k], 0, E);
+    const double delta = dt / M;
+    // assembly: h^{n+1} = h3 (interior), H0 (fine), h + delta acc_h (interface)
+    set(c[h3b], 1.0, c[hNb], if2e, N);
+    set(c[H0b], 1.0, c[hNb], 0, nF);
+    set(c[hb], 1.0, c[hNb], nF, if2e);
+    set(c[ahb], delta, c[hNb], nF, if2e);
+    set(e[u3b], 1.0, e[uNb], if2ee, E);
+    set(e[U0b], 1.0, e[uNb], 0, nFE);
+    set(e[ub], 1.0, e[uNb], nFE, if2ee);
+    set(e[aub], delta, e[uNb], nFE, if2ee);
+    for (int k = M - 1; k >= 0; --k) {
+      const double* H0k = TC(4 + 4 * k);
+      const double* H1k = TC(5 + 4 * k);
+      const double* H2k = TC(6 + 4 * k);
+      const double* H3k = TC(7 + 4 * k);
+      const double* U0k = TE(4 + 3 * k);
+      const double* U1k = TE(5 + 3 * k);
+      const double* U2k = TE(6 + 3 * k);
+      // H0[F] <- H3[F]; U0[Fe] <- U3F[Fe]
+      axpy(c[H3b], 1.0, c[H0b], 0, nF);
+      zero(c[H0b], 0, nF);
+      set(e[U3Fb], 1.0, e[U0b], 0, nFE);
+      zero(e[U0b], 0, nFE);
+      // stage 3, momentum: U3F = U0 + delta Phi(U2, hs3) on Fe; acc_u += Phi on IFe
+      zero(e[fb], 0, E);
+      set(e[fb], delta, e[U3Fb], 0, nFE);
+      set(e[fb], 1.0, e[aub], nFE, if2ee);
+      axpy(e[U0b], 1.0, e[U3Fb], 0, nFE);
+      lin(c[hspt], 0.0, H3k, b3, H2k, 1.0 - 2.0 * b3, H0k, b3, 0, N);
+      phi_vjp(U2k, c[hspt], e[fb], e[U2b], c[hsb]);
+      lin(c[H3b], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
+      lin(c[H2b], 1.0, c[hsb], 1.0 - 2.0 * b3, nullptr, 0, nullptr, 0, 0, N);
+      lin(c[H0b], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
+      // stage 3, thickness: H3[F] = H0 + delta Psi(U2, H2); acc_h += Psi on IF
+      zero(c[pb], 0, N);
+      set(c[pb], delta, c[H3b], 0, nF);
+      set(c[pb], 1.0, c[ahb], nF, if2e);
+      axpy(c[H0b], 1.0, c[H3b], 0, nF);
+      zero(c[H3b], 0, nF);
+      psi_vjp(U2k, H2k, c[pb], e[U2b], c[H2b]);
+      // stage 2, momentum: U2[Fe] = U0 + delta/2 Phi(U1, hs2)
+      zero(e[fb], 0, E);
+      set(e[fb], delta / 2, e[U2b], 0, nFE);
+      axpy(e[U0b], 1.0, e[U2b], 0, nFE);
+      zero(e[U2b], 0, nFE);
+      lin(c[hspt], 0.0, H2k, b2, H0k, 1.0 - b2, nullptr, 0, 0, N);
+      phi_vjp(U1k, c[hspt], e[fb], e[U1b], c[hsb]);
+      lin(c[H2b], 1.0, c[hsb], b2, nullptr, 0, nullptr, 0, 0, N);
+      lin(c[H0b], 1.0, c[hsb], 1.0 - b2, nullptr, 0, nullptr, 0, 0, N);
+      // stage 2, thickness: H2[F] = H0 + delta/2 Psi(U1, H1)
+      zero(c[pb], 0, N);
+      set(c[pb], delta / 2, c[H2b], 0, nF);
+      axpy(c[H0b], 1.0, c[H2b], 0, nF);
+      zero(c[H2b], 0, nF);
+      psi_vjp(U1k, H1k, c[pb], e[U1b], c[H1b]);
+      // stage 1, momentum: U1[Fe] = U0 + delta/3 Phi(U0, hs1)
+      zero(e[fb], 0, E);
+      set(e[fb], delta / 3, e[U1b], 0, nFE);
+      axpy(e[U0b], 1.0, e[U1b], 0, nFE);
+      zero(e[U1b], 0, nFE);
+      lin(c[hspt], 0.0, H1k, b1, H0k, 1.0 - b1, nullptr, 0, 0, N);
+      phi_vjp(U0k, c[hspt], e[fb], e[U0b], c[hsb]);
+      lin(c[H1b], 1.0, c[hsb], b1, nullptr, 0, nullptr, 0, 0, N);
+      lin(c[H0b], 1.0, c[hsb], 1.0 - b1, nullptr, 0, nullptr, 0, 0, N);
+      // stage 1, thickness: H1[F] = H0 + delta/3 Psi(U0, H0)
+      zero(c[pb], 0, N);
+      set(c[pb], delta / 3, c[H1b], 0, nF);
+      axpy(c[H0b], 1.0, c[H1b], 0, nF);
+      zero(c[H1b], 0, nF);
+      psi_vjp(U0k, H0k, c[pb], e[U0b], c[H0b]);
+      // interface-one prediction (eq. preds) of substep k
+      const double a = (double)k / (double)M, oma = (double)(M - k) / (double)M;
+      const double cc = (double)(M - k - 1) / (double)M, ap = (double)(k + 1) / (double)M, iM = 1.0 / M;
+      lin(c[h3b], 1.0, c[H0b], a, c[H1b], a, c[H2b], a, nF, if1e);
+      lin(c[h3b], 1.0, c[H3b], ap, nullptr, 0, nullptr, 0, nF, if1e);
+      lin(c[hb], 1.0, c[H0b], oma, c[H1b], cc, c[H2b], cc, nF, if1e);
+      lin(c[hb], 1.0, c[H3b], cc, nullptr, 0, nullptr, 0, nF, if1e);
+      axpy(c[h1b], iM, c[H1b], nF, if1e);
+      axpy(c[h2b], iM, c[H2b], nF, if1e);
+      for (int q : {H0b, H1b, H2b, H3b}) zero(c[q], nF, if1e);
+      lin(e[u3b], 1.0, e[U0b], a, e[U1b], a, e[U2b], a, nFE, if1ee);
+      lin(e[ub], 1.0, e[U0b], oma, e[U1b], cc, e[U2b], cc, nFE, if1ee);
+      axpy(e[u1b], iM, e[U1b], nFE, if1ee);
+      axpy(e[u2b], iM, e[U2b], nFE, if1ee);
+      for (int q : {U0b, U1b, U2b}) zero(e[q], nFE, if1ee);
+    }
+    // the fine arrays start as copies of the coarse stage values
+    axpy(c[hb], 1.0, c[H0b], 0, N);
+    axpy(c[h1b], 1.0, c[H1b], 0, N);
+    axpy(c[h2b], 1.0, c[H2b], 0, N);
+    axpy(c[h3b], 1.0, c[H3b], 0, N);
+    axpy(e[ub], 1.0, e[U0b], 0, E);
+    axpy(e[u1b], 1.0, e[U1b], 0, E);
+    axpy(e[u2b], 1.0, e[U2b], 0, E);
+    // coarse advancement (eq. fbrk32), stage 3 to 1
+    axpy(e[ub], 1.0, e[u3b], 0, E);
+    set(e[fb], dt, e[u3b], 0, E);
+    lin(c[hspt], 0.0, h3, b3, h2, 1.0 - 2.0 * b3, h, b3, 0, N);
+    phi_vjp(u2, c[hspt], e[fb], e[u2b], c[hsb]);
+    lin(c[h3b], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
+    lin(c[h2b], 1.0, c[hsb], 1.0 - 2.0 * b3, nullptr, 0, nullptr, 0, 0, N);
+    lin(c[hb], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
+    axpy(c[hb], 1.0, c[h3b], 0, N);
+    set(c[pb], dt, c[h3b], 0, N);
+    psi_vjp(u2, h2, c[pb], e[u2b], c[h2b]);
+    axpy(e[ub], 1.0, e[u2b], 0, E);
+    set(e[fb], dt / 2, e[u2b], 0, E);
+    lin(c[hspt], 0.0, h2, b2, h, 1.0 - b2, nullptr, 0, 0, N);
+    phi_vjp(u1, c[hspt], e[fb], e[u1b], c[hsb]);
+    lin(c[h2b], 1.0, c[hsb], b2, nullptr, 0, nullptr, 0, 0, N);
+    lin(c[hb], 1.0, c[hsb], 1.0 - b2, nullptr, 0, nullptr, 0, 0, N);
+    axpy(c[hb], 1.0, c[h2b], 0, N);
+    set(c[pb], dt / 2, c[h2b], 0, N);
+    psi_vjp(u1, h1, c[pb], e[u1b], c[h1b]);
+    axpy(e[ub], 1.0, e[u1b], 0, E);
+    set(e[fb], dt / 3, e[u1b], 0, E);
+    lin(c[hspt], 0.0, h1, b1, h, 1.0 - b1, nullptr, 0, 0, N);
+    phi_vjp(u, c[hspt], e[fb], e[ub], c[hsb]);
+    lin(c[h1b], 1.0, c[hsb], b1, nullptr, 0, nullptr, 0, 0, N);
+    lin(c[hb], 1.0, c[hsb], 1.0 - b1, nullptr, 0, nullptr, 0, 0, N);
+    axpy(c[hb], 1.0, c[h1b], 0, N);
+    set(c[pb], dt / 3, c[h1b], 0, N);
+    psi_vjp(u, h, c[pb], e[ub], c[hb]);
+  }
+};
 
 }  // namespace
 
@@ -606,6 +860,7 @@ struct fblts_solver {
   DevBuf dbg_h, dbg_u, dbg_out;
   double time = 0.0;
   int64_t step = 0;
+  std::unique_ptr<AdjointState> adj;
   ~fblts_solver() {
     drop_graph();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -1366,6 +1621,286 @@ int fblts_ensemble_info(fblts_ensemble* e, int64_t* member_cells, int64_t* cell_
     if (member_cells) *member_cells = mc;
     if (cell_substeps) *cell_substeps = cs;
     if (model_bytes) *model_bytes = b;
+    return FBLTS_OK;
+  });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- adjoint ABI
+
+static void adj_check(fblts_solver* s) {
+  if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+  if (!s->have_state) throw Err(FBLTS_ESTATE, "set_state must come first");
+  if (s->P.p.scheme != FBLTS_SCHEME_FBLTS) throw Err(FBLTS_EINVAL, "the adjoint covers the FB-LTS scheme");
+  if (s->unit->st.has_wind) throw Err(FBLTS_EINVAL, "the adjoint does not cover the wind-stress term");
+}
+
+static Rev make_rev(fblts_solver* s, AdjointState& A) {
+  MeshUnit& u = *s->unit;
+  Rev r;
+  r.m = &u.dm.md;
+  r.N = u.pm.N;
+  r.E = u.pm.E;
+  r.V = u.pm.V;
+  r.nF = u.plan.nF;
+  r.if1e = r.nF + u.plan.nIF1;
+  r.if2e = r.if1e + u.plan.nIF2;
+  r.nFE = u.plan.nFE;
+  r.if1ee = r.nFE + u.plan.nIF1E;
+  r.if2ee = r.if1ee + u.plan.nIF2E;
+  r.M = s->P.p.M;
+  r.dt = s->P.p.dt;
+  r.b1 = s->P.p.beta1;
+  r.b2 = s->P.p.beta2;
+  r.b3 = s->P.p.beta3;
+  r.g = s->P.p.g;
+  r.linear = !s->P.nonlinear();
+  r.drag = s->drag_on;
+  r.cd = u.st.cd.as<double>();
+  for (int k = 0; k < kNCellArr; ++k) r.C[k] = A.cells.as<double>() + (size_t)k * r.N;
+  for (int k = 0; k < kNEdgeArr; ++k) r.Ed[k] = A.edges.as<double>() + (size_t)k * r.E;
+  r.ZA = A.verts.as<double>();
+  r.HV = r.ZA + r.V;
+  r.qf = r.HV + r.V;
+  r.P = A.Pf.as<double>();
+  r.st = s->stream;
+  return r;
+}
+
+static void adj_alloc(fblts_solver* s, AdjointState& A) {
+  const MeshUnit& u = *s->unit;
+  const size_t N = u.pm.N, E = u.pm.E, V = u.pm.V;
+  if (A.cells.bytes < kNCellArr * N * 8) A.cells.alloc(kNCellArr * N * 8);
+  if (A.edges.bytes < kNEdgeArr * E * 8) A.edges.alloc(kNEdgeArr * E * 8);
+  if (A.verts.bytes < 3 * V * 8) A.verts.alloc(3 * V * 8);
+  if (A.Pf.bytes < 4 * E * 8) A.Pf.alloc(4 * E * 8);
+}
+
+// Recording forward: the definition-mode pass list with tape snapshots.
+static void build_recording(fblts_solver* s, AdjointState& A) {
+  MeshUnit& u = *s->unit;
+  const int N = u.pm.N, E = u.pm.E, M = s->P.p.M;
+  build_plan(*u.hm, u.lab4, u.layer, true, s->P.nonlinear(), s->P.p.r_layers, A.plan_full, true);
+  if (A.plan_full.cell_new2old != u.plan.cell_new2old || A.plan_full.edge_new2old != u.plan.edge_new2old)
+    throw Err(FBLTS_EINVAL, "internal: definition-mode plan reordered the mesh");
+  // build the definition-mode pass list without disturbing the solver's own
+  std::vector<Pass> keep = u.passes;
+  const double kb = u.bytes_edge;
+  const int64_t ki = u.edge_items, kc = u.cell_substeps;
+  build_passes_impl(u, s->P, s->drag_on, false, &A.plan_full);
+  std::vector<Pass> def = u.passes;
+  u.passes = keep;
+  u.bytes_edge = kb;
+  u.edge_items = ki;
+  u.cell_substeps = kc;
+  A.tape_c = (size_t)(4 + 4 * M) * N;
+  A.tape_e = (size_t)(4 + 3 * M) * E;
+  if (A.step_tape.bytes < (A.tape_c + A.tape_e) * 8) A.step_tape.alloc((A.tape_c + A.tape_e) * 8);
+  double* tc = A.step_tape.as<double>();
+  double* te = tc + A.tape_c;
+  auto H = [&](int k) { return u.st.H[k].as<double>(); };
+  auto U = [&](int k) { return u.st.U[k].as<double>(); };
+  auto copy = [&](double* dst, const double* src, long n) {
+    Pass c;
+    c.kind = Pass::COPY;
+    c.cdst = dst;
+    c.csrc = src;
+    c.cn = n;
+    A.rec.push_back(c);
+  };
+  A.rec.clear();
+  copy(tc, H(0), N);
+  copy(te, U(0), E);
+  for (size_t i = 0; i < def.size(); ++i) {
+    const Pass& p = def[i];
+    A.rec.push_back(p);
+    const bool last_of_tag = i + 1 == def.size() || def[i + 1].tag != p.tag;
+    if (p.tag == 3 && last_of_tag) {
+      for (int k = 1; k <= 3; ++k) {
+        copy(tc + (size_t)k * N, H(k), N);
+        copy(te + (size_t)k * E, U(k), E);
+      }
+    }
+    if (p.kind == Pass::PRED) {
+      const int k = (p.tag - 200) / 10;
+      copy(tc + (size_t)(4 + 4 * k) * N, H(0), N);
+      copy(te + (size_t)(4 + 3 * k) * E, U(0), E);
+    }
+    if (p.tag >= 100 && p.tag < 200) {
+      const int k = (p.tag - 100) / 10, st = (p.tag - 100) % 10;
+      if (p.kind == Pass::EDGE && st == 1) {
+        copy(tc + (size_t)(5 + 4 * k) * N, H(1), N);
+        copy(te + (size_t)(5 + 3 * k) * E, U(1), E);
+      }
+      if (p.kind == Pass::EDGE && st == 2) {
+        copy(tc + (size_t)(6 + 4 * k) * N, H(2), N);
+        copy(te + (size_t)(6 + 3 * k) * E, U(2), E);
+      }
+      if (p.kind == Pass::CELL && st == 3) {   // H3: fine cells were written into H0
+        copy(tc + (size_t)(7 + 4 * k) * N, H(3), N);
+        copy(tc + (size_t)(7 + 4 * k) * N, H(0), u.plan.nF);
+      }
+    }
+  }
+}
+
+extern "C" {
+
+int fblts_adjoint_forward(fblts_solver* s, int32_t n_steps, int32_t ckpt_every) {
+  return guarded([&] {
+    adj_check(s);
+    if (n_steps < 1 || ckpt_every < 1) throw Err(FBLTS_EINVAL, "n_steps and ckpt_every must be positive");
+    if (s->unit->st.nm != 1) throw Err(FBLTS_EINVAL, "the adjoint needs a one-member solver");
+    if (!s->adj) s->adj = std::make_unique<AdjointState>();
+    AdjointState& A = *s->adj;
+    MeshUnit& u = *s->unit;
+    const int N = u.pm.N, E = u.pm.E;
+    A.n_steps = n_steps;
+    A.ckpt_every = ckpt_every;
+    A.M = s->P.p.M;
+    const int nck = (n_steps + ckpt_every - 1) / ckpt_every;
+    if (A.ckpt.bytes < (size_t)nck * (N + E) * 8) A.ckpt.alloc((size_t)nck * (N + E) * 8);
+    if (A.final_state.bytes < (size_t)(N + E) * 8) A.final_state.alloc((size_t)(N + E) * 8);
+    const bool nl = s->P.nonlinear();
+    for (int t = 0; t < n_steps; ++t) {
+      if (t % ckpt_every == 0) {
+        double* c = A.ckpt.as<double>() + (size_t)(t / ckpt_every) * (N + E);
+        launch_copy(c, u.st.H[0].as<double>(), N, s->stream);
+        launch_copy(c + N, u.st.U[0].as<double>(), E, s->stream);
+      }
+      run_passes(u.passes, nl, s->drag_on, false, s->stream, nullptr);
+    }
+    launch_copy(A.final_state.as<double>(), u.st.H[0].as<double>(), N, s->stream);
+    launch_copy(A.final_state.as<double>() + N, u.st.U[0].as<double>(), E, s->stream);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->step += n_steps;
+    s->time += n_steps * s->P.p.dt;
+    A.recorded = true;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_adjoint_backward(fblts_solver* s, const double* gh_final, const double* gu_final, double* gh0, double* gu0,
+                           double* gcd, int32_t on_device) {
+  return guarded([&] {
+    adj_check(s);
+    if (!s->adj || !s->adj->recorded) throw Err(FBLTS_ESTATE, "fblts_adjoint_forward must come first");
+    if (!gh_final || !gu_final) throw Err(FBLTS_EINVAL, "NULL seed");
+    AdjointState& A = *s->adj;
+    MeshUnit& u = *s->unit;
+    const int N = u.pm.N, E = u.pm.E;
+    if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    adj_alloc(s, A);
+    build_recording(s, A);
+    const int K = A.ckpt_every;
+    if (A.seg_tape.bytes < (size_t)K * (A.tape_c + A.tape_e) * 8) A.seg_tape.alloc((size_t)K * (A.tape_c + A.tape_e) * 8);
+    Rev r = make_rev(s, A);
+    // seeds into the library's numbering
+    DevBuf th, tu;
+    const double* sh = gh_final;
+    const double* su = gu_final;
+    if (!on_device) {
+      th.alloc((size_t)N * 8);
+      tu.alloc((size_t)E * 8);
+      hip_check(hipMemcpy(th.p, gh_final, (size_t)N * 8, hipMemcpyHostToDevice), "memcpy");
+      hip_check(hipMemcpy(tu.p, gu_final, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
+      sh = th.as<double>();
+      su = tu.as<double>();
+    }
+    launch_permute(r.C[hNb], sh, u.dm.cell_n2o.as<int>(), N, 0, 0, 1, s->stream);
+    launch_permute(r.Ed[uNb], su, u.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
+    r.zero(r.C[cdb], 0, N);
+    const bool nl = s->P.nonlinear();
+    const int nseg = (A.n_steps + K - 1) / K;
+    const size_t per = A.tape_c + A.tape_e;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+      const int t0 = seg * K, t1 = std::min(A.n_steps, t0 + K);
+      const double* c = A.ckpt.as<double>() + (size_t)seg * (N + E);
+      launch_copy(u.st.H[0].as<double>(), c, N, s->stream);
+      launch_copy(u.st.U[0].as<double>(), c + N, E, s->stream);
+      for (int t = t0; t < t1; ++t) {
+        run_passes(A.rec, nl, s->drag_on, false, s->stream, nullptr);
+        launch_copy(A.seg_tape.as<double>() + (size_t)(t - t0) * per, A.step_tape.as<double>(), (long)per, s->stream);
+      }
+      for (int t = t1 - 1; t >= t0; --t) {
+        const double* tc = A.seg_tape.as<double>() + (size_t)(t - t0) * per;
+        r.step(tc, tc + A.tape_c);
+        // the input cotangent of this step is the output cotangent of the previous one
+        launch_copy(r.C[hNb], r.C[hb], N, s->stream);
+        launch_copy(r.Ed[uNb], r.Ed[ub], E, s->stream);
+      }
+    }
+    hip_check(hipGetLastError(), "adjoint launches");
+    // outputs in the caller's numbering
+    auto out = [&](double* dst, const double* src, const int* perm, int n) {
+      if (!dst) return;
+      if (on_device) {
+        launch_permute(dst, src, perm, n, 0, 0, 0, s->stream);
+      } else {
+        DevBuf t;
+        t.alloc((size_t)n * 8);
+        launch_permute(t.as<double>(), src, perm, n, 0, 0, 0, s->stream);
+        hip_check(hipMemcpyAsync(dst, t.p, (size_t)n * 8, hipMemcpyDeviceToHost, s->stream), "memcpy");
+        hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+      }
+    };
+    out(gh0, r.C[hNb], u.dm.cell_n2o.as<int>(), N);
+    out(gu0, r.Ed[uNb], u.dm.edge_n2o.as<int>(), E);
+    out(gcd, r.C[cdb], u.dm.cell_n2o.as<int>(), N);
+    // leave the solver at the final state of the forward run
+    launch_copy(u.st.H[0].as<double>(), A.final_state.as<double>(), N, s->stream);
+    launch_copy(u.st.U[0].as<double>(), A.final_state.as<double>() + N, E, s->stream);
+    init_scratch(u, s->stream);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    return FBLTS_OK;
+  });
+}
+
+int fblts_debug_vjp(fblts_solver* s, int32_t which, const double* h, const double* u, const double* cot, double* hbar,
+                    double* ubar, double* cdbar) {
+  return guarded([&] {
+    if (!s || !h || !u || !cot || !hbar || !ubar) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
+    if (which != 0 && which != 1) throw Err(FBLTS_EINVAL, "which must be 0 (Psi) or 1 (Phi)");
+    if (!s->adj) s->adj = std::make_unique<AdjointState>();
+    AdjointState& A = *s->adj;
+    MeshUnit& U = *s->unit;
+    const int N = U.pm.N, E = U.pm.E;
+    adj_alloc(s, A);
+    Rev r = make_rev(s, A);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    DevBuf th, tu, tc, dh, du;
+    th.alloc((size_t)N * 8);
+    tu.alloc((size_t)E * 8);
+    tc.alloc((size_t)std::max(N, E) * 8);
+    dh.alloc((size_t)N * 8);
+    du.alloc((size_t)E * 8);
+    hip_check(hipMemcpy(th.p, h, (size_t)N * 8, hipMemcpyHostToDevice), "memcpy");
+    hip_check(hipMemcpy(tu.p, u, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
+    hip_check(hipMemcpy(tc.p, cot, (size_t)(which == 0 ? N : E) * 8, hipMemcpyHostToDevice), "memcpy");
+    // inputs into library order: h -> hspt, u -> U3Fb, cotangent -> pb / fb
+    launch_permute(r.C[hspt], th.as<double>(), U.dm.cell_n2o.as<int>(), N, 0, 0, 1, s->stream);
+    launch_permute(r.Ed[U3Fb], tu.as<double>(), U.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
+    r.zero(r.Ed[ub], 0, E);
+    r.zero(r.C[hb], 0, N);
+    r.zero(r.C[cdb], 0, N);
+    if (which == 0) {
+      launch_permute(r.C[pb], tc.as<double>(), U.dm.cell_n2o.as<int>(), N, 0, 0, 1, s->stream);
+      r.psi_vjp(r.Ed[U3Fb], r.C[hspt], r.C[pb], r.Ed[ub], r.C[hb]);
+    } else {
+      launch_permute(r.Ed[fb], tc.as<double>(), U.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
+      r.phi_vjp(r.Ed[U3Fb], r.C[hspt], r.Ed[fb], r.Ed[ub], r.C[hb]);
+    }
+    launch_permute(dh.as<double>(), r.C[hb], U.dm.cell_n2o.as<int>(), N, 0, 0, 0, s->stream);
+    launch_permute(du.as<double>(), r.Ed[ub], U.dm.edge_n2o.as<int>(), E, 0, 0, 0, s->stream);
+    hip_check(hipMemcpyAsync(hbar, dh.p, (size_t)N * 8, hipMemcpyDeviceToHost, s->stream), "memcpy");
+    hip_check(hipMemcpyAsync(ubar, du.p, (size_t)E * 8, hipMemcpyDeviceToHost, s->stream), "memcpy");
+    if (cdbar) {
+      launch_permute(dh.as<double>(), r.C[cdb], U.dm.cell_n2o.as<int>(), N, 0, 0, 0, s->stream);
+      hip_check(hipMemcpyAsync(cdbar, dh.p, (size_t)N * 8, hipMemcpyDeviceToHost, s->stream), "memcpy");
+    }
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     return FBLTS_OK;
   });
 }
