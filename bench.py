@@ -13,7 +13,12 @@ Also reported: the momentum (edge) pass against the HBM roofline, the
 time-to-solution of global FB-RK(3,2) and RK4 at their own largest stable
 steps (the paper's speedup definition), and the oracle timed on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cvt50k|hex32|ensemble]
+Other workloads: sphere400k (the ~400k-cell spherical coastline-refined CVT,
+6 -> 60 km, bathymetry field, drag and a moving analytic cyclone, M = 8; by
+default two simulated days), hex32, ensemble, adjoint.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload cvt50k|sphere400k|hex32|ensemble|adjoint]
 """
 import argparse
 import hashlib
@@ -32,9 +37,9 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 200; sphere400k: two days)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cvt50k", choices=["cvt50k", "hex32", "ensemble"])
+    ap.add_argument("--workload", default="cvt50k", choices=["cvt50k", "sphere400k", "hex32", "ensemble", "adjoint"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the global-scheme comparison")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -74,6 +79,9 @@ def make_solver(F, w, scheme, dt, M, labels=None, graph=True):
     if w.cd is not None and not w.linear:
         s.set_drag(w.cd)
     s.set_state(w.h0, w.u0)
+    storm = w.meta.get("storm")
+    if storm is not None and not w.linear:
+        s.set_cyclone(w.mesh.x_edge, w.mesh.normal_edge, **storm.cyclone_kwargs())
     s.set_graph(graph)
     return s
 
@@ -143,11 +151,13 @@ def cpu_baseline(w, steps):
     from oracle import regions, schemes, trisk
     om = trisk.OMesh(w.mesh)
     lab, _ = regions.layer(om, w.fine_mask, 2)
-    ph = trisk.Physics(linear=w.linear, cd=w.cd if not w.linear else None)
+    storm = w.meta.get("storm")
     u, h = w.u0.copy(), w.h0.copy()
     t0 = time.perf_counter()
     n = 0
     while n < steps:
+        wind = storm.edge_components(w.mesh, n * w.dt) if storm is not None else None
+        ph = trisk.Physics(linear=w.linear, cd=w.cd if not w.linear else None, wind=wind)
         u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
         n += 1
         if time.perf_counter() - t0 > 20.0:
@@ -170,12 +180,23 @@ def main():
     import paper_2405_10505_amd as F
     from paper_2405_10505_amd.inputs import workloads
 
+    if args.steps is None and args.workload != "sphere400k":
+        args.steps = 200
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
     if args.workload == "ensemble":
         return bench_ensemble(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
     t = time.perf_counter()
-    w = workloads.config1() if args.workload == "hex32" else workloads.config2()
+    if args.workload == "hex32":
+        w = workloads.config1()
+    elif args.workload == "sphere400k":
+        w = workloads.config3(progress=log)
+    else:
+        w = workloads.config2()
+    if args.steps is None:
+        args.steps = w.steps
     log("workload %s: N=%d E=%d fine=%d dt=%.3f M=%d (built in %.1fs)" % (
         w.name, w.mesh.n_cells, w.mesh.n_edges, int(w.fine_mask.sum()), w.dt, w.M, time.perf_counter() - t))
     w._fm = F.Mesh(w.mesh)
@@ -278,38 +299,171 @@ def main():
 
 
 def bench_ensemble(args):
+    """Configuration 4: 64 members on the 50k-cell mesh plus 16 members each on
+    20k / 50k / 120k-cell meshes, one launch per pass covering all meshes,
+    hipGraph replay, autotuned schedule; compared with looping the
+    single-member solver over every member on the same GPU."""
     import numpy as np
     import torch
     import paper_2405_10505_amd as F
+    from paper_2405_10505_amd import autotune
     from paper_2405_10505_amd.inputs import workloads
-    # 64 members on the 50k-cell mesh and 16 each on 20k / 50k / 120k-cell meshes
     specs = [(50000, 2, 64), (20000, 20, 16), (50000, 21, 16), (120000, 22, 16)]
     ws = []
     for n, seed, nm in specs:
         t = time.perf_counter()
         w = workloads.config2(n=n, seed_mesh=seed)
         ws.append((w, nm))
-        log("mesh %d (seed %d) built in %.1fs, fine %d" % (n, seed, time.perf_counter() - t, int(w.fine_mask.sum())))
-    # one coarse dt for all meshes: the most restrictive
-    dt = min(w.dt for w, _ in ws)
+        log("mesh %d (seed %d) built in %.1fs, fine %d, dt %.2f" % (n, seed, time.perf_counter() - t,
+                                                                    int(w.fine_mask.sum()), w.dt))
+    dt = min(w.dt for w, _ in ws)   # one coarse step for all meshes: the most restrictive
     fms = [F.Mesh(w.mesh) for w, _ in ws]
     labels = [np.where(w.fine_mask, 0, 1) for w, _ in ws]
     ens = F.Ensemble(fms, labels, [nm for _, nm in ws], dt, M=4, linear=False)
+    inputs = []
     for k, (w, nm) in enumerate(ws):
         fields, cds = workloads.ensemble_members(w.mesh, nm, seed_ssh0=1000 + 100 * k)
+        inputs.append([(w.h0 + fields[m], w.u0, np.full(w.mesh.n_cells, cds[m])) for m in range(nm)])
         for m in range(nm):
-            ens.set_member(k, m, w.h0 + fields[m], w.u0, np.full(w.mesh.n_cells, cds[m]))
-    ens.set_graph(True)
+            ens.set_member(k, m, *inputs[k][m])
+    tune = autotune.autotune(ens, steps=10, repeats=2)
+    log("ensemble schedule: fuse_vertex=%d block=%d" % (tune["fuse_vertex"], tune["block"]))
     info = ens.info()
     el = time_steps(torch, ens, args.steps, args.warmup)
     members = sum(nm for _, nm in ws)
+    ms = el / args.steps * 1e3
+    log("ensemble: %.3f ms per coarse step for %d members, %.3e member-cells" % (ms, members, info["member_cells"]))
+    # the same work as a loop of single-member solvers (time one member per mesh)
+    loop_ms = 0.0
+    per_mesh = []
+    for k, (w, nm) in enumerate(ws):
+        s = F.Solver(fms[k], dt, M=4, linear=False)
+        s.set_regions(labels[k], binary=True)
+        s.set_drag(inputs[k][0][2])
+        s.set_state(inputs[k][0][0], inputs[k][0][1])
+        autotune.autotune(s, steps=10, repeats=2)
+        e = time_steps(torch, s, max(20, args.steps // 4), 5)
+        t1 = e / max(20, args.steps // 4) * 1e3
+        per_mesh.append(dict(n_cells=w.mesh.n_cells, members=nm, single_member_ms=t1))
+        loop_ms += nm * t1
+    # spot check: member 0 of mesh 1 equals the single-member solver (same kernels, same order)
+    chk = F.Solver(fms[1], dt, M=4, linear=False)
+    chk.set_regions(labels[1], binary=True)
+    chk.set_drag(inputs[1][0][2])
+    chk.set_state(inputs[1][0][0], inputs[1][0][1])
+    e2 = F.Ensemble([fms[1]], [labels[1]], [16], dt, M=4, linear=False)
+    for m in range(16):
+        e2.set_member(0, m, *inputs[1][m])
+    e2.set_graph(True)
+    e2.step(10)
+    chk.step(10)
+    he, ue = e2.get_member(0, 0)
+    hc, uc = chk.get_state()
+    same = bool(np.array_equal(he, hc) and np.array_equal(ue, uc))
     out = dict(metric=METRIC, value=members * args.steps / el, unit="member-steps/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=el / args.steps * 1e3, higher_is_better=True, scaling="weak",
+               warmup=args.warmup, ms_per_step=ms, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(workload="ensemble_4meshes_112members", members=members,
-                           member_cells=info["member_cells"], dt=dt, M=4),
+               config=dict(workload="ensemble_4meshes_112members_cvt", members=members,
+                           member_cells=info["member_cells"], dt=dt, M=4, hipgraph=True,
+                           launch_schedule=dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"])),
                cell_substeps_per_s=info["cell_substeps_per_step"] * args.steps / el,
-               model_GBs=info["model_bytes_per_step"] * args.steps / el / 1e9)
+               model_GBs=info["model_bytes_per_step"] * args.steps / el / 1e9,
+               loop_of_single_member_solvers_ms_per_step=loop_ms, speedup_vs_member_loop=loop_ms / ms,
+               per_mesh=per_mesh, member_equals_single_solver_bitwise=same)
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """Configuration 5: reverse mode through 200 FB-LTS coarse steps on the 50k-cell
+    mesh, loss = sum of squared SSH at 50 gauge cells, gradients with respect to
+    h0 and the per-cell drag coefficient, checkpoint every 20 steps; checked by
+    central finite differences on 20 random directions."""
+    import numpy as np
+    import torch
+    import paper_2405_10505_amd as F
+    from paper_2405_10505_amd import autotune
+    from paper_2405_10505_amd.inputs import workloads
+    w = workloads.config2()
+    fm = F.Mesh(w.mesh)
+    n_steps, K = 200, 20
+    rg = workloads.rng_for(9)
+    gauges = np.sort(rg.choice(np.nonzero(w.fine_mask)[0], size=50, replace=False))
+    H = w.mesh.bottom_depth
+    s = F.Solver(fm, w.dt, M=w.M, linear=False)
+    s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+    s.set_drag(w.cd)
+    s.set_state(w.h0, w.u0)
+    tune = autotune.autotune(s, steps=10, repeats=2)
+
+    def loss_of(h0, cd):
+        q = F.Solver(fm, w.dt, M=w.M, linear=False)
+        q.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+        q.set_drag(cd)
+        q.set_state(h0, w.u0)
+        autotune.apply(q, tune)
+        q.step(n_steps)
+        h, _ = q.get_state()
+        return float(np.sum((h[gauges] - H[gauges]) ** 2))
+
+    # forward alone (graph replay)
+    s.set_state(w.h0, w.u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(n_steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    # forward with checkpoints + backward
+    s.set_state(w.h0, w.u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.adjoint_forward(n_steps, K)
+    hN, uN = s.get_state()
+    ghN = np.zeros(w.mesh.n_cells)
+    ghN[gauges] = 2 * (hN[gauges] - H[gauges])
+    t1 = time.perf_counter()
+    gh0, gu0, gcd = s.adjoint_backward(ghN, np.zeros(w.mesh.n_edges))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    L0 = float(np.sum((hN[gauges] - H[gauges]) ** 2))
+    log("adjoint: forward %.3f s, checkpointed forward %.3f s, backward %.3f s, L = %.6e" % (
+        t_fwd, t1 - t0, t2 - t1, L0))
+    # central finite differences on 20 random unit directions in (h0, C_D)
+    rd = workloads.rng_for(10)
+    errs = []
+    t3 = time.perf_counter()
+    for k in range(20):
+        vh = rd.normal(size=w.mesh.n_cells)
+        vc = rd.normal(size=w.mesh.n_cells)
+        nrm = np.sqrt(vh @ vh + (vc @ vc))
+        vh, vc = vh / nrm, vc / nrm
+        # the C_D part of the direction is scaled to C_D's size so both parts are resolved
+        ref = gh0 @ vh + 1e-3 * (gcd @ vc)
+
+        def fd(eps):
+            return (loss_of(w.h0 + eps * vh, w.cd + eps * 1e-3 * vc) -
+                    loss_of(w.h0 - eps * vh, w.cd - eps * 1e-3 * vc)) / (2 * eps)
+        # step sweep with Richardson extrapolation of the O(eps^2) central difference
+        best = np.inf
+        prev = None
+        for eps in (4e-2, 2e-2, 1e-2, 5e-3, 2.5e-3):
+            d = fd(eps)
+            best = min(best, abs(d - ref) / max(abs(ref), 1e-300))
+            if prev is not None:
+                best = min(best, abs((4 * d - prev) / 3 - ref) / max(abs(ref), 1e-300))
+            prev = d
+        errs.append(best)
+    t_fd = (time.perf_counter() - t3) / (20 * 10.0)   # one FD evaluation = one forward run
+    log("finite-difference check, 20 directions: max rel err %.2e (median %.2e)" % (max(errs), np.median(errs)))
+    n_params = 2 * w.mesh.n_cells
+    out = dict(metric=METRIC, value=1.0 / (t2 - t0), unit="gradients/s", n_gpus=1, steps=n_steps, warmup=0,
+               ms_per_step=(t2 - t0) / n_steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload="adjoint_cvt50k_200steps_50gauges", n_params=n_params, ckpt_every=K, M=w.M),
+               forward_s=t_fwd, adjoint_total_s=t2 - t0, backward_s=t2 - t1,
+               adjoint_over_forward=(t2 - t0) / t_fwd,
+               fd_gradient_s_extrapolated=2 * n_params * t_fd,
+               speedup_vs_fd_gradient=2 * n_params * t_fd / (t2 - t0),
+               fd_check=dict(directions=20, max_rel_err=max(errs), median_rel_err=float(np.median(errs))))
     print(json.dumps(out), flush=True)
 
 

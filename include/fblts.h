@@ -164,6 +164,44 @@ int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device);
 int fblts_set_wind(fblts_solver* s, const double* wind_normal, const double* wind_tangential,
                    int32_t on_device);
 
+/* Moving analytic cyclone as the wind of the wind-stress term of eq.
+ * hurricane_model (the paper forces it with observed hurricane winds; this is
+ * the analytic stand-in): a Holland (1980) gradient-wind vortex
+ *   V(r) = sqrt((b/rho_air)(rm/r)^b dp exp(-(rm/r)^b) + (r f/2)^2) - r|f|/2,
+ * f = 2 omega z, r the great-circle distance to the centre, turning
+ * counter-clockwise about the centre where the centre's f > 0, plus a
+ * translation part v_trans V(r)/V(rm, f_centre) along the track.  The centre
+ * starts at `center` and moves about the unit `axis` at angular speed
+ * v_trans/radius.  The wind of the k-th coarse step after this call is
+ * evaluated on the device at t = t0 + k dt before that step's first stage and
+ * held for the whole step (coarse advancement and every fine substep); the
+ * step counter lives on the device, so captured graphs replay correctly.
+ * Components at edges: W.n_e and W.(x_e cross n_e) (the tangent convention of
+ * the mesh, t_e = k x n_e).
+ *   x_edge[3*n_edges]: edge positions (any length; normalised), host, caller order;
+ *   n_edge[3*n_edges]: unit edge normals n_e, host, caller order.
+ * Both are copied.  c = NULL disables the wind (as does fblts_set_wind).
+ * Errors: FBLTS_EINVAL (linear physics, NULL arrays, non-unit or non-tangent
+ * normals, non-finite or non-positive parameters), FBLTS_ESTATE before
+ * set_regions. */
+typedef struct fblts_cyclone {
+  double center[3];   /* initial centre (direction; normalised) */
+  double axis[3];     /* track rotation axis (direction; normalised) */
+  double v_trans;     /* translation speed (m/s) */
+  double dp;          /* central pressure deficit (Pa) */
+  double rm;          /* radius of maximum wind (m) */
+  double b;           /* Holland shape parameter */
+  double rho_air;     /* air density (kg/m^3) */
+  double radius;      /* sphere radius (m) */
+  double omega;       /* rotation rate in f = 2 omega z (1/s) */
+  double t0;          /* time of the first step's wind (s) */
+} fblts_cyclone;
+int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_edge, const double* n_edge);
+/* Copy the wind components the last step used (or the first step will use,
+ * right after fblts_set_cyclone) to host arrays in caller order.
+ * Errors: FBLTS_ESTATE when no wind is set. */
+int fblts_get_wind(fblts_solver* s, double* wind_normal, double* wind_tangential);
+
 /* Advance n coarse steps (async).  Errors: FBLTS_ESTATE before set_state. */
 int fblts_step(fblts_solver* s, int32_t n_coarse_steps);
 /* Capture one coarse step in a hipGraph and replay it in fblts_step (1), or

@@ -51,6 +51,11 @@ class fblts_diag(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class fblts_cyclone(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("axis", C.c_double * 3)] + [
+        (k, C.c_double) for k in ("v_trans", "dp", "rm", "b", "rho_air", "radius", "omega", "t0")]
+
+
 class fblts_info(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_cells", "n_edges", "n_vertices", "n_fine", "n_if1", "n_if2", "n_int",
                                          "n_fine_e", "n_if1_e", "n_if2_e", "n_int_e", "max_edges", "max_eoe")] + \
@@ -77,6 +82,8 @@ _SIGS = {
     "fblts_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_set_drag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_set_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_set_cyclone": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fblts_get_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fblts_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
@@ -244,6 +251,30 @@ class Solver:
         pn, dn, kn = _ptr(wn, np.float64)
         pt, dt, kt = _ptr(wt, np.float64)
         _check(lib().fblts_set_wind(self.handle, pn, pt, dn))
+
+    def set_cyclone(self, x_edge, n_edge, center, axis, v_trans=5.0, dp=6000.0, rm=40e3, b=1.5,
+                    rho_air=1.15, radius=6.371229e6, omega=7.292e-5, t0=0.0):
+        """Moving Holland cyclone as the wind-stress forcing (device-evaluated per coarse step)."""
+        c = fblts_cyclone()
+        for k in range(3):
+            c.center[k] = float(center[k])
+            c.axis[k] = float(axis[k])
+        c.v_trans, c.dp, c.rm, c.b, c.rho_air = v_trans, dp, rm, b, rho_air
+        c.radius, c.omega, c.t0 = radius, omega, t0
+        x = np.ascontiguousarray(x_edge, dtype=np.float64).reshape(-1)
+        n = np.ascontiguousarray(n_edge, dtype=np.float64).reshape(-1)
+        if x.size != 3 * self.mesh.n_edges or n.size != 3 * self.mesh.n_edges:
+            raise ValueError("x_edge and n_edge must hold 3 values per edge")
+        _check(lib().fblts_set_cyclone(self.handle, C.byref(c), x.ctypes.data, n.ctypes.data))
+
+    def clear_wind(self):
+        _check(lib().fblts_set_cyclone(self.handle, None, None, None))
+
+    def get_wind(self):
+        wn = np.empty(self.mesh.n_edges)
+        wt = np.empty(self.mesh.n_edges)
+        _check(lib().fblts_get_wind(self.handle, wn.ctypes.data, wt.ctypes.data))
+        return wn, wt
 
     def step(self, n=1):
         _check(lib().fblts_step(self.handle, int(n)))

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfblts.so")
-SOURCES = ["csrc/kernels.hip", "csrc/adjoint.hip", "csrc/solver.hip", "csrc/mesh_plan.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/adjoint.hip", "csrc/forcing.hip", "csrc/solver.hip", "csrc/mesh_plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

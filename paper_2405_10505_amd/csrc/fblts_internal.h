@@ -140,6 +140,19 @@ struct AsmSeg {
   double delta;
 };
 
+// Cyclone wind at edges for the wind-stress term: Holland vortex on a
+// great-circle track, evaluated at t = t0 + clock[0] * dt.
+struct CycloneArgs {
+  const double* x;          // [3][E] unit edge positions
+  const double* n;          // [3][E] unit edge normals
+  double* wn;               // [E] W . n_e
+  double* wt;               // [E] W . (x cross n_e)
+  const long long* clock;   // coarse steps since the storm was set
+  int E;
+  double c0[3], axis[3];
+  double v_trans, dp, rm, b, rho_air, radius, omega, t0, dt, omega_track;
+};
+
 template <class S>
 struct Launch {
   int nseg;

@@ -39,6 +39,8 @@ void launch_permute(double* dst, const double* src, const int* perm, int n, int 
                     hipStream_t st);
 void launch_copy(double* dst, const double* src, long n, hipStream_t st);
 void launch_fill(double* dst, double v, long n, hipStream_t st);
+void launch_cyclone(const CycloneArgs& a, hipStream_t st);
+void launch_clock_tick(long long* clock, hipStream_t st);
 int diag_blocks(const MeshDev& m);
 void launch_diag(const MeshDev& m, int nm_log2, int linear, const double* h, const double* u, double g,
                  double* partial, double* out, hipStream_t st);
@@ -197,6 +199,10 @@ struct DevState {
   DevBuf U[4], acc_u, sv_u, P, q;
   DevBuf wind_n, wind_t;
   bool has_wind = false;
+  // moving cyclone: wind evaluated on the device once per coarse step
+  DevBuf cyc_x, cyc_n, cyc_clock;
+  bool cyclone = false;
+  CycloneArgs cyc{};
   void alloc(const PermMesh& pm, const Plan& p, int nm_) {
     nm = nm_;
     nm_log2 = 0;
@@ -219,7 +225,7 @@ struct DevState {
 };
 
 struct Pass {
-  enum Kind { CELL, VERT, PREP, EDGE, PRED, ASM, RK4FIN, COPY } kind;
+  enum Kind { CELL, VERT, PREP, EDGE, PRED, ASM, RK4FIN, COPY, WIND, TICK } kind;
   // position in the step: 100*phase + 10*substep + stage (phase 0 coarse, 1 fine,
   // 2 prediction, 3 assembly); used to place the adjoint's tape snapshots
   int tag = 0;
@@ -232,6 +238,8 @@ struct Pass {
   Launch<EdgeSeg> edge;
   Launch<PredSeg> pred;
   Launch<AsmSeg> asmb;
+  CycloneArgs cyc{};               // WIND
+  long long* clock = nullptr;      // TICK
   // RK4 final: per segment (y, acc, n)
   std::vector<std::tuple<double*, const double*, long>> fin;
   double fin_c = 0.0;
@@ -513,8 +521,26 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
   u.cell_substeps = ((int64_t)(N - pl.nF) + (int64_t)M * pl.nF) * nm;
 }
 
+// With a moving cyclone, each coarse step starts by evaluating the wind at
+// the step's time and ends by advancing the device step clock.
+void add_forcing_passes(MeshUnit& u) {
+  if (!u.st.cyclone) return;
+  Pass w;
+  w.kind = Pass::WIND;
+  w.tag = -1;
+  w.cyc = u.st.cyc;
+  w.model_bytes = (double)u.pm.E * 8.0 * 8.0;
+  Pass t;
+  t.kind = Pass::TICK;
+  t.tag = -2;
+  t.clock = u.st.cyc_clock.as<long long>();
+  u.passes.insert(u.passes.begin(), w);
+  u.passes.push_back(t);
+}
+
 void build_passes(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, int bs) {
   build_passes_impl(u, P, drag_on, fuse_q);
+  add_forcing_passes(u);
   for (Pass& p : u.passes) p.bs = bs;
 }
 
@@ -542,7 +568,9 @@ std::vector<Pass> merge_passes(const std::vector<MeshUnit*>& units) {
         case Pass::RK4FIN:
           for (auto& t : q.fin) ps.fin.push_back(t);
           break;
-        case Pass::COPY: break;
+        case Pass::COPY:
+        case Pass::WIND:
+        case Pass::TICK: break;
       }
       ps.model_bytes += q.model_bytes;
     }
@@ -601,6 +629,8 @@ void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool
         for (auto& t : ps.fin) launch_axpy_final(std::get<0>(t), std::get<1>(t), ps.fin_c, std::get<2>(t), st);
         break;
       case Pass::COPY: launch_copy(ps.cdst, ps.csrc, ps.cn, st); break;
+      case Pass::WIND: launch_cyclone(ps.cyc, st); break;
+      case Pass::TICK: launch_clock_tick(ps.clock, st); break;
     }
     if (evp.first) hip_check(hipEventRecord(evp.second, st), "hipEventRecord");
   }
@@ -1127,6 +1157,7 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
     MeshUnit& u = *s->unit;
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->drop_graph();
+    u.st.cyclone = false;
     if (!wn || !wt) {
       u.st.has_wind = false;
     } else {
@@ -1154,6 +1185,106 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
       u.st.has_wind = true;
     }
     build_passes(u, s->P, s->drag_on, s->fuse_q, s->block);
+    return FBLTS_OK;
+  });
+}
+
+int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_edge, const double* n_edge) {
+  return guarded([&] {
+    if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
+    if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
+    MeshUnit& u = *s->unit;
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->drop_graph();
+    if (!c) {
+      u.st.cyclone = false;
+      u.st.has_wind = false;
+    } else {
+      if (!s->P.nonlinear()) throw Err(FBLTS_EINVAL, "wind stress needs nonlinear physics");
+      if (!x_edge || !n_edge) throw Err(FBLTS_EINVAL, "edge positions and normals are required");
+      const double vals[] = {c->v_trans, c->dp, c->rm, c->b, c->rho_air, c->radius, c->omega, c->t0};
+      for (double v : vals)
+        if (!std::isfinite(v)) throw Err(FBLTS_EINVAL, "cyclone parameters must be finite");
+      if (!(c->rm > 0) || !(c->b > 0) || !(c->rho_air > 0) || !(c->radius > 0) || !(c->dp >= 0))
+        throw Err(FBLTS_EINVAL, "cyclone: rm, b, rho_air, radius must be positive and dp non-negative");
+      auto unit3 = [](const double* v, double* o, const char* what) {
+        const double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (!(l > 0) || !std::isfinite(l)) throw Err(FBLTS_EINVAL, std::string("cyclone: zero or non-finite ") + what);
+        for (int k = 0; k < 3; ++k) o[k] = v[k] / l;
+      };
+      CycloneArgs a{};
+      unit3(c->center, a.c0, "centre");
+      unit3(c->axis, a.axis, "track axis");
+      const int E = u.pm.E;
+      std::vector<double> hx((size_t)3 * E), hn((size_t)3 * E);
+      for (int i = 0; i < E; ++i) {
+        const int o = u.plan.edge_new2old[i];
+        double xu[3];
+        unit3(x_edge + 3 * (size_t)o, xu, "edge position");
+        const double* nv = n_edge + 3 * (size_t)o;
+        const double nl = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        const double nx = nv[0] * xu[0] + nv[1] * xu[1] + nv[2] * xu[2];
+        if (!(std::fabs(nl - 1.0) < 1e-6) || !(std::fabs(nx) < 1e-6))
+          throw Err(FBLTS_EINVAL, "cyclone: edge normals must be unit vectors tangent to the sphere");
+        for (int k = 0; k < 3; ++k) {
+          hx[(size_t)k * E + i] = xu[k];
+          hn[(size_t)k * E + i] = nv[k];
+        }
+      }
+      u.st.cyc_x.alloc(hx.size() * 8);
+      u.st.cyc_n.alloc(hn.size() * 8);
+      u.st.cyc_clock.alloc(8);
+      if (u.st.wind_n.bytes < (size_t)E * 8) {
+        u.st.wind_n.alloc((size_t)E * 8);
+        u.st.wind_t.alloc((size_t)E * 8);
+      }
+      const long long zero = 0;
+      hip_check(hipMemcpy(u.st.cyc_x.p, hx.data(), hx.size() * 8, hipMemcpyHostToDevice), "memcpy");
+      hip_check(hipMemcpy(u.st.cyc_n.p, hn.data(), hn.size() * 8, hipMemcpyHostToDevice), "memcpy");
+      hip_check(hipMemcpy(u.st.cyc_clock.p, &zero, 8, hipMemcpyHostToDevice), "memcpy");
+      a.x = u.st.cyc_x.as<double>();
+      a.n = u.st.cyc_n.as<double>();
+      a.wn = u.st.wind_n.as<double>();
+      a.wt = u.st.wind_t.as<double>();
+      a.clock = u.st.cyc_clock.as<long long>();
+      a.E = E;
+      a.v_trans = c->v_trans;
+      a.dp = c->dp;
+      a.rm = c->rm;
+      a.b = c->b;
+      a.rho_air = c->rho_air;
+      a.radius = c->radius;
+      a.omega = c->omega;
+      a.t0 = c->t0;
+      a.dt = s->P.p.dt;
+      a.omega_track = c->v_trans / c->radius;
+      u.st.cyc = a;
+      u.st.cyclone = true;
+      u.st.has_wind = true;
+      // wind of the first step, so that the state is complete before any step
+      launch_cyclone(a, s->stream);
+      hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    }
+    build_passes(u, s->P, s->drag_on, s->fuse_q, s->block);
+    return FBLTS_OK;
+  });
+}
+
+int fblts_get_wind(fblts_solver* s, double* wn, double* wt) {
+  return guarded([&] {
+    if (!s || !wn || !wt) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (!s->have_regions || !s->unit->st.has_wind) throw Err(FBLTS_ESTATE, "no wind is set");
+    MeshUnit& u = *s->unit;
+    const int E = u.pm.E;
+    std::vector<double> a(E), b(E);
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    hip_check(hipMemcpy(a.data(), u.st.wind_n.p, (size_t)E * 8, hipMemcpyDeviceToHost), "memcpy");
+    hip_check(hipMemcpy(b.data(), u.st.wind_t.p, (size_t)E * 8, hipMemcpyDeviceToHost), "memcpy");
+    for (int i = 0; i < E; ++i) {
+      const int o = u.plan.edge_new2old[i];
+      wn[o] = a[i];
+      wt[o] = b[i];
+    }
     return FBLTS_OK;
   });
 }

@@ -543,7 +543,7 @@ def lloyd_sphere(pts, density, iters):
             p2 = 0.5 * (p0 + pts[s[:, (k + 2) % 3]])
             for q1, q2 in ((p1, cc), (cc, p2)):
                 q1n, q2n = _normalize(q1), _normalize(q2)
-                ar = np.abs(_sph_tri_area(p0, q1n, q2n))
+                ar = _sph_tri_area(p0, q1n, q2n)      # signed: exact decomposition for obtuse triangles
                 cen = _normalize(p0 + q1n + q2n)
                 w = ar * density(cen)
                 for d in range(3):
@@ -552,8 +552,16 @@ def lloyd_sphere(pts, density, iters):
     return pts
 
 
+def refine_midpoints(pts):
+    """Add the midpoint of every Delaunay edge: N -> 4N - 6 points, each triangle split into four."""
+    s = ConvexHull(pts).simplices
+    e = np.concatenate([s[:, [0, 1]], s[:, [1, 2]], s[:, [2, 0]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    return np.concatenate([pts, _normalize(pts[e[:, 0]] + pts[e[:, 1]])])
+
+
 def sphere_from_generators(pts, radius=EARTH_RADIUS, omega=OMEGA, depth=4000.0):
-    """TRiSK mesh of the spherical Voronoi diagram of unit vectors ``pts``."""
+    """TRiSK mesh of the spherical Voronoi diagram of unit vectors ``pts`` (vectorised)."""
     pts = _normalize(np.asarray(pts, dtype=np.float64))
     n = pts.shape[0]
     hull = ConvexHull(pts)
@@ -564,17 +572,20 @@ def sphere_from_generators(pts, radius=EARTH_RADIUS, omega=OMEGA, depth=4000.0):
     a, b, c = pts[s[:, 0]], pts[s[:, 1]], pts[s[:, 2]]
     cc = _normalize(np.cross(b - a, c - a))
     nv = s.shape[0]
-    # edges from triangle sides
-    edge_tris = {}
-    for t in range(nv):
-        for k in range(3):
-            u, v = int(s[t, (k + 1) % 3]), int(s[t, (k + 2) % 3])
-            key = (u, v) if u < v else (v, u)
-            edge_tris.setdefault(key, []).append(t)
-    keys = list(edge_tris.keys())
-    ne = len(keys)
-    coe = np.array(keys, dtype=np.int32)
-    t12 = np.array([edge_tris[k] for k in keys], dtype=np.int64)
+    # edges: each triangle side, deduplicated; every edge borders exactly two triangles
+    u = np.concatenate([s[:, 1], s[:, 2], s[:, 0]])
+    v = np.concatenate([s[:, 2], s[:, 0], s[:, 1]])
+    tri = np.tile(np.arange(nv), 3)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    key = lo.astype(np.int64) * n + hi
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    if np.any(ks[0::2] != ks[1::2]):
+        raise RuntimeError("spherical Delaunay: an edge does not border exactly two triangles")
+    coe = np.stack([lo[order][0::2], hi[order][0::2]], 1).astype(np.int32)
+    t12 = np.stack([tri[order][0::2], tri[order][1::2]], 1)
+    ekeys = ks[0::2]
+    ne = coe.shape[0]
     pa, pb = pts[coe[:, 0]], pts[coe[:, 1]]
     xe = _normalize(pa + pb)
     nvec = _normalize(pb - pa - np.einsum("ij,ij->i", pb - pa, xe)[:, None] * xe)
@@ -592,50 +603,35 @@ def sphere_from_generators(pts, radius=EARTH_RADIUS, omega=OMEGA, depth=4000.0):
         M1 = _normalize(P0 + pts[s[:, (k + 1) % 3]])
         M2 = _normalize(P0 + pts[s[:, (k + 2) % 3]])
         kites[:, k] = (_sph_tri_area(P0, M1, cc) + _sph_tri_area(P0, cc, M2)) * radius ** 2
-    pair_edge = {}
-    for e in range(ne):
-        u, v = int(coe[e, 0]), int(coe[e, 1])
-        for t in voe[e]:
-            pair_edge[(min(u, v), max(u, v), int(t))] = e
+    # edges on vertex: edge j joins cells_on_vertex j and j+1
     eov = np.zeros((nv, 3), np.int32)
-    for vi in range(nv):
-        for j in range(3):
-            u, v = int(cov[vi, j]), int(cov[vi, (j + 1) % 3])
-            eov[vi, j] = pair_edge[(min(u, v), max(u, v), vi)]
-    # ccw ordering around each cell in its local tangent frame
-    cell_edges = [[] for _ in range(n)]
-    cell_verts = [[] for _ in range(n)]
-    for e in range(ne):
-        for side, cid in enumerate(coe[e]):
-            cell_edges[cid].append(e)
-    for vi in range(nv):
-        for j in range(3):
-            cell_verts[cov[vi, j]].append(vi)
-    eoc_off = np.zeros(n + 1, np.int32)
-    eoc, voc = [], []
+    for j in range(3):
+        x, y = cov[:, j].astype(np.int64), cov[:, (j + 1) % 3].astype(np.int64)
+        q = np.minimum(x, y) * n + np.maximum(x, y)
+        eov[:, j] = np.searchsorted(ekeys, q)
+    # counter-clockwise edges of each cell: angle of the Voronoi-edge midpoint in the cell's tangent frame
     vmid = _normalize(cc[voe[:, 0]] + cc[voe[:, 1]])
-    for i in range(n):
-        p = pts[i]
-        ex = np.cross(np.array([0.0, 0.0, 1.0]) if abs(p[2]) < 0.9 else np.array([1.0, 0.0, 0.0]), p)
-        ex /= np.linalg.norm(ex)
-        ey = np.cross(p, ex)
-        es = cell_edges[i]
-        vs = cell_verts[i]
-        ang_e = [math.atan2(np.dot(vmid[e] - p, ey), np.dot(vmid[e] - p, ex)) for e in es]
-        ang_v = [math.atan2(np.dot(cc[v] - p, ey), np.dot(cc[v] - p, ex)) for v in vs]
-        oe = np.argsort(ang_e)
-        ov = np.argsort(ang_v)
-        ea = np.array(ang_e)[oe]
-        va = np.array(ang_v)[ov]
-        es = [es[k] for k in oe]
-        vs = [vs[k] for k in ov]
-        k0 = int(np.searchsorted(va, ea[0], side="right")) % len(vs)
-        vs = vs[k0:] + vs[:k0]
-        eoc.extend(es)
-        voc.extend(vs)
-        eoc_off[i + 1] = len(eoc)
-    eoc = np.array(eoc, np.int32)
-    voc = np.array(voc, np.int32)
+    cell_of = np.concatenate([coe[:, 0], coe[:, 1]]).astype(np.int64)
+    edge_of = np.concatenate([np.arange(ne), np.arange(ne)])
+    p = pts[cell_of]
+    ref = np.where(np.abs(p[:, 2:3]) < 0.9, np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]]))
+    ex = _normalize(np.cross(ref, p))
+    ey = np.cross(p, ex)
+    d = vmid[edge_of] - p
+    ang = np.arctan2(np.einsum("ij,ij->i", d, ey), np.einsum("ij,ij->i", d, ex))
+    o = np.lexsort((ang, cell_of))
+    eoc = edge_of[o].astype(np.int32)
+    deg = np.bincount(cell_of, minlength=n)
+    eoc_off = np.zeros(n + 1, np.int32)
+    eoc_off[1:] = np.cumsum(deg)
+    # vertex j: the vertex shared by edges j and j+1 of the cell
+    nxt = np.arange(eoc.size) + 1
+    ends = eoc_off[1:] - 1
+    nxt[ends] = eoc_off[:-1]
+    e0, e1 = eoc, eoc[nxt]
+    a0, a1 = voe[e0, 0], voe[e0, 1]
+    b0, b1 = voe[e1, 0], voe[e1, 1]
+    voc = np.where((a0 == b0) | (a0 == b1), a0, a1).astype(np.int32)
     area_cell = np.zeros(n)
     np.add.at(area_cell, cov.reshape(-1), kites.reshape(-1))
     area_tri = kites.sum(axis=1)
@@ -651,11 +647,21 @@ def sphere_from_generators(pts, radius=EARTH_RADIUS, omega=OMEGA, depth=4000.0):
         edges_on_vertex=eov, cells_on_vertex=cov, kite_areas_on_vertex=kites,
         dc_edge=dc, dv_edge=dv, area_cell=area_cell, area_triangle=area_tri,
         f_vertex=2 * omega * np.sin(lat_v), f_edge=2 * omega * np.sin(lat_e),
-        bottom_depth=np.full(n, depth),
+        bottom_depth=np.full(n, depth) if np.isscalar(depth) else np.asarray(depth, float),
         is_sphere=1, sphere_radius=radius,
         x_cell=pts * radius, x_edge=xe * radius, x_vertex=cc * radius,
         normal_edge=nvec, tangent_edge=tvec,
     )
+
+
+def morton_order_sphere(pts, bits=16):
+    """Permutation sorting unit vectors along a 3-D Morton curve (locality ordering)."""
+    q = np.clip(((pts + 1.0) * 0.5 * ((1 << bits) - 1)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(pts.shape[0], dtype=np.int64)
+    for bit in range(bits):
+        for k in range(3):
+            code |= ((q[:, k] >> bit) & 1) << (3 * bit + k)
+    return np.argsort(code, kind="stable")
 
 
 def fibonacci_sphere(n):

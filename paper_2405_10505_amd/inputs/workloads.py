@@ -178,3 +178,144 @@ def ensemble_members(mesh, n_members, seed_ssh0=1000, seed_cd=8, sigma=0.05, cor
         fld = np.sqrt(2.0 / n_modes) * np.cos(np.outer(x, kx) + np.outer(y, ky) + ph).sum(axis=1)
         fields.append(sigma * fld)
     return fields, cds
+
+
+# ----------------------------------------------------------------------------
+# configuration 3: spherical coastline-refined CVT, bathymetry field, cyclone
+# ----------------------------------------------------------------------------
+
+def _smoothstep(x):
+    x = np.clip(x, 0.0, 1.0)
+    return x * x * (3.0 - 2.0 * x)
+
+
+class Coastline:
+    """Seeded perturbed small circle (angular radius 20 deg, 6 Fourier modes)."""
+
+    def __init__(self, seed, radius_deg=20.0, modes=6, amp=0.04):
+        r = rng_for(seed)
+        c0 = r.normal(size=3)
+        c0[2] = abs(c0[2]) + 0.5          # keep the storm region in the northern hemisphere
+        self.c0 = c0 / np.linalg.norm(c0)
+        e1 = np.cross(self.c0, [0.0, 0.0, 1.0])
+        self.e1 = e1 / np.linalg.norm(e1)
+        self.e2 = np.cross(self.c0, self.e1)
+        self.rho0 = math.radians(radius_deg)
+        self.a = r.uniform(0, amp, size=modes)
+        self.ph = r.uniform(0, 2 * math.pi, size=modes)
+
+    def angular_distance(self, x):
+        theta = np.arccos(np.clip(x @ self.c0, -1, 1))
+        phi = np.arctan2(x @ self.e2, x @ self.e1)
+        m = np.arange(1, self.a.size + 1)
+        rho = self.rho0 * (1 + (self.a[None, :] * np.cos(np.outer(phi, m) + self.ph[None, :])).sum(axis=1))
+        return np.abs(theta - rho)
+
+
+def sphere_dx_factory(coast, n_target, radius=meshgen.EARTH_RADIUS, dx_fine=6e3, dx_coarse=60e3, nq=200000):
+    """dx(x) = fine + (coarse - fine) smoothstep(d / D), D solved for n_target cells."""
+    q = meshgen.fibonacci_sphere(nq)
+    dq = coast.angular_distance(q) * radius
+    area = 4 * math.pi * radius ** 2 / nq
+
+    def count(D):
+        dx = dx_fine + (dx_coarse - dx_fine) * _smoothstep(dq / D)
+        return np.sum(area / (math.sqrt(3) / 2 * dx * dx))
+
+    lo, hi = 1e3, 2e7
+    for _ in range(80):
+        mid = math.sqrt(lo * hi)
+        if count(mid) < n_target:
+            lo = mid
+        else:
+            hi = mid
+    D = 0.5 * (lo + hi)
+
+    def dx(x):
+        return dx_fine + (dx_coarse - dx_fine) * _smoothstep(coast.angular_distance(x) * radius / D)
+    return dx, D
+
+
+def gaussian_field_sphere(x, seed, mean, std, corr, radius=meshgen.EARTH_RADIUS, n_modes=256):
+    """Smooth random field on the sphere: random Fourier features of the embedding coordinates."""
+    r = rng_for(seed)
+    k = r.normal(0, 1.0 / corr, size=(n_modes, 3))
+    ph = r.uniform(0, 2 * math.pi, n_modes)
+    fld = np.sqrt(2.0 / n_modes) * np.cos((x * radius) @ k.T + ph).sum(axis=1)
+    return mean + std * fld
+
+
+_SPHERE_CACHE = {}
+
+
+def sphere_mesh(n=400000, seed_coast=5, iters=20, dx_fine=6e3, dx_coarse=60e3, progress=None):
+    """Spherical CVT refined near the seeded coastline.
+
+    Multilevel construction: generators drawn with density ~ dx^-2 at
+    n0 = (n + 30) / 16 points (or n when that is small), density-weighted Lloyd
+    iterations (density dx^-4), then per level the Delaunay edge midpoints are
+    added (N -> 4N - 6, halving the spacing everywhere) and the Lloyd sweeps are
+    repeated; the final generators are sorted along a Morton curve."""
+    key = (n, seed_coast, iters, dx_fine, dx_coarse)
+    if key in _SPHERE_CACHE:
+        return _SPHERE_CACHE[key]
+    coast = Coastline(seed_coast)
+    dx, D = sphere_dx_factory(coast, n, dx_fine=dx_fine, dx_coarse=dx_coarse)
+    levels = 0
+    n0 = n
+    while n0 > 80000:
+        n0 = (n0 + 6) // 4
+        levels += 1
+    r = rng_for(seed_coast + 1000)
+    pts = []
+    need = n0
+    while need > 0:
+        cand = meshgen._normalize(r.normal(size=(need * 8, 3)))
+        acc = r.uniform(size=cand.shape[0]) < (dx_fine / dx(cand)) ** 2
+        got = cand[acc][:need]
+        pts.append(got)
+        need -= got.shape[0]
+    pts = np.concatenate(pts)
+    density = lambda x: dx(x) ** -4   # noqa: E731
+    for lev in range(levels + 1):
+        if lev > 0:
+            pts = meshgen.refine_midpoints(pts)
+        its = iters if lev == 0 else max(3, iters // 4)
+        for it in range(its):
+            pts = meshgen.lloyd_sphere(pts, density, 1)
+            if progress:
+                progress("sphere level %d (%d points) Lloyd %d/%d" % (lev, pts.shape[0], it + 1, its))
+    pts = pts[meshgen.morton_order_sphere(pts)]
+    m = meshgen.sphere_from_generators(pts)
+    m.meta.update(kind="sphere", n=m.n_cells, seed=seed_coast, iters=iters, levels=levels, D=D)
+    m.meta["coast"] = coast
+    _SPHERE_CACHE[key] = m
+    return m
+
+
+def config3(n=400000, M=8, seed_coast=5, seed_bathy=6, seed_track=7, iters=20, cd=2.5e-3, dx_fine=6e3,
+            dx_coarse=60e3, progress=None):
+    """Spherical CVT refined 60 -> 6 km near a seeded coastline, bathymetry field in [10, 5000] m,
+    quadratic drag, Holland cyclone wind stress along a seeded great-circle track, M = 8."""
+    from . import forcing
+    base = sphere_mesh(n, seed_coast, iters, dx_fine, dx_coarse, progress)
+    xc = base.x_cell / base.sphere_radius
+    H = np.clip(gaussian_field_sphere(xc, seed_bathy, 3000.0, 1500.0, 500e3), 10.0, 5000.0)
+    mesh = base.copy_with(bottom_depth=H)
+    h0 = H.copy()
+    u0 = np.zeros(mesh.n_edges)
+    fine, dt_c, dt_f = cfl_fine_mask(mesh, M)
+    coast = base.meta["coast"]
+    # the storm starts 6 degrees outside the mean coastline and heads for its centre
+    storm = forcing.seeded_track(seed_track, target=coast.c0, start_distance=coast.rho0 + math.radians(6.0),
+                                 radius=base.sphere_radius)
+    steps = int(math.ceil(2 * 86400.0 / dt_c))      # two simulated days
+    return Workload("sphere%dk_cyclone" % (round(mesh.n_cells / 1000)), mesh, h0, u0, fine, dt_c, M, False,
+                    np.full(mesh.n_cells, cd), steps, dict(dt_fine=dt_f, n_fine=int(fine.sum()), storm=storm,
+                                                         seeds=(seed_coast, seed_bathy, seed_track)))
+
+
+def small_sphere(n=3000, M=4, iters=20):
+    """Configuration-3 recipe at test size: the same construction with the
+    resolution range scaled to the cell count (200 -> 600 km)."""
+    return config3(n=n, M=M, iters=iters, dx_fine=200e3, dx_coarse=600e3)
