@@ -252,10 +252,14 @@ int fblts_get_info(fblts_solver* s, fblts_info* out);
 int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const double* u,
                          double* out, int32_t on_device);
 
-/* Timing export: event-timed average duration (ms) of the kernels of one
+/* Timing export: average duration (ms) per launch of the kernels of one
  * class launched during the last fblts_step: 0 = momentum (edge) passes,
  * 1 = thickness (cell) passes, 2 = vertex passes, 3 = edge-prep passes.
- * Requires fblts_set_timing(s,1) before the step; synchronises. */
+ * With timing enabled (fblts_set_timing(s,1)) steps launch directly (no
+ * graph) and every pass of these classes records a pair of HIP events from
+ * its own dispatch (kernel start and end timestamps, hipExtLaunchKernel), so
+ * the figure is the kernels' execution time inside the step sequence.
+ * Synchronises. */
 int fblts_set_timing(fblts_solver* s, int32_t enable);
 int fblts_kernel_time(fblts_solver* s, int32_t kernel_class, double* avg_ms, int64_t* launches);
 /* Timing export: launch every pass of one class of the current step program

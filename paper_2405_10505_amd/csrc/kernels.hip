@@ -15,6 +15,7 @@
 // member index fastest, blocks are remapped so that each XCD works on a
 // contiguous slice of the range (its L2 then holds that slice's neighbours),
 // and every value has exactly one writer (no atomics; bitwise deterministic).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "fblts_internal.h"
@@ -474,37 +475,57 @@ static long asm_items(const AsmSeg& s) {
   return ((long)(s.N - s.if1_c_begin) + (long)(s.E - s.if1_e_begin)) << s.nm_log2;
 }
 
+// Kernel timing: when a pair of events is armed, the next stencil-pass launch
+// records them from its own dispatch (start and end timestamps of the kernel,
+// no marker packets in between), then the pair is disarmed.
+static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+void arm_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+
+template <typename F, typename... A>
+static void launch_timed(F kernel, int nb, int bs, hipStream_t st, A... args) {
+  if (g_ev_start) {
+    hipExtLaunchKernelGGL(kernel, dim3(nb), dim3(bs), 0, st, g_ev_start, g_ev_stop, 0, args...);
+    g_ev_start = g_ev_stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, dim3(nb), dim3(bs), 0, st, args...);
+  }
+}
+
 // Each launcher returns the number of blocks launched (0: nothing to do).
 int launch_cell(Launch<CellSeg> L, bool nonlinear, int bs, hipStream_t st) {
   const int nb = blocks_for(L, cell_items, bs);
   if (nb == 0) return 0;
-  if (nonlinear) hipLaunchKernelGGL(k_cell<true>, dim3(nb), dim3(bs), 0, st, L);
-  else hipLaunchKernelGGL(k_cell<false>, dim3(nb), dim3(bs), 0, st, L);
+  if (nonlinear) launch_timed(k_cell<true>, nb, bs, st, L);
+  else launch_timed(k_cell<false>, nb, bs, st, L);
   return nb;
 }
 
 int launch_vertex(Launch<VertSeg> L, int bs, hipStream_t st) {
   const int nb = blocks_for(L, vert_items, bs);
   if (nb == 0) return 0;
-  hipLaunchKernelGGL(k_vertex, dim3(nb), dim3(bs), 0, st, L);
+  launch_timed(k_vertex, nb, bs, st, L);
   return nb;
 }
 
 int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st) {
   const int nb = blocks_for(L, prep_items, bs);
   if (nb == 0) return 0;
-  if (fuse_q) hipLaunchKernelGGL(k_prep<true>, dim3(nb), dim3(bs), 0, st, L);
-  else hipLaunchKernelGGL(k_prep<false>, dim3(nb), dim3(bs), 0, st, L);
+  if (fuse_q) launch_timed(k_prep<true>, nb, bs, st, L);
+  else launch_timed(k_prep<false>, nb, bs, st, L);
   return nb;
 }
 
 int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st) {
   const int nb = blocks_for(L, edge_items, bs);
   if (nb == 0) return 0;
-  if (drag && wind) hipLaunchKernelGGL((k_edge<true, true>), dim3(nb), dim3(bs), 0, st, L);
-  else if (drag) hipLaunchKernelGGL((k_edge<true, false>), dim3(nb), dim3(bs), 0, st, L);
-  else if (wind) hipLaunchKernelGGL((k_edge<false, true>), dim3(nb), dim3(bs), 0, st, L);
-  else hipLaunchKernelGGL((k_edge<false, false>), dim3(nb), dim3(bs), 0, st, L);
+  if (drag && wind) launch_timed(k_edge<true, true>, nb, bs, st, L);
+  else if (drag) launch_timed(k_edge<true, false>, nb, bs, st, L);
+  else if (wind) launch_timed(k_edge<false, true>, nb, bs, st, L);
+  else launch_timed(k_edge<false, false>, nb, bs, st, L);
   return nb;
 }
 

@@ -40,6 +40,7 @@ void launch_permute(double* dst, const double* src, const int* perm, int n, int 
 void launch_copy(double* dst, const double* src, long n, hipStream_t st);
 void launch_fill(double* dst, double v, long n, hipStream_t st);
 void launch_cyclone(const CycloneArgs& a, hipStream_t st);
+void arm_launch_events(hipEvent_t start, hipEvent_t stop);
 void launch_clock_tick(long long* clock, hipStream_t st);
 int diag_blocks(const MeshDev& m);
 void launch_diag(const MeshDev& m, int nm_log2, int linear, const double* h, const double* u, double g,
@@ -599,6 +600,7 @@ struct Timing {
     }
     return ev[cls][used[cls]++];
   }
+  void unget(int cls) { --used[cls]; }
   void reset() { std::fill(used, used + 4, 0); }
 };
 
@@ -613,16 +615,18 @@ void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool
       case Pass::PREP: cls = 3; break;
       default: break;
     }
+    // timed passes: the launch records the pair from its own dispatch timestamps
     std::pair<hipEvent_t, hipEvent_t> evp{nullptr, nullptr};
     if (tm && tm->on && cls >= 0) {
       evp = tm->get(cls);
-      hip_check(hipEventRecord(evp.first, st), "hipEventRecord");
+      arm_launch_events(evp.first, evp.second);
     }
+    int nb = -1;
     switch (ps.kind) {
-      case Pass::CELL: launch_cell(ps.cell, nonlinear, ps.bs, st); break;
-      case Pass::VERT: launch_vertex(ps.vert, ps.bs, st); break;
-      case Pass::PREP: launch_prep(ps.prep, ps.fuse_q, ps.bs, st); break;
-      case Pass::EDGE: launch_edge(ps.edge, drag, wind, ps.bs, st); break;
+      case Pass::CELL: nb = launch_cell(ps.cell, nonlinear, ps.bs, st); break;
+      case Pass::VERT: nb = launch_vertex(ps.vert, ps.bs, st); break;
+      case Pass::PREP: nb = launch_prep(ps.prep, ps.fuse_q, ps.bs, st); break;
+      case Pass::EDGE: nb = launch_edge(ps.edge, drag, wind, ps.bs, st); break;
       case Pass::PRED: launch_predict(ps.pred, st); break;
       case Pass::ASM: launch_assemble(ps.asmb, st); break;
       case Pass::RK4FIN:
@@ -632,7 +636,10 @@ void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool
       case Pass::WIND: launch_cyclone(ps.cyc, st); break;
       case Pass::TICK: launch_clock_tick(ps.clock, st); break;
     }
-    if (evp.first) hip_check(hipEventRecord(evp.second, st), "hipEventRecord");
+    if (evp.first) {
+      arm_launch_events(nullptr, nullptr);
+      if (nb == 0) tm->unget(cls);   // empty range: nothing was launched or recorded
+    }
   }
   hip_check(hipGetLastError(), "kernel launch");
 }

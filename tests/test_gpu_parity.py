@@ -220,3 +220,25 @@ def test_autotuner_restores_state_and_picks_a_candidate(cvt, tmp_path):
     # cached: a second call returns the same choice without timing
     again = autotune.autotune(s, cache_path=str(tmp_path / "tune.json"))
     assert (again["fuse_vertex"], again["block"]) == (choice["fuse_vertex"], choice["block"])
+
+
+def test_dispatch_timing_mode_counts_launches_and_keeps_results(cvt):
+    """Timing mode launches directly with dispatch-recorded events: same bits, one timed launch per pass."""
+    w, om, lab, fm = cvt
+    ref = _solver(fm, w)
+    ref.step(3)
+    s = _solver(fm, w)
+    s.set_timing(True)
+    s.step(3)
+    ms, launches = s.kernel_time(0)
+    info = s.info()
+    assert ms > 0
+    assert launches % 3 == 0 and launches // 3 == 3 * (1 + w.M)   # 3 stages x (coarse + M fine)
+    for cls in (1, 3):
+        m2, n2 = s.kernel_time(cls)
+        assert m2 > 0 and n2 > 0
+    s.set_timing(False)
+    hr, ur = ref.get_state()
+    hs, us = s.get_state()
+    assert np.array_equal(hr, hs) and np.array_equal(ur, us)
+    assert info["launches_per_step"] > 0
