@@ -40,23 +40,36 @@ BETA = (0.531, 0.531, 0.313)
 F_LABEL, IF1_LABEL, IF2_LABEL, INT_LABEL = 0, 1, 2, 3
 
 
-def fbrk32_stages(om, u, h, dt, ph, beta=BETA):
-    """The three FB-RK(3,2) stages of eq. fbrk32; returns (h1, h2, h3, u1, u2, u3)."""
+def momentum_tendency(om, ph, slow=None):
+    """Phi as a function of (u, h): the full Phi, or, under the operator
+    splitting of eq. ``splitting`` (Section 3.2), Phi_fast(u, h) plus the slow
+    tendency ``slow`` frozen at an earlier state."""
+    if slow is None:
+        return lambda uu, hh: trisk.phi(om, uu, hh, ph)
+    return lambda uu, hh: trisk.phi_fast(om, uu, hh, ph) + slow
+
+
+def fbrk32_stages(om, u, h, dt, ph, beta=BETA, split=False):
+    """The three FB-RK(3,2) stages of eq. fbrk32; returns (h1, h2, h3, u1, u2, u3).
+
+    ``split``: Lie-Trotter operator splitting (eq. ``splitting``): the slow
+    terms are evaluated once at (u, h) and added to the fast Phi of every stage."""
     b1, b2, b3 = beta
+    Phi = momentum_tendency(om, ph, trisk.phi_slow(om, u, h, ph) if split else None)
     h1 = h + (dt / 3.0) * trisk.psi(om, u, h, ph)
     hs = b1 * h1 + (1.0 - b1) * h
-    u1 = u + (dt / 3.0) * trisk.phi(om, u, hs, ph)
+    u1 = u + (dt / 3.0) * Phi(u, hs)
     h2 = h + (dt / 2.0) * trisk.psi(om, u1, h1, ph)
     hss = b2 * h2 + (1.0 - b2) * h
-    u2 = u + (dt / 2.0) * trisk.phi(om, u1, hss, ph)
+    u2 = u + (dt / 2.0) * Phi(u1, hss)
     h3 = h + dt * trisk.psi(om, u2, h2, ph)
     hsss = b3 * h3 + (1.0 - 2.0 * b3) * h2 + b3 * h
-    u3 = u + dt * trisk.phi(om, u2, hsss, ph)
+    u3 = u + dt * Phi(u2, hsss)
     return h1, h2, h3, u1, u2, u3
 
 
-def fbrk32_step(om, u, h, dt, ph, beta=BETA):
-    h1, h2, h3, u1, u2, u3 = fbrk32_stages(om, u, h, dt, ph, beta)
+def fbrk32_step(om, u, h, dt, ph, beta=BETA, split=False):
+    h1, h2, h3, u1, u2, u3 = fbrk32_stages(om, u, h, dt, ph, beta, split)
     return u3, h3
 
 
@@ -90,13 +103,22 @@ def edge_labels(om, cell_label):
     return np.minimum(cell_label[om.coe[:, 0]], cell_label[om.coe[:, 1]])
 
 
-def fblts_step(om, u, h, dt, M, ph, cell_label, beta=BETA, correct_interface=True):
+def fblts_step(om, u, h, dt, M, ph, cell_label, beta=BETA, correct_interface=True, split=0):
     """One FB-LTS coarse step (Section 2.2) in definition mode.
 
     ``cell_label``: 0 = fine, 1 = interface one, 2 = interface two,
     3 = interior coarse.  ``correct_interface=False`` is the negative control
     of the conservation tests: interface one and two keep the uncorrected
     coarse values instead of step 4.
+
+    ``split``: 0 = unsplit; 1 = the operator splitting of Section 3.2 (eq.
+    ``splitting``): the slow momentum terms are evaluated once at t^n and held
+    for the whole step, every stage adds them to the fast terms of eq.
+    ``fast_terms``; 2 = the variant proposed in Section 4.2: the fine
+    advancement re-evaluates the slow terms at t^{n,k} before each substep k
+    from the substep's starting state (fine values, interface-one predictions
+    and the time-level-n aliases elsewhere), the coarse advancement keeps the
+    t^n values.
     """
     b1, b2, b3 = beta
     cl = np.asarray(cell_label)
@@ -105,7 +127,8 @@ def fblts_step(om, u, h, dt, M, ph, cell_label, beta=BETA, correct_interface=Tru
     Fe, IF1e, IFe = el == F_LABEL, el == IF1_LABEL, (el == IF1_LABEL) | (el == IF2_LABEL)
 
     # step 1: coarse advancement (tilde values on the interface, bar values on the interior)
-    h1, h2, h3, u1, u2, u3 = fbrk32_stages(om, u, h, dt, ph, beta)
+    h1, h2, h3, u1, u2, u3 = fbrk32_stages(om, u, h, dt, ph, beta, split=split > 0)
+    slow_n = trisk.phi_slow(om, u, h, ph) if split else None
 
     # step 3 arrays; on interface two and the interior they hold the coarse
     # aliases listed under eq. if_correction (time-level independent)
@@ -121,21 +144,25 @@ def fblts_step(om, u, h, dt, M, ph, cell_label, beta=BETA, correct_interface=Tru
         U0[IF1e], U1[IF1e], U2[IF1e], _ = predictions(
             u[IF1e], u1[IF1e], u2[IF1e], u3[IF1e], M, k)
         # step 3: fine advancement with dt/M (eq. fine_fbrk32)
+        if split == 2 and k > 0:
+            Phi = momentum_tendency(om, ph, trisk.phi_slow(om, U0, H0, ph))
+        else:
+            Phi = momentum_tendency(om, ph, slow_n)
         p = trisk.psi(om, U0, H0, ph)
         H1[Fc] = H0[Fc] + (delta / 3.0) * p[Fc]
         hs = b1 * H1 + (1.0 - b1) * H0
-        f = trisk.phi(om, U0, hs, ph)
+        f = Phi(U0, hs)
         U1[Fe] = U0[Fe] + (delta / 3.0) * f[Fe]
         p = trisk.psi(om, U1, H1, ph)
         H2[Fc] = H0[Fc] + (delta / 2.0) * p[Fc]
         hs = b2 * H2 + (1.0 - b2) * H0
-        f = trisk.phi(om, U1, hs, ph)
+        f = Phi(U1, hs)
         U2[Fe] = U0[Fe] + (delta / 2.0) * f[Fe]
         p = trisk.psi(om, U2, H2, ph)
         H3[Fc] = H0[Fc] + delta * p[Fc]
         acc_h[IFc] = acc_h[IFc] + p[IFc]
         hs = b3 * H3 + (1.0 - 2.0 * b3) * H2 + b3 * H0
-        f = trisk.phi(om, U2, hs, ph)
+        f = Phi(U2, hs)
         U3F = U0 + delta * f
         acc_u[IFe] = acc_u[IFe] + f[IFe]
         H0[Fc] = H3[Fc]

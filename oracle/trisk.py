@@ -128,10 +128,17 @@ def gradient(om, B):
 # ----------------------------------------------------------------------------
 
 class Physics:
-    """Model switches: linear or nonlinear TRiSK, gravity, drag, wind."""
+    """Model switches: linear or nonlinear TRiSK, gravity, drag, wind.
 
-    def __init__(self, linear=False, g=9.81, cd=None, wind=None, rho_air=1.15, rho_w=1000.0):
+    ``gravity_wave=True`` keeps only the fast terms of eq. ``fast_terms``
+    (Section 3.2): Psi = -div(h u) and Phi = -g grad(h + z_b) with
+    z_b = -H; the system of eq. ``grav_wave_model`` (Section 2.4).
+    """
+
+    def __init__(self, linear=False, g=9.81, cd=None, wind=None, rho_air=1.15, rho_w=1000.0,
+                 gravity_wave=False):
         self.linear = linear
+        self.gravity_wave = gravity_wave
         self.g = g
         self.cd = cd            # per-cell quadratic drag coefficient C_D (nonlinear only)
         self.wind = wind        # (uW_normal[E], uW_tangential[E]) at edges (nonlinear only)
@@ -148,8 +155,44 @@ def psi(om, u, h, ph):
     return divergence_term(om, F)
 
 
+def phi_fast(om, u, h, ph):
+    """Fast momentum tendency of eq. fast_terms: -g grad(h + z_b), z_b = -H."""
+    return -gradient(om, ph.g * (h - om.H))
+
+
+def phi_slow(om, u, h, ph):
+    """Slow momentum tendency (Section 3.2): everything in Phi but the pressure
+    gradient, i.e. the PV flux, -grad K, drag and wind stress, evaluated at (u, h)."""
+    he = edge_thickness(om, h)
+    F = he * u
+    q = (relative_vorticity(om, u) + om.fv) / vertex_thickness(om, h)
+    q_edge = 0.5 * (q[om.voe[:, 0]] + q[om.voe[:, 1]])
+    out = pv_flux(om, F, q_edge) - gradient(om, kinetic_energy(om, u))
+    return out + forcing_terms(om, u, he, ph)
+
+
+def forcing_terms(om, u, he, ph):
+    """Quadratic bottom drag and wind stress of eq. hurricane_model at edges."""
+    out = np.zeros_like(u)
+    if ph.cd is None and ph.wind is None:
+        return out
+    up = perp(om, u)
+    if ph.cd is not None:
+        cde = 0.5 * (ph.cd[om.coe[:, 0]] + ph.cd[om.coe[:, 1]])
+        speed = np.sqrt(u * u + up * up)
+        out = out - cde * speed * u / he
+    if ph.wind is not None:
+        wn, wt = ph.wind
+        cw = wind_drag_coefficient(np.sqrt(wn * wn + wt * wt), ph)
+        rel = np.sqrt((wn - u) ** 2 + (wt - up) ** 2)
+        out = out + cw * rel * (wn - u) / he
+    return out
+
+
 def phi(om, u, h, ph):
     """Momentum tendency Phi(u, h); h is whatever thickness the stage passes."""
+    if ph.gravity_wave:
+        return phi_fast(om, u, h, ph)
     if ph.linear:
         # linearisation about rest: F = H_e u, q = f_v / H_v, B = g (h - H)
         F = om.He * u

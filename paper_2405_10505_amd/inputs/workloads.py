@@ -319,3 +319,26 @@ def small_sphere(n=3000, M=4, iters=20):
     """Configuration-3 recipe at test size: the same construction with the
     resolution range scaled to the cell count (200 -> 600 km)."""
     return config3(n=n, M=M, iters=iters, dx_fine=200e3, dx_coarse=600e3)
+
+
+# ----------------------------------------------------------------------------
+# aquaplanet gravity wave (the paper's temporal-convergence experiment)
+# ----------------------------------------------------------------------------
+
+def aquaplanet(n=2000, M=4, depth=1000.0, amp=1.0, width=600e3, seed=9, iters=20,
+               dx_fine=100e3, dx_coarse=800e3):
+    """Non-rotating aquaplanet at rest with constant depth and a Gaussian SSH bump
+    (Section 2.4): the coastline-refined spherical CVT with f = 0 everywhere, the
+    fine set from the local CFL number, the external gravity-wave system."""
+    base = sphere_mesh(n, 5, iters, dx_fine, dx_coarse)
+    mesh = base.copy_with(f_vertex=np.zeros(base.n_vertices), f_edge=np.zeros(base.n_edges),
+                          bottom_depth=np.full(base.n_cells, depth))
+    r = rng_for(seed)
+    c = meshgen._normalize(r.normal(size=3))
+    xc = mesh.x_cell / mesh.sphere_radius
+    d = np.arctan2(np.linalg.norm(np.cross(xc, c), axis=1), xc @ c) * mesh.sphere_radius
+    h0 = depth + amp * np.exp(-0.5 * (d / width) ** 2)
+    u0 = np.zeros(mesh.n_edges)
+    fine, dt_c, dt_f = cfl_fine_mask(mesh, M)
+    return Workload("aquaplanet%dk" % round(mesh.n_cells / 1000), mesh, h0, u0, fine, dt_c, M, False, None, 0,
+                    dict(dt_fine=dt_f, n_fine=int(fine.sum()), centre=c))
