@@ -55,7 +55,20 @@ enum {
 };
 
 enum { FBLTS_SCHEME_FBLTS = 0, FBLTS_SCHEME_FBRK32 = 1, FBLTS_SCHEME_RK4 = 2 };
-enum { FBLTS_PHYS_LINEAR = 0, FBLTS_PHYS_NONLINEAR = 1 };
+/* Physics: LINEAR = TRiSK linearised about rest; NONLINEAR = eq. nonlinear_swe
+ * with optional drag and wind stress (eq. hurricane_model); GRAVITY_WAVE = the
+ * fast terms only (eq. fast_terms: Psi = -div(h u), Phi = -g grad(h + z_b)),
+ * the external gravity-wave system of Section 2.4 (eq. grav_wave_model). */
+enum { FBLTS_PHYS_LINEAR = 0, FBLTS_PHYS_NONLINEAR = 1, FBLTS_PHYS_GRAVITY_WAVE = 2 };
+/* Operator splitting of the momentum equation (Section 3.2, eq. splitting):
+ * NONE = unsplit; COARSE = slow terms (everything in Phi but the pressure
+ * gradient: PV flux, -grad K, drag, wind) evaluated once at t^n and held for
+ * the whole step, every stage uses the fast terms plus that frozen value;
+ * FINE = as COARSE, but the fine advancement re-evaluates the slow terms
+ * before each substep k from the substep's starting state (the variant
+ * Section 4.2 proposes).  Needs FBLTS_PHYS_NONLINEAR; COARSE also applies to
+ * global FB-RK(3,2). */
+enum { FBLTS_SPLIT_NONE = 0, FBLTS_SPLIT_COARSE = 1, FBLTS_SPLIT_FINE = 2 };
 enum { FBLTS_LABEL_F = 0, FBLTS_LABEL_IF1 = 1, FBLTS_LABEL_IF2 = 2, FBLTS_LABEL_INT = 3 };
 
 /* Message of the last failing call on this thread ("" if none).  Valid until
@@ -135,6 +148,8 @@ typedef struct {
   int32_t physics;        /* FBLTS_PHYS_* */
   int32_t r_layers;       /* interface thickness in cell layers for binary labels (2) */
   double rho_air, rho_water;    /* wind-stress law densities (1.15, 1000) */
+  int32_t split;          /* FBLTS_SPLIT_* (0) */
+  int32_t reserved;       /* 0 */
 } fblts_params;
 
 typedef struct fblts_solver fblts_solver;
@@ -247,8 +262,11 @@ typedef struct {
 int fblts_get_info(fblts_solver* s, fblts_info* out);
 
 /* Test export: evaluate one tendency on caller-numbered (h,u) over all
- * entities.  which = 0: Psi (out[n_cells]); 1: Phi (out[n_edges]).  Uses the
- * solver's physics, drag and wind.  Synchronises when out is a host pointer. */
+ * entities.  which = 0: Psi (out[n_cells]); 1: Phi (out[n_edges]); 2: the
+ * slow part of Phi under the operator splitting (PV flux, -grad K, drag,
+ * wind; nonlinear physics only).  Uses the solver's physics, drag and wind
+ * (the unsplit Phi for which = 1 even when the solver splits).  Synchronises
+ * when out is a host pointer. */
 int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const double* u,
                          double* out, int32_t on_device);
 

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libfblts.so")
 
 FBLTS_OK, FBLTS_EINVAL, FBLTS_ENOMEM, FBLTS_EDEVICE, FBLTS_EREGION, FBLTS_ESTATE, FBLTS_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 SCHEME_FBLTS, SCHEME_FBRK32, SCHEME_RK4 = 0, 1, 2
-PHYS_LINEAR, PHYS_NONLINEAR = 0, 1
+PHYS_LINEAR, PHYS_NONLINEAR, PHYS_GRAVITY_WAVE = 0, 1, 2
+SPLIT_NONE, SPLIT_COARSE, SPLIT_FINE = 0, 1, 2
 BETA = (0.531, 0.531, 0.313)
 OPT_FUSE_VERTEX, OPT_BLOCK = 1, 2
 
@@ -39,7 +40,8 @@ class fblts_mesh_desc(C.Structure):
 class fblts_params(C.Structure):
     _fields_ = [("dt", C.c_double), ("g", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("beta3", C.c_double), ("M", C.c_int32), ("scheme", C.c_int32), ("physics", C.c_int32),
-                ("r_layers", C.c_int32), ("rho_air", C.c_double), ("rho_water", C.c_double)]
+                ("r_layers", C.c_int32), ("rho_air", C.c_double), ("rho_water", C.c_double),
+                ("split", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fblts_diag(C.Structure):
@@ -195,12 +197,16 @@ class Mesh:
 
 
 def make_params(dt, M=1, scheme=SCHEME_FBLTS, linear=False, g=9.81, beta=BETA, r_layers=2,
-                rho_air=1.15, rho_water=1000.0):
+                rho_air=1.15, rho_water=1000.0, physics=None, split=SPLIT_NONE):
+    """physics overrides `linear` (PHYS_*); split selects the operator splitting (SPLIT_*)."""
     p = fblts_params()
     p.dt, p.g = float(dt), float(g)
     p.beta1, p.beta2, p.beta3 = beta
-    p.M, p.scheme, p.physics, p.r_layers = int(M), int(scheme), PHYS_LINEAR if linear else PHYS_NONLINEAR, int(r_layers)
+    if physics is None:
+        physics = PHYS_LINEAR if linear else PHYS_NONLINEAR
+    p.M, p.scheme, p.physics, p.r_layers = int(M), int(scheme), int(physics), int(r_layers)
     p.rho_air, p.rho_water = rho_air, rho_water
+    p.split, p.reserved = int(split), 0
     return p
 
 

@@ -113,6 +113,7 @@ struct EdgeSeg {
   const double* cd;        // per cell and member, or nullptr
   const double* wind_n;    // per edge, or nullptr
   const double* wind_t;
+  const double* slow;      // fast pass: frozen slow tendency per edge and member, or nullptr
   double c_dt, acc_w, rho_ratio;
 };
 

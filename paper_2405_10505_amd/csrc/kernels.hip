@@ -41,8 +41,13 @@ __device__ __forceinline__ int find_seg(const Launch<S>& L, int b) {
 }
 
 // ---------------------------------------------------------------- cell pass
-template <bool NONLINEAR>
+// MODE 0: linear TRiSK (flux H_e u, B = g(h* - H)); 1: nonlinear (flux h_e u,
+// B = K + g(h* - H)); 2: fast terms of the operator splitting, eq. fast_terms
+// (flux h_e u, B = g(h* - H), no kinetic energy).
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
+  constexpr bool NONLINEAR = MODE != 0;   // thickness flux with h_e
+  constexpr bool KE = MODE == 1;          // kinetic energy in B
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg(L, b);
   const CellSeg& S = L.seg[s];
@@ -78,7 +83,7 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
     ue[j] = S.Usrc[(long)e * nm + mem];
     dv[j] = m.e_dv[e];
     if (NONLINEAR) {
-      dc[j] = m.e_dc[e];
+      dc[j] = KE ? m.e_dc[e] : 0.0;
       hx[j] = S.Hsrc[(long)nb[j] * nm + mem];
     } else {
       hx[j] = m.e_He[e];
@@ -90,7 +95,7 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
     double f = l * (he * u);
     f = (c & 1) ? -f : f;
     flux += valid ? f : 0.0;
-    if (NONLINEAR) ke += valid ? l * d * (u * u) : 0.0;
+    if (KE) ke += valid ? l * d * (u * u) : 0.0;
   };
 #pragma unroll
   for (int j = 0; j < kUnrollCell; ++j) acc_slot(code[j], ue[j], dv[j], dc[j], hx[j], j < ne);
@@ -99,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
     const int e = c >> 1;
     const double u = S.Usrc[(long)e * nm + mem];
     const double hnb = NONLINEAR ? S.Hsrc[(long)m.c_nbr[j * m.cs + i] * nm + mem] : m.e_He[e];
-    acc_slot(c, u, m.e_dv[e], NONLINEAR ? m.e_dc[e] : 0.0, hnb, true);
+    acc_slot(c, u, m.e_dv[e], KE ? m.e_dc[e] : 0.0, hnb, true);
   }
   (void)need_psi;
   const long ii = (long)i * nm + mem;
@@ -118,7 +123,7 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   }
   const double hs = S.wn * hnew + S.ws * h_i + S.wb * h0;
   S.hs[ii] = hs;
-  const double K = NONLINEAR ? 0.25 * ke * m.c_invA[i] : 0.0;
+  const double K = KE ? 0.25 * ke * m.c_invA[i] : 0.0;
   S.B[ii] = K + S.g * (hs - m.c_H[i]);
 }
 
@@ -246,6 +251,33 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
       phi += cw * sqrt(rn * rn + rt * rt) * rn / pe.w;
     }
   }
+  if (e >= S.upd_begin && e < S.upd_end) S.Udst[ee] = fma(S.c_dt, phi, S.U0[ee]);
+  if (e >= S.acc_begin && e < S.acc_end) {
+    const double a = S.acc_w * phi;
+    S.acc[ee] = S.acc_first ? a : S.acc[ee] + a;
+  }
+}
+
+// ----------------------------------------------------- fast momentum pass
+// Fast momentum tendency of the operator splitting (eq. fast_terms):
+// Phi = -(B_c1 - B_c0) / d_e with B = g(h* - H), plus (SLOW) the slow tendency
+// frozen at the start of the step or substep (eq. splitting).
+template <bool SLOW>
+__global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = find_seg(L, b);
+  const EdgeSeg& S = L.seg[s];
+  const int nm_log2 = S.nm_log2;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const int e = (int)(item >> nm_log2);
+  if (e >= S.end) return;
+  const int mem = (int)(item & ((1 << nm_log2) - 1));
+  const int nm = 1 << nm_log2;
+  const MeshDev& m = S.m;
+  const long ee = (long)e * nm + mem;
+  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  double phi = -(S.B[(long)c1 * nm + mem] - S.B[(long)c0 * nm + mem]) * m.e_invdc[e];
+  if (SLOW) phi += S.slow[ee];
   if (e >= S.upd_begin && e < S.upd_end) S.Udst[ee] = fma(S.c_dt, phi, S.U0[ee]);
   if (e >= S.acc_begin && e < S.acc_end) {
     const double a = S.acc_w * phi;
@@ -496,11 +528,12 @@ static void launch_timed(F kernel, int nb, int bs, hipStream_t st, A... args) {
 }
 
 // Each launcher returns the number of blocks launched (0: nothing to do).
-int launch_cell(Launch<CellSeg> L, bool nonlinear, int bs, hipStream_t st) {
+int launch_cell(Launch<CellSeg> L, int mode, int bs, hipStream_t st) {
   const int nb = blocks_for(L, cell_items, bs);
   if (nb == 0) return 0;
-  if (nonlinear) launch_timed(k_cell<true>, nb, bs, st, L);
-  else launch_timed(k_cell<false>, nb, bs, st, L);
+  if (mode == 1) launch_timed(k_cell<1>, nb, bs, st, L);
+  else if (mode == 2) launch_timed(k_cell<2>, nb, bs, st, L);
+  else launch_timed(k_cell<0>, nb, bs, st, L);
   return nb;
 }
 
@@ -526,6 +559,14 @@ int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st)
   else if (drag) launch_timed(k_edge<true, false>, nb, bs, st, L);
   else if (wind) launch_timed(k_edge<false, true>, nb, bs, st, L);
   else launch_timed(k_edge<false, false>, nb, bs, st, L);
+  return nb;
+}
+
+int launch_edge_fast(Launch<EdgeSeg> L, bool slow, int bs, hipStream_t st) {
+  const int nb = blocks_for(L, edge_items, bs);
+  if (nb == 0) return 0;
+  if (slow) launch_timed(k_edge_fast<true>, nb, bs, st, L);
+  else launch_timed(k_edge_fast<false>, nb, bs, st, L);
   return nb;
 }
 

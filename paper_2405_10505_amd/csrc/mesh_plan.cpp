@@ -732,7 +732,7 @@ struct Stamp {
 };
 }  // namespace
 
-double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm) {
+double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm, bool ke) {
   const double S = 8.0 * nm;
   double b = 0;
   Stamp se(pm.E), sc(pm.N);
@@ -751,7 +751,7 @@ double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear,
     if (acc) b += 2 * S;
     for (int j = 0; j < n; ++j) {
       const int e = pm.c_edge[(size_t)j * pm.cs + i] >> 1;
-      if ((nonlinear || psi) && se.mark(e)) b += S + 8 + (nonlinear ? 8 : 8);  // u, l, d (or He)
+      if ((nonlinear || psi) && se.mark(e)) b += S + 8 + ((nonlinear && !ke) ? 0 : 8);  // u, l, d (or He)
       if (psi && nonlinear) {
         const int nb = pm.c_nbr[(size_t)j * pm.cs + i];
         if (sc.mark(nb)) b += S;
@@ -834,6 +834,24 @@ double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool
       if (sp.mark(pm.e_eoe[(size_t)j * pm.es + e])) b += 4 * S;
     for (int j = 0; j < 2; ++j)
       if (sc.mark(pm.e_cell[(size_t)j * pm.es + e])) b += S + (drag ? S : 0);   // B (+ C_D)
+  }
+  return b;
+}
+
+double bytes_edge_fast_pass(const PermMesh& pm, const StageRanges& r, bool slow, int nm) {
+  const double S = 8.0 * nm;
+  double b = 0;
+  Stamp sc(pm.N);
+  sc.next();
+  for (int e = r.edge.b; e < r.edge.e; ++e) {
+    b += 8 + 8;                              // cells, 1/d_e
+    const bool upd = e >= r.edge_upd.b && e < r.edge_upd.e;
+    const bool acc = e >= r.edge_acc.b && e < r.edge_acc.e;
+    if (upd) b += 2 * S;                     // U0, Udst
+    if (acc) b += 2 * S;
+    if (slow) b += S;
+    for (int j = 0; j < 2; ++j)
+      if (sc.mark(pm.e_cell[(size_t)j * pm.es + e])) b += S;   // B
   }
   return b;
 }

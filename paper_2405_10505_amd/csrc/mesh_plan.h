@@ -76,9 +76,11 @@ void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm);
 // Algorithmic (compulsory) bytes of each pass kind over a range: every mesh
 // array element and state element the pass's mathematics references, once.
 // nm = members; state bytes scale with nm, mesh bytes do not.
-double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm);
+double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm, bool ke = true);
 double bytes_vert_pass(const PermMesh& pm, const Range& r, int nm);
 double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm, bool fuse_q = false);
 double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm);
+// fast momentum pass of the operator splitting (pressure gradient + frozen slow tendency)
+double bytes_edge_fast_pass(const PermMesh& pm, const StageRanges& r, bool slow, int nm);
 
 }  // namespace fblts

@@ -28,10 +28,11 @@
 #include "mesh_plan.h"
 
 namespace fblts {
-int launch_cell(Launch<CellSeg> L, bool nonlinear, int bs, hipStream_t st);
+int launch_cell(Launch<CellSeg> L, int mode, int bs, hipStream_t st);
 int launch_vertex(Launch<VertSeg> L, int bs, hipStream_t st);
 int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st);
 int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st);
+int launch_edge_fast(Launch<EdgeSeg> L, bool slow, int bs, hipStream_t st);
 int launch_predict(Launch<PredSeg> L, hipStream_t st);
 int launch_assemble(Launch<AsmSeg> L, hipStream_t st);
 void launch_axpy_final(double* y, const double* acc, double c, long n, hipStream_t st);
@@ -200,6 +201,7 @@ struct DevState {
   DevBuf U[4], acc_u, sv_u, P, q;
   DevBuf wind_n, wind_t;
   bool has_wind = false;
+  DevBuf slow;   // operator splitting: frozen slow momentum tendency [E*nm]
   // moving cyclone: wind evaluated on the device once per coarse step
   DevBuf cyc_x, cyc_n, cyc_clock;
   bool cyclone = false;
@@ -246,6 +248,8 @@ struct Pass {
   double fin_c = 0.0;
   double model_bytes = 0.0;
   bool fuse_q = false;   // PREP: evaluate q_v in the prep pass (no vertex pass)
+  int cell_mode = 1;     // CELL: 0 linear, 1 nonlinear, 2 fast terms (k_cell<MODE>)
+  bool edge_fast = false;   // EDGE: fast momentum pass (k_edge_fast)
   int bs = kBlock;       // threads per block of the stencil passes
 };
 
@@ -267,6 +271,11 @@ struct MeshUnit {
 struct Params {
   fblts_params p;
   bool nonlinear() const { return p.physics == FBLTS_PHYS_NONLINEAR; }
+  bool gravity_wave() const { return p.physics == FBLTS_PHYS_GRAVITY_WAVE; }
+  // stencils reach neighbour thicknesses (nonlinear flux): nonlinear and fast terms
+  bool wide() const { return p.physics != FBLTS_PHYS_LINEAR; }
+  // stages evaluate only the fast terms (plus a frozen slow tendency when split)
+  bool fast() const { return gravity_wave() || p.split > 0; }
 };
 
 void check_params(const fblts_params* p) {
@@ -275,7 +284,13 @@ void check_params(const fblts_params* p) {
   if (!(p->g > 0)) throw Err(FBLTS_EINVAL, "g must be positive");
   if (p->M < 1 || p->M > 1024) throw Err(FBLTS_EINVAL, "M must be in 1..1024");
   if (p->scheme < 0 || p->scheme > 2) throw Err(FBLTS_EINVAL, "unknown scheme");
-  if (p->physics < 0 || p->physics > 1) throw Err(FBLTS_EINVAL, "unknown physics");
+  if (p->physics < 0 || p->physics > 2) throw Err(FBLTS_EINVAL, "unknown physics");
+  if (p->split < 0 || p->split > 2) throw Err(FBLTS_EINVAL, "split must be 0, 1 or 2");
+  if (p->split && p->physics != FBLTS_PHYS_NONLINEAR)
+    throw Err(FBLTS_EINVAL, "operator splitting needs nonlinear physics");
+  if (p->split && p->scheme == FBLTS_SCHEME_RK4) throw Err(FBLTS_EINVAL, "operator splitting applies to FB schemes");
+  if (p->split == 2 && p->scheme != FBLTS_SCHEME_FBLTS)
+    throw Err(FBLTS_EINVAL, "per-substep slow terms (split 2) need the FB-LTS scheme");
   if (p->r_layers < 1 || p->r_layers > 64) throw Err(FBLTS_EINVAL, "r_layers must be in 1..64");
 }
 
@@ -294,11 +309,16 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
   u.edge_items = 0;
   const int nm = s.nm;
 
+  const bool fast = P.fast();
+  const int stage_cell_mode = fast ? 2 : (nl ? 1 : 0);
+  if (p.split && s.slow.bytes < (size_t)md.E * nm * 8) s.slow.alloc((size_t)md.E * nm * 8);
+  const double* slow = p.split ? s.slow.as<double>() : nullptr;
   auto cell_pass = [&](const StageRanges& r, const double* Hsrc, const double* Usrc, const double* H0,
                        const double* Hnew_src, double* Hdst, double c_dt, double wn, double ws, double wb,
-                       double* acc, double acc_w, int acc_first) {
+                       double* acc, double acc_w, int acc_first, int mode, double g) {
     Pass ps;
     ps.kind = Pass::CELL;
+    ps.cell_mode = mode;
     ps.cell.nseg = 1;
     CellSeg& c = ps.cell.seg[0];
     c.m = md;
@@ -323,8 +343,8 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     c.ws = ws;
     c.wb = wb;
     c.acc_w = acc_w;
-    c.g = p.g;
-    ps.model_bytes = bytes_cell_pass(u.pm, r, nl, nm);
+    c.g = g;
+    ps.model_bytes = bytes_cell_pass(u.pm, r, mode != 0, nm, mode == 1);
     ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
@@ -365,9 +385,10 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     u.passes.push_back(ps);
   };
   auto edge_pass = [&](const StageRanges& r, const double* Usrc, const double* U0, double* Udst, double c_dt,
-                       double* acc, double acc_w, int acc_first) {
+                       double* acc, double acc_w, int acc_first, bool fast_pass) {
     Pass ps;
     ps.kind = Pass::EDGE;
+    ps.edge_fast = fast_pass;
     ps.edge.nseg = 1;
     EdgeSeg& e = ps.edge.seg[0];
     e.m = md;
@@ -391,7 +412,9 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     e.c_dt = c_dt;
     e.acc_w = acc_w;
     e.rho_ratio = p.rho_air / p.rho_water;
-    ps.model_bytes = bytes_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
+    e.slow = fast_pass ? slow : nullptr;
+    ps.model_bytes = fast_pass ? bytes_edge_fast_pass(u.pm, r, slow != nullptr, nm)
+                               : bytes_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
     u.bytes_edge += ps.model_bytes;
     u.edge_items += (int64_t)r.edge.size() * nm;
     ps.tag = cur_tag;
@@ -400,17 +423,40 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
   auto stage = [&](const StageRanges& r, const double* Hsrc, const double* Usrc, const double* H0,
                    const double* Hnew_src, double* Hdst, double c_dt, double wn, double ws, double wb, double* acch,
                    const double* U0, double* Udst, double* accu, double acc_w, int acc_first) {
-    cell_pass(r, Hsrc, Usrc, H0, Hnew_src, Hdst, c_dt, wn, ws, wb, acch, acc_w, acc_first);
-    vert_pass(r, Usrc);
-    prep_pass(r, Usrc);
-    edge_pass(r, Usrc, U0, Udst, c_dt, accu, acc_w, acc_first);
+    cell_pass(r, Hsrc, Usrc, H0, Hnew_src, Hdst, c_dt, wn, ws, wb, acch, acc_w, acc_first, stage_cell_mode, p.g);
+    if (!fast) {
+      vert_pass(r, Usrc);
+      prep_pass(r, Usrc);
+    }
+    edge_pass(r, Usrc, U0, Udst, c_dt, accu, acc_w, acc_first, fast);
   };
+  // Operator splitting (Section 3.2, eq. splitting): the slow momentum
+  // tendency (PV flux, -grad K, drag, wind) at the state (Hs, Us), written to
+  // `slow` on the edge range of r.  Cell pass with g = 0 (B = K) and h* = Hs,
+  // then the full vertex / prep / momentum passes with the result accumulated
+  // (first write) into `slow`; nothing is updated.
+  auto slow_eval = [&](const StageRanges& r, const double* Hs, const double* Us) {
+    StageRanges q = r;
+    q.cell_upd = q.cell_acc = Range{0, 0};
+    q.edge_upd = Range{0, 0};
+    q.edge_acc = q.edge;
+    cell_pass(q, Hs, Us, Hs, Hs, nullptr, 0.0, 0.0, 1.0, 0.0, nullptr, 1.0, 1, 1, 0.0);
+    vert_pass(q, Us);
+    prep_pass(q, Us);
+    edge_pass(q, Us, Us, nullptr, 0.0, s.slow.as<double>(), 1.0, 1, false);
+  };
+  StageRanges full{};
+  full.cell = Range{0, md.N};
+  full.vert = Range{0, md.V};
+  full.prep = Range{0, md.E};
+  full.edge = Range{0, md.E};
 
   const double dt = p.dt, b1 = p.beta1, b2 = p.beta2, b3 = p.beta3;
   const Plan& pl = plan ? *plan : u.plan;
   const int N = md.N, E = md.E;
   if (p.scheme == FBLTS_SCHEME_FBRK32) {
     const StageRanges* R = pl.coarse;
+    if (p.split) slow_eval(full, H(0), U(0));
     stage(R[0], H(0), U(0), H(0), H(1), H(1), dt / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
     stage(R[1], H(1), U(1), H(0), H(2), H(2), dt / 2, b2, 0.0, 1 - b2, nullptr, U(0), U(2), nullptr, 1, 1);
     // stage 3 updates the state in place
@@ -447,6 +493,10 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
   const int M = p.M;
   const double delta = dt / M;
   const StageRanges* C = pl.coarse;
+  if (p.split) {
+    cur_tag = 0;
+    slow_eval(full, H(0), U(0));
+  }
   cur_tag = 1;
   stage(C[0], H(0), U(0), H(0), H(1), H(1), dt / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
   cur_tag = 2;
@@ -456,6 +506,10 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
   const int if1b = pl.nF, if1e = pl.nF + pl.nIF1, if2e = if1e + pl.nIF2;
   const int if1eb = pl.nFE, if1ee = pl.nFE + pl.nIF1E, if2ee = if1ee + pl.nIF2E;
   const StageRanges* F = pl.fine;
+  if (p.split == 2)
+    for (int j = 0; j < 2; ++j)
+      if (F[j].edge.size() > 0 && (F[j].edge.b < F[2].edge.b || F[j].edge.e > F[2].edge.e))
+        throw Err(FBLTS_EINVAL, "fine stage edge ranges are not nested (per-substep slow terms)");
   double* ah = s.acc_h.as<double>();
   double* au = s.acc_u.as<double>();
   for (int k = 0; k < M; ++k) {
@@ -487,6 +541,12 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     pr.model_bytes = ((double)(if1e - if1b) * 8 + (double)(if1ee - if1eb) * 7) * 8.0 * nm;
     pr.tag = 200 + 10 * k;
     u.passes.push_back(pr);
+    if (p.split == 2 && k > 0) {
+      // Section 4.2's variant: slow terms at t^{n,k} from the substep's starting
+      // state, on every edge the substep's stages compute (stage 3's range)
+      cur_tag = 100 + 10 * k;
+      slow_eval(F[2], H(0), U(0));
+    }
     cur_tag = 100 + 10 * k + 1;
     stage(F[0], H(0), U(0), H(0), H(1), H(1), delta / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
     cur_tag = 100 + 10 * k + 2;
@@ -605,7 +665,7 @@ struct Timing {
 };
 
 // Launch a pass list on a stream.
-void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool wind, hipStream_t st, Timing* tm) {
+void run_passes(const std::vector<Pass>& passes, bool drag, bool wind, hipStream_t st, Timing* tm) {
   for (const Pass& ps : passes) {
     int cls = -1;
     switch (ps.kind) {
@@ -623,10 +683,13 @@ void run_passes(const std::vector<Pass>& passes, bool nonlinear, bool drag, bool
     }
     int nb = -1;
     switch (ps.kind) {
-      case Pass::CELL: nb = launch_cell(ps.cell, nonlinear, ps.bs, st); break;
+      case Pass::CELL: nb = launch_cell(ps.cell, ps.cell_mode, ps.bs, st); break;
       case Pass::VERT: nb = launch_vertex(ps.vert, ps.bs, st); break;
       case Pass::PREP: nb = launch_prep(ps.prep, ps.fuse_q, ps.bs, st); break;
-      case Pass::EDGE: nb = launch_edge(ps.edge, drag, wind, ps.bs, st); break;
+      case Pass::EDGE:
+        nb = ps.edge_fast ? launch_edge_fast(ps.edge, ps.edge.seg[0].slow != nullptr, ps.bs, st)
+                          : launch_edge(ps.edge, drag, wind, ps.bs, st);
+        break;
       case Pass::PRED: launch_predict(ps.pred, st); break;
       case Pass::ASM: launch_assemble(ps.asmb, st); break;
       case Pass::RK4FIN:
@@ -943,7 +1006,7 @@ static void setup_unit(MeshUnit& u, const HostMesh& hm, const Params& P, const i
     u.lab4.assign(hm.N, 3);
     u.layer.assign(hm.N, 1 << 20);
   }
-  build_plan(hm, u.lab4, u.layer, fblts_scheme, P.nonlinear(), P.p.r_layers, u.plan);
+  build_plan(hm, u.lab4, u.layer, fblts_scheme, P.wide(), P.p.r_layers, u.plan);
   permute_mesh(hm, u.plan, u.pm);
   u.dm.upload_from(u.pm, u.plan);
   u.st.alloc(u.pm, u.plan, nm);
@@ -1017,7 +1080,7 @@ static void diag_of(MeshUnit& u, const Params& P, DevBuf& part, DevBuf& out, hip
   const size_t need = (size_t)kDiagQ * nb * u.st.nm * 8;
   if (part.bytes < need) part.alloc(need);
   if (out.bytes < (size_t)kDiagQ * u.st.nm * 8) out.alloc((size_t)kDiagQ * u.st.nm * 8);
-  launch_diag(u.dm.md, u.st.nm_log2, P.nonlinear() ? 0 : 1, u.st.H[0].as<double>(), u.st.U[0].as<double>(), P.p.g,
+  launch_diag(u.dm.md, u.st.nm_log2, P.wide() ? 0 : 1, u.st.H[0].as<double>(), u.st.U[0].as<double>(), P.p.g,
               part.as<double>(), out.as<double>(), st);
   hip_check(hipGetLastError(), "diagnostics launch");
   res.resize((size_t)kDiagQ * u.st.nm);
@@ -1335,7 +1398,7 @@ int fblts_step(fblts_solver* s, int32_t n) {
       if (!s->graph_valid) {
         hip_check(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         try {
-          run_passes(u.passes, nl, s->drag_on, u.st.has_wind, s->stream, nullptr);
+          run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, nullptr);
         } catch (...) {
           hipGraph_t g;
           (void)hipStreamEndCapture(s->stream, &g);
@@ -1349,7 +1412,7 @@ int fblts_step(fblts_solver* s, int32_t n) {
       for (int k = 0; k < n; ++k) hip_check(hipGraphLaunch(s->gexec, s->stream), "hipGraphLaunch");
     } else {
       if (s->timing.on) s->timing.reset();
-      for (int k = 0; k < n; ++k) run_passes(u.passes, nl, s->drag_on, u.st.has_wind, s->stream, &s->timing);
+      for (int k = 0; k < n; ++k) run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, &s->timing);
     }
     s->step += n;
     s->time += n * s->P.p.dt;
@@ -1449,7 +1512,7 @@ int fblts_time_kernels(fblts_solver* s, int32_t cls, int32_t repeats, double* av
     hip_check(hipEventRecord(a, s->stream), "hipEventRecord");
     for (const Pass& p : sel) {
       one[0] = p;
-      for (int r = 0; r < repeats; ++r) run_passes(one, s->P.nonlinear(), s->drag_on, u.st.has_wind, s->stream, nullptr);
+      for (int r = 0; r < repeats; ++r) run_passes(one, s->drag_on, u.st.has_wind, s->stream, nullptr);
     }
     hip_check(hipEventRecord(b, s->stream), "hipEventRecord");
     hip_check(hipEventSynchronize(b), "hipEventSynchronize");
@@ -1466,7 +1529,8 @@ int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const 
                          int32_t on_device) {
   return guarded([&] {
     if (!s || !h || !u || !out) throw Err(FBLTS_EINVAL, "NULL argument");
-    if (which != 0 && which != 1) throw Err(FBLTS_EINVAL, "which must be 0 (Psi) or 1 (Phi)");
+    if (which < 0 || which > 2) throw Err(FBLTS_EINVAL, "which must be 0 (Psi), 1 (Phi) or 2 (slow part of Phi)");
+    if (which == 2 && !s->P.nonlinear()) throw Err(FBLTS_EINVAL, "the slow tendency needs nonlinear physics");
     if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
     MeshUnit& U = *s->unit;
     const int N = U.pm.N, E = U.pm.E, V = U.pm.V;
@@ -1524,10 +1588,26 @@ int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const 
     cs.ws = 1;
     cs.wb = 0;
     cs.acc_w = 1;
-    cs.g = s->P.p.g;
+    cs.g = which == 2 ? 0.0 : s->P.p.g;   // slow part: B = K only
     if (U.st.nm != 1) throw Err(FBLTS_EINVAL, "debug tendency needs a one-member solver");
-    launch_cell(c, nl, kBlock, s->stream);
-    if (which == 1) {
+    const bool gw = s->P.gravity_wave();
+    launch_cell(c, gw ? 2 : (nl ? 1 : 0), kBlock, s->stream);
+    if (which >= 1 && gw) {
+      Launch<EdgeSeg> ee{};
+      ee.nseg = 1;
+      EdgeSeg& es = ee.seg[0];
+      es.m = U.dm.md;
+      es.begin = 0;
+      es.end = E;
+      es.upd_begin = es.upd_end = 0;
+      es.acc_begin = 0;
+      es.acc_end = E;
+      es.acc_first = 1;
+      es.B = U.st.B.as<double>();
+      es.acc = acc;
+      es.acc_w = 1;
+      launch_edge_fast(ee, false, kBlock, s->stream);
+    } else if (which >= 1) {
       if (nl) {
         Launch<VertSeg> v{};
         v.nseg = 1;
@@ -1708,7 +1788,7 @@ int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
       if (!e->graph_valid) {
         hip_check(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         try {
-          run_passes(e->passes, nl, nl, false, e->stream, nullptr);
+          run_passes(e->passes, nl, false, e->stream, nullptr);
         } catch (...) {
           hipGraph_t g;
           (void)hipStreamEndCapture(e->stream, &g);
@@ -1721,7 +1801,7 @@ int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
       }
       for (int k = 0; k < n; ++k) hip_check(hipGraphLaunch(e->gexec, e->stream), "hipGraphLaunch");
     } else {
-      for (int k = 0; k < n; ++k) run_passes(e->passes, nl, nl, false, e->stream, nullptr);
+      for (int k = 0; k < n; ++k) run_passes(e->passes, nl, false, e->stream, nullptr);
     }
     e->step += n;
     return FBLTS_OK;
@@ -1772,6 +1852,7 @@ static void adj_check(fblts_solver* s) {
   if (!s->have_state) throw Err(FBLTS_ESTATE, "set_state must come first");
   if (s->P.p.scheme != FBLTS_SCHEME_FBLTS) throw Err(FBLTS_EINVAL, "the adjoint covers the FB-LTS scheme");
   if (s->unit->st.has_wind) throw Err(FBLTS_EINVAL, "the adjoint does not cover the wind-stress term");
+  if (s->P.fast()) throw Err(FBLTS_EINVAL, "the adjoint covers the unsplit linear and nonlinear systems only");
 }
 
 static Rev make_rev(fblts_solver* s, AdjointState& A) {
@@ -1907,7 +1988,7 @@ int fblts_adjoint_forward(fblts_solver* s, int32_t n_steps, int32_t ckpt_every) 
         launch_copy(c, u.st.H[0].as<double>(), N, s->stream);
         launch_copy(c + N, u.st.U[0].as<double>(), E, s->stream);
       }
-      run_passes(u.passes, nl, s->drag_on, false, s->stream, nullptr);
+      run_passes(u.passes, s->drag_on, false, s->stream, nullptr);
     }
     launch_copy(A.final_state.as<double>(), u.st.H[0].as<double>(), N, s->stream);
     launch_copy(A.final_state.as<double>() + N, u.st.U[0].as<double>(), E, s->stream);
@@ -1958,7 +2039,7 @@ int fblts_adjoint_backward(fblts_solver* s, const double* gh_final, const double
       launch_copy(u.st.H[0].as<double>(), c, N, s->stream);
       launch_copy(u.st.U[0].as<double>(), c + N, E, s->stream);
       for (int t = t0; t < t1; ++t) {
-        run_passes(A.rec, nl, s->drag_on, false, s->stream, nullptr);
+        run_passes(A.rec, s->drag_on, false, s->stream, nullptr);
         launch_copy(A.seg_tape.as<double>() + (size_t)(t - t0) * per, A.step_tape.as<double>(), (long)per, s->stream);
       }
       for (int t = t1 - 1; t >= t0; --t) {
