@@ -39,7 +39,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 200; sphere400k: two days)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cvt50k", choices=["cvt50k", "sphere400k", "hex32", "ensemble", "adjoint"])
+    ap.add_argument("--workload", default="cvt50k", choices=["cvt50k", "sphere400k", "hex32", "ensemble", "adjoint", "aquaplanet"])
+    ap.add_argument("--split", type=int, default=0, choices=[0, 1, 2],
+                    help="operator splitting: 0 unsplit, 1 slow terms per coarse step, 2 per fine substep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the global-scheme comparison")
     ap.add_argument("--schedule", default=None,
@@ -71,9 +73,14 @@ def traffic_from_profiles(workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def make_solver(F, w, scheme, dt, M, labels=None, graph=True):
+def make_solver(F, w, scheme, dt, M, labels=None, graph=True, split=0):
     import numpy as np
-    s = F.Solver(F.Mesh(w.mesh) if not hasattr(w, "_fm") else w._fm, dt, M=M, scheme=scheme, linear=w.linear)
+    if scheme == F.SCHEME_RK4 or w.linear:
+        split = 0
+    elif scheme == F.SCHEME_FBRK32:
+        split = min(split, 1)
+    s = F.Solver(F.Mesh(w.mesh) if not hasattr(w, "_fm") else w._fm, dt, M=M, scheme=scheme, linear=w.linear,
+                 split=split)
     if labels is None:
         s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
     else:
@@ -88,16 +95,16 @@ def make_solver(F, w, scheme, dt, M, labels=None, graph=True):
     return s
 
 
-def stable(F, w, scheme, dt, steps, umax=50.0):
+def stable(F, w, scheme, dt, steps, umax=50.0, split=0):
     """Run `steps` steps; stable if the state stays finite, h > 0 and |u| < umax.
 
     Global schemes run with every cell coarse; FB-LTS with the workload's fine
     set and M (dt is then the coarse step)."""
     import numpy as np
     if scheme == F.SCHEME_FBLTS:
-        s = make_solver(F, w, scheme, dt, w.M, graph=True)
+        s = make_solver(F, w, scheme, dt, w.M, graph=True, split=split)
     else:
-        s = make_solver(F, w, scheme, dt, 1, labels=np.full(w.mesh.n_cells, 3, np.int8))
+        s = make_solver(F, w, scheme, dt, 1, labels=np.full(w.mesh.n_cells, 3, np.int8), split=split)
     s.step(steps)
     d = s.diagnostics(allow_nonfinite=True)
     if d["n_nonfinite"] > 0 or not (d["min_h"] > 0):
@@ -106,12 +113,12 @@ def stable(F, w, scheme, dt, steps, umax=50.0):
     return bool(np.max(np.abs(u)) < umax)
 
 
-def largest_stable_dt(F, w, scheme, dt0, steps=200, iters=10):
+def largest_stable_dt(F, w, scheme, dt0, steps=200, iters=10, split=0):
     """The paper's procedure: grow dt until the run becomes unstable, then bisect."""
     lo, hi = None, None
     dt = dt0
     for _ in range(20):
-        if stable(F, w, scheme, dt, steps):
+        if stable(F, w, scheme, dt, steps, split=split):
             lo = dt
             dt *= 1.5
         else:
@@ -124,14 +131,14 @@ def largest_stable_dt(F, w, scheme, dt0, steps=200, iters=10):
         dt = dt0
         for _ in range(20):
             dt /= 1.5
-            if stable(F, w, scheme, dt, steps):
+            if stable(F, w, scheme, dt, steps, split=split):
                 lo = dt
                 break
     if hi is None:
         return lo
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
-        if stable(F, w, scheme, mid, steps):
+        if stable(F, w, scheme, mid, steps, split=split):
             lo = mid
         else:
             hi = mid
@@ -147,7 +154,7 @@ def time_steps(torch, s, steps, warmup):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(w, steps):
+def cpu_baseline(w, steps, split=0):
     """The oracle (plain numpy FP64, definition mode) on a bounded sample of the workload."""
     import numpy as np
     from oracle import regions, schemes, trisk
@@ -160,7 +167,7 @@ def cpu_baseline(w, steps):
     while n < steps:
         wind = storm.edge_components(w.mesh, n * w.dt) if storm is not None else None
         ph = trisk.Physics(linear=w.linear, cd=w.cd if not w.linear else None, wind=wind)
-        u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
+        u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab, split=split)
         n += 1
         if time.perf_counter() - t0 > 20.0:
             break
@@ -190,6 +197,8 @@ def main():
         return bench_ensemble(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "aquaplanet":
+        return bench_aquaplanet(args)
     t = time.perf_counter()
     if args.workload == "hex32":
         w = workloads.config1()
@@ -202,7 +211,7 @@ def main():
     log("workload %s: N=%d E=%d fine=%d dt=%.3f M=%d (built in %.1fs)" % (
         w.name, w.mesh.n_cells, w.mesh.n_edges, int(w.fine_mask.sum()), w.dt, w.M, time.perf_counter() - t))
     w._fm = F.Mesh(w.mesh)
-    s = make_solver(F, w, F.SCHEME_FBLTS, w.dt, w.M)
+    s = make_solver(F, w, F.SCHEME_FBLTS, w.dt, w.M, split=args.split)
     info = s.info()
     from paper_2405_10505_amd import autotune
     # the profiled run replays the schedule the timed run chose (cached by shape)
@@ -251,7 +260,7 @@ def main():
     launches_per_step = edge_launches / reps
     bytes_per_launch = info["model_bytes_edge_pass"] / launches_per_step
     achieved = bytes_per_launch / (edge_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(args.workload)
+    traffic = traffic_from_profiles(args.workload) if args.split == 0 else None
     roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                 traffic=traffic, kernel="fblts::k_edge (momentum pass)", avg_launch_ms=edge_ms,
                 timing="HIP events recorded by each dispatch, %d in-step launches over %d coarse steps" % (
@@ -265,10 +274,10 @@ def main():
     if not args.no_compare:
         dt_f = w.dt / w.M
         t0 = time.perf_counter()
-        dt_fb = largest_stable_dt(F, w, F.SCHEME_FBRK32, dt_f)
+        dt_fb = largest_stable_dt(F, w, F.SCHEME_FBRK32, dt_f, split=args.split)
         dt_rk4 = largest_stable_dt(F, w, F.SCHEME_RK4, dt_f)
         # FB-LTS: the fine set and M are fixed, the coarse step is searched
-        dt_lts = largest_stable_dt(F, w, F.SCHEME_FBLTS, w.dt)
+        dt_lts = largest_stable_dt(F, w, F.SCHEME_FBLTS, w.dt, split=args.split)
         log("stable dt: FB-RK(3,2) %.3f s, RK4 %.3f s, FB-LTS coarse %.3f s (fine %.3f s), recipe coarse %.3f s "
             "(search %.1fs)" % (dt_fb, dt_rk4, dt_lts, dt_lts / w.M, w.dt, time.perf_counter() - t0))
         ks = max(20, args.steps // 2)
@@ -276,7 +285,7 @@ def main():
         for name, scheme, dt in (("fbrk32_own_limit", F.SCHEME_FBRK32, dt_fb),
                                  ("fbrk32_fine_dt", F.SCHEME_FBRK32, dt_f),
                                  ("rk4_own_limit", F.SCHEME_RK4, dt_rk4)):
-            g = make_solver(F, w, scheme, dt, 1, labels=np.full(w.mesh.n_cells, 3, np.int8))
+            g = make_solver(F, w, scheme, dt, 1, labels=np.full(w.mesh.n_cells, 3, np.int8), split=args.split)
             e = time_steps(torch, g, ks, 5)
             res[name] = dict(dt=dt, ms_per_step=e / ks * 1e3, sim_seconds_per_wall_second=dt * ks / e)
         fblts_rate = dt_lts * args.steps / el
@@ -285,12 +294,15 @@ def main():
                     **res,
                     speedup_vs_rk4=fblts_rate / res["rk4_own_limit"]["sim_seconds_per_wall_second"],
                     speedup_vs_fbrk32=fblts_rate / res["fbrk32_own_limit"]["sim_seconds_per_wall_second"],
-                    definition="time-to-solution ratio for equal simulated time (paper eq. speedup)")
+                    definition="time-to-solution ratio for equal simulated time (paper eq. speedup)",
+                    splitting=("FB-LTS and FB-RK(3,2) split (slow terms %s), RK4 unsplit" % (
+                        "per coarse step" if args.split == 1 else "per fine substep on the fine region")
+                        if args.split else "none"))
         log("speedup vs RK4 %.2fx, vs global FB-RK(3,2) %.2fx" % (comp["speedup_vs_rk4"], comp["speedup_vs_fbrk32"]))
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, 50)
+        cpu = cpu_baseline(w, 50, split=args.split)
         log("oracle: %.3e cell-substeps/s (%s)" % (cpu["value"], cpu["sample"]))
 
     out = dict(metric=METRIC, value=value, unit="cell-substeps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -300,6 +312,7 @@ def main():
                            n_vertices=w.mesh.n_vertices, n_fine=info["n_fine"], n_if1=info["n_if1"],
                            n_if2=info["n_if2"], n_int=info["n_int"], M=w.M, dt_coarse=w.dt,
                            physics="linear" if w.linear else "nonlinear+drag", scheme="FB-LTS",
+                           split=["none", "slow terms per coarse step", "slow terms per fine substep"][args.split],
                            cell_substeps_per_step=info["cell_substeps_per_step"],
                            launches_per_step=info["launches_per_step"], hipgraph=True,
                            launch_schedule=dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"])),
@@ -475,6 +488,61 @@ def bench_adjoint(args):
                fd_gradient_s_extrapolated=2 * n_params * t_fd,
                speedup_vs_fd_gradient=2 * n_params * t_fd / (t2 - t0),
                fd_check=dict(directions=20, max_rel_err=max(errs), median_rel_err=float(np.median(errs))))
+    print(json.dumps(out), flush=True)
+
+
+def bench_aquaplanet(args):
+    """The paper's temporal-convergence experiment (Section 2.4) at a larger size:
+    external gravity wave on a non-rotating, constant-depth aquaplanet (spherical
+    coastline-refined CVT, ~40k cells, 25 -> 200 km), FB-LTS with M = 4 at coarse
+    steps dt, dt/2, dt/4, dt/8 against RK4 at 10 s over 4 simulated hours; RMS
+    thickness error, fitted order, and the FB-LTS throughput on this system."""
+    import numpy as np
+    import torch
+    import paper_2405_10505_amd as F
+    from paper_2405_10505_amd.inputs import workloads
+    t = time.perf_counter()
+    w = workloads.aquaplanet(n=40000, dx_fine=25e3, dx_coarse=200e3)
+    fm = F.Mesh(w.mesh)
+    lab4, _ = fm.layer_regions(np.where(w.fine_mask, 0, 1), binary=True, r=2)
+    log("aquaplanet: N=%d fine=%d regions %s dt=%.1f (built in %.1fs)" % (
+        w.mesh.n_cells, int(w.fine_mask.sum()), np.bincount(lab4, minlength=4).tolist(), w.dt,
+        time.perf_counter() - t))
+
+    def solver(scheme, dt, M, lab):
+        s = F.Solver(fm, dt, M=M, scheme=scheme, physics=F.PHYS_GRAVITY_WAVE)
+        s.set_regions(lab, binary=False)
+        s.set_state(w.h0, w.u0)
+        s.set_graph(True)
+        return s
+
+    T = 4 * 3600.0
+    ref = solver(F.SCHEME_RK4, 10.0, 1, np.full(w.mesh.n_cells, 3, np.int8))
+    ref.step(int(round(T / 10.0)))
+    _, href = ref.get_state()
+    rows = []
+    for k in (1, 2, 4, 8):
+        n = int(round(T / (w.dt / k)))
+        dt = T / n
+        s = solver(F.SCHEME_FBLTS, dt, w.M, lab4)
+        s.step(n)
+        _, h = s.get_state()
+        rows.append(dict(dt_coarse=dt, steps=n, rms_error=float(np.sqrt(np.mean((h - href) ** 2)))))
+        log("dt %.1f s: RMS error %.3e m" % (dt, rows[-1]["rms_error"]))
+    order = float(np.polyfit(np.log([r["dt_coarse"] for r in rows]), np.log([r["rms_error"] for r in rows]), 1)[0])
+    s = solver(F.SCHEME_FBLTS, w.dt, w.M, lab4)
+    steps = args.steps or 200
+    el = time_steps(torch, s, steps, args.warmup)
+    info = s.info()
+    value = info["cell_substeps_per_step"] * steps / el
+    log("order %.3f; FB-LTS %.4f ms/step, %.3e cell-substeps/s" % (order, el / steps * 1e3, value))
+    out = dict(metric="aquaplanet gravity wave: FB-LTS temporal order and cell-substeps/s", value=value,
+               unit="cell-substeps/s", n_gpus=1, steps=steps, warmup=args.warmup, ms_per_step=el / steps * 1e3,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload=w.name, n_cells=w.mesh.n_cells, n_fine=int(w.fine_mask.sum()), M=w.M,
+                           physics="gravity wave (fast terms only)", reference="RK4, dt = 10 s",
+                           simulated_seconds=T),
+               convergence=dict(rows=rows, fitted_order=order), roofline=None, cpu_baseline=None)
     print(json.dumps(out), flush=True)
 
 

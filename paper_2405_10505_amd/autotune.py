@@ -25,10 +25,12 @@ def _sync():
 def _key(obj):
     if isinstance(obj, Solver):
         i = obj.info()
-        return "solver:N%d:E%d:F%d:scheme%d:M%d:phys%d" % (
-            i["n_cells"], i["n_edges"], i["n_fine"], obj.params.scheme, obj.params.M, obj.params.physics)
+        return "solver:N%d:E%d:F%d:scheme%d:M%d:phys%d:split%d" % (
+            i["n_cells"], i["n_edges"], i["n_fine"], obj.params.scheme, obj.params.M, obj.params.physics,
+            obj.params.split)
     i = obj.info()
-    return "ensemble:mc%d:members%s:M%d" % (i["member_cells"], "-".join(map(str, obj.members)), obj.params.M)
+    return "ensemble:mc%d:members%s:M%d:phys%d:split%d" % (i["member_cells"], "-".join(map(str, obj.members)),
+                                                           obj.params.M, obj.params.physics, obj.params.split)
 
 
 def _save(obj):
