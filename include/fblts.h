@@ -229,8 +229,19 @@ int fblts_set_graph(fblts_solver* s, int32_t enable);
  *     per-edge prep pass, one launch fewer per stage; 0 runs a vertex pass.
  *   FBLTS_OPT_BLOCK: threads per block of the stencil passes, 64/128/256
  *     (default 256).
- * Errors: FBLTS_EINVAL for an unknown option or value. */
-enum { FBLTS_OPT_FUSE_VERTEX = 1, FBLTS_OPT_BLOCK = 2 };
+ *   FBLTS_OPT_EDGE_CELLS: 1 forms the PV flux of the momentum pass (eq.
+ *     trisk_vorticity) by walking the edge lists of the edge's two cells and
+ *     building each TRiSK weight n_{e,i} n_{e',i} (1/2 - sum of the kite
+ *     fractions R_{i,v} passed) on the fly, instead of reading the
+ *     edges_on_edge list and its stored weights: about half the momentum
+ *     pass's compulsory bytes.  Available (after set_regions) when the mesh's
+ *     edges_on_edge lists and weights are those walks, in that order (each
+ *     cell's edges counter-clockwise after e, the first cell's first); bit for
+ *     bit identical when the stored weights equal the walk's FP64 arithmetic
+ *     exactly, else within 1e-13 of them.  Default 0.
+ * Errors: FBLTS_EINVAL for an unknown option or value, or EDGE_CELLS on a
+ * mesh whose weights are not the kite-fraction walks. */
+enum { FBLTS_OPT_FUSE_VERTEX = 1, FBLTS_OPT_BLOCK = 2, FBLTS_OPT_EDGE_CELLS = 3 };
 int fblts_set_option(fblts_solver* s, int32_t option, int32_t value);
 
 typedef struct {

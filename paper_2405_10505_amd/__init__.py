@@ -20,7 +20,7 @@ SCHEME_FBLTS, SCHEME_FBRK32, SCHEME_RK4 = 0, 1, 2
 PHYS_LINEAR, PHYS_NONLINEAR, PHYS_GRAVITY_WAVE = 0, 1, 2
 SPLIT_NONE, SPLIT_COARSE, SPLIT_FINE = 0, 1, 2
 BETA = (0.531, 0.531, 0.313)
-OPT_FUSE_VERTEX, OPT_BLOCK = 1, 2
+OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS = 1, 2, 3
 
 _P_i32 = C.POINTER(C.c_int32)
 _P_f64 = C.POINTER(C.c_double)
@@ -126,11 +126,15 @@ _lib = None
 
 
 def lib():
-    """The loaded libfblts.so (raises ImportError if it has not been built)."""
+    """The loaded libfblts.so (raises ImportError if it has not been built).
+
+    The environment variable FBLTS_LIB names another build of the library to
+    load instead (same C ABI), e.g. to compare two builds on one machine."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError("libfblts.so is not built (%s); run paper_2405_10505_amd.build_lib.build()" % LIB_PATH)
+        path = os.environ.get("FBLTS_LIB", LIB_PATH)
+        if not os.path.exists(path):
+            raise ImportError("libfblts.so is not built (%s); run paper_2405_10505_amd.build_lib.build()" % path)
         # Load PyTorch's HIP runtime first when PyTorch is present: libfblts
         # then binds to that same runtime (both carry SONAME libamdhip64.so.7),
         # so tensors, streams and the library share one device context.
@@ -138,7 +142,7 @@ def lib():
             import torch  # noqa: F401
         except ImportError:
             pass
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
             f.restype = res

@@ -1,7 +1,8 @@
 """Launch-schedule autotuner for a Solver or an Ensemble.
 
 Searches the library's tuning options (fused vertex evaluation on/off, block
-size 64/128/256), timing hipGraph-replayed coarse steps for each candidate,
+size 64/128/256, momentum pass through the cells' edge lists on/off where the
+mesh allows it), timing hipGraph-replayed coarse steps for each candidate,
 and keeps the fastest.  All candidates produce identical bits, so tuning never
 changes results; the state is saved before and restored after the search.
 Results are cached in a JSON file keyed by the workload's shape.
@@ -12,9 +13,9 @@ import json
 import os
 import time
 
-from . import OPT_BLOCK, OPT_FUSE_VERTEX, Ensemble, Solver
+from . import OPT_BLOCK, OPT_EDGE_CELLS, OPT_FUSE_VERTEX, Ensemble, FBLTSError, Solver
 
-CANDIDATES = [(fuse, bs) for fuse in (1, 0) for bs in (256, 128, 64)]
+CANDIDATES = [(fuse, bs, cells) for cells in (0, 1) for fuse in (1, 0) for bs in (256, 128, 64)]
 
 
 def _sync():
@@ -51,7 +52,17 @@ def _restore(obj, saved):
 def apply(obj, choice):
     obj.set_option(OPT_FUSE_VERTEX, choice["fuse_vertex"])
     obj.set_option(OPT_BLOCK, choice["block"])
+    obj.set_option(OPT_EDGE_CELLS, choice.get("edge_cells", 0))
     obj.set_graph(True)
+
+
+def _cells_available(obj):
+    try:
+        obj.set_option(OPT_EDGE_CELLS, 1)
+    except FBLTSError:
+        return False
+    obj.set_option(OPT_EDGE_CELLS, 0)
+    return True
 
 
 def autotune(obj, steps=20, repeats=3, cache_path=None, verbose=False):
@@ -68,8 +79,11 @@ def autotune(obj, steps=20, repeats=3, cache_path=None, verbose=False):
             return cache[key]
     saved = _save(obj)
     results = []
-    for fuse, bs in CANDIDATES:
-        choice = dict(fuse_vertex=fuse, block=bs)
+    cells_ok = _cells_available(obj)
+    for fuse, bs, cells in CANDIDATES:
+        if cells and not cells_ok:
+            continue
+        choice = dict(fuse_vertex=fuse, block=bs, edge_cells=cells)
         apply(obj, choice)
         obj.step(2)                      # capture the graph and warm up
         _sync()
@@ -81,7 +95,8 @@ def autotune(obj, steps=20, repeats=3, cache_path=None, verbose=False):
             best = min(best, (time.perf_counter() - t0) / steps)
         results.append((best, choice))
         if verbose:
-            print("autotune %s fuse=%d block=%d: %.4f ms/step" % (key, fuse, bs, best * 1e3), flush=True)
+            print("autotune %s fuse=%d block=%d cells=%d: %.4f ms/step" % (key, fuse, bs, cells, best * 1e3),
+                  flush=True)
     _restore(obj, saved)
     best_t, choice = min(results, key=lambda r: r[0])
     choice = dict(choice, ms_per_step=best_t * 1e3,

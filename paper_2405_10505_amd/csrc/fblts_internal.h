@@ -52,6 +52,9 @@ struct MeshDev {
   const double* e_wT;      // [maxEOE][es]  w_{e2,e} for e2 = e_eoe[j][e] (0 on padding)
   const int* c_vert;       // [maxE][cs]    vertices of the cell (ccw; padding repeats slot 0)
   const double* c_kite;    // [maxE][cs]    kite area of the cell at that vertex (0 on padding)
+  // momentum pass through the cells' edge lists
+  const double* c_R;       // [maxE][cs]    kite fraction R_{i,v} = kite / A_i (0 on padding)
+  const int* e_cs;         // [E] slot0 | deg0 << 4 | slot1 << 8 | deg1 << 12
 };
 
 // Thickness pass: Psi, FB stage update, FB-averaged thickness and Bernoulli

@@ -205,7 +205,64 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
 }
 
 // ---------------------------------------------------------------- edge pass
-template <bool DRAG, bool WIND>
+// PV flux through one cell's edge list (CELLS variant of the momentum pass):
+// walk the cell's other edges counter-clockwise starting after e and form the
+// TRiSK weight w = n_{e,i} n_{e',i} (1/2 - sum of the kite fractions passed),
+// the same weights, in the same order, as the cell's part of e's
+// edges_on_edge list.  w = (slot << 0) | (degree << 4) of e in this cell.
+template <bool NEED_U>
+__device__ __forceinline__ void walk_cell(const MeshDev& m, const double4* __restrict__ P, int i, int w,
+                                          double pey, int nm, int mem, double& sq, double& su) {
+  constexpr int U = kUnrollCell - 1;   // walk positions whose loads issue together
+  const int j0 = w & 15, n = (w >> 4) & 15;
+  const int se = m.c_edge[j0 * m.cs + i] & 1;
+  int code[U];
+  double R[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    // position t + 1: previous slot (j0 + t) mod n, slot (j0 + t + 1) mod n;
+    // positions past the degree load valid slots and are masked below
+    int jp = j0 + t;
+    jp -= jp >= n ? n : 0;
+    jp -= jp >= n ? n : 0;
+    int j = jp + 1;
+    j -= j >= n ? n : 0;
+    R[t] = m.c_R[jp * m.cs + i];
+    code[t] = m.c_edge[j * m.cs + i];
+  }
+  double4 p2[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) p2[t] = P[(long)(code[t] >> 1) * nm + mem];
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < U; ++t) {
+    if (t + 1 < n) {
+      acc = acc + R[t];
+      double wt = 0.5 - acc;
+      wt = (code[t] & 1) != se ? -wt : wt;
+      sq = fma(wt * p2[t].x, pey + p2[t].y, sq);
+      if (NEED_U) su = fma(wt, p2[t].z, su);
+    }
+  }
+  int j = j0 + U;
+  while (j >= n) j -= n;
+  for (int mm = U + 1; mm < n; ++mm) {
+    const int jp = j;
+    j = j + 1 == n ? 0 : j + 1;
+    acc = acc + m.c_R[jp * m.cs + i];
+    const int c = m.c_edge[j * m.cs + i];
+    double wt = 0.5 - acc;
+    wt = (c & 1) != se ? -wt : wt;
+    const double4 q = P[(long)(c >> 1) * nm + mem];
+    sq = fma(wt * q.x, pey + q.y, sq);
+    if (NEED_U) su = fma(wt, q.z, su);
+  }
+}
+
+// CELLS: the PV flux through the two cells' edge lists and kite fractions
+// (walk_cell) instead of the edges_on_edge list and stored weights; only for
+// meshes whose stored weights are exactly those walks (the planner checks).
+template <bool DRAG, bool WIND, bool CELLS>
 __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg(L, b);
@@ -221,19 +278,25 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const long ee = (long)e * nm + mem;
   const double4 pe = P[ee];
   double sq = 0.0, su = 0.0;
-  const int n = m.e_neoe[e];
-  auto slot = [&](int j) {
-    const int e2 = m.e_eoe[j * m.es + e];
-    const double w = m.e_w[j * m.es + e];
-    const double4 p2 = P[(long)e2 * nm + mem];
-    sq = fma(w * p2.x, pe.y + p2.y, sq);
-    if (DRAG || WIND) su = fma(w, p2.z, su);
-  };
-  // the first kUnrollEOE slots exist for every edge (padded with the edge
-  // itself at weight 0, an exact no-op): their loads issue together
+  if (CELLS) {
+    const int w = m.e_cs[e];
+    walk_cell<DRAG || WIND>(m, P, m.e_cell[e], w & 0xff, pe.y, nm, mem, sq, su);
+    walk_cell<DRAG || WIND>(m, P, m.e_cell[m.es + e], (w >> 8) & 0xff, pe.y, nm, mem, sq, su);
+  } else {
+    const int n = m.e_neoe[e];
+    auto slot = [&](int j) {
+      const int e2 = m.e_eoe[j * m.es + e];
+      const double w = m.e_w[j * m.es + e];
+      const double4 p2 = P[(long)e2 * nm + mem];
+      sq = fma(w * p2.x, pe.y + p2.y, sq);
+      if (DRAG || WIND) su = fma(w, p2.z, su);
+    };
+    // the first kUnrollEOE slots exist for every edge (padded with the edge
+    // itself at weight 0, an exact no-op): their loads issue together
 #pragma unroll
-  for (int j = 0; j < kUnrollEOE; ++j) slot(j);
-  for (int j = kUnrollEOE; j < n; ++j) slot(j);
+    for (int j = 0; j < kUnrollEOE; ++j) slot(j);
+    for (int j = kUnrollEOE; j < n; ++j) slot(j);
+  }
   const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
   const double idc = m.e_invdc[e];
   double phi = 0.5 * sq * idc - (S.B[(long)c1 * nm + mem] - S.B[(long)c0 * nm + mem]) * idc;
@@ -552,13 +615,19 @@ int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st) {
   return nb;
 }
 
-int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st) {
+template <bool CELLS>
+static void launch_edge_t(const Launch<EdgeSeg>& L, bool drag, bool wind, int nb, int bs, hipStream_t st) {
+  if (drag && wind) launch_timed(k_edge<true, true, CELLS>, nb, bs, st, L);
+  else if (drag) launch_timed(k_edge<true, false, CELLS>, nb, bs, st, L);
+  else if (wind) launch_timed(k_edge<false, true, CELLS>, nb, bs, st, L);
+  else launch_timed(k_edge<false, false, CELLS>, nb, bs, st, L);
+}
+
+int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st, bool cells) {
   const int nb = blocks_for(L, edge_items, bs);
   if (nb == 0) return 0;
-  if (drag && wind) launch_timed(k_edge<true, true>, nb, bs, st, L);
-  else if (drag) launch_timed(k_edge<true, false>, nb, bs, st, L);
-  else if (wind) launch_timed(k_edge<false, true>, nb, bs, st, L);
-  else launch_timed(k_edge<false, false>, nb, bs, st, L);
+  if (cells) launch_edge_t<true>(L, drag, wind, nb, bs, st);
+  else launch_edge_t<false>(L, drag, wind, nb, bs, st);
   return nb;
 }
 

@@ -690,6 +690,53 @@ void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm) {
       }
     }
   }
+  // kite fractions per cell slot and the per-edge slot/degree word; then check
+  // that the mesh's edges_on_edge lists and weights are the cell walks
+  pm.c_R.assign((size_t)maxE * pm.cs, 0.0);
+  for (int in = 0; in < N; ++in) {
+    const int n = pm.c_nedge[in];
+    for (int j = 0; j < n; ++j) pm.c_R[(size_t)j * pm.cs + in] = pm.c_kite[(size_t)j * pm.cs + in] / pm.c_A[in];
+  }
+  pm.e_cs.assign(E, 0);
+  pm.kite_weights = maxE <= 15 ? 2 : 0;
+  for (int in = 0; in < N && pm.kite_weights; ++in) {
+    const int n = pm.c_nedge[in];
+    if (n < 3) pm.kite_weights = 0;
+    for (int j = 0; j < n; ++j) {
+      const int en = pm.c_edge[(size_t)j * pm.cs + in] >> 1;
+      const int side = pm.e_cell[en] == in ? 0 : 1;
+      pm.e_cs[en] |= (j | (n << 4)) << (8 * side);
+    }
+  }
+  for (int en = 0; en < E && pm.kite_weights; ++en) {
+    int k = 0;
+    for (int side = 0; side < 2 && pm.kite_weights; ++side) {
+      const int in = pm.e_cell[(size_t)side * pm.es + en];
+      const int w = (pm.e_cs[en] >> (8 * side)) & 0xff, j0 = w & 15, n = w >> 4;
+      if (n != pm.c_nedge[in] || j0 >= n || (pm.c_edge[(size_t)j0 * pm.cs + in] >> 1) != en) {
+        pm.kite_weights = 0;   // e.g. an edge whose two cells coincide
+        break;
+      }
+      const int se = pm.c_edge[(size_t)j0 * pm.cs + in] & 1;
+      double acc = 0.0;
+      int j = j0;
+      for (int mm = 1; mm < n; ++mm, ++k) {
+        const int jp = j;
+        j = j + 1 == n ? 0 : j + 1;
+        acc = acc + pm.c_R[(size_t)jp * pm.cs + in];
+        const int code = pm.c_edge[(size_t)j * pm.cs + in];
+        double wt = 0.5 - acc;
+        if ((code & 1) != se) wt = -wt;
+        if (k >= pm.e_neoe[en] || pm.e_eoe[(size_t)k * pm.es + en] != (code >> 1)) {
+          pm.kite_weights = 0;
+          break;
+        }
+        const double d = std::fabs(wt - pm.e_w[(size_t)k * pm.es + en]);
+        if (d != 0.0) pm.kite_weights = d <= 1e-13 ? std::min(pm.kite_weights, 1) : 0;
+      }
+    }
+    if (k != pm.e_neoe[en]) pm.kite_weights = 0;
+  }
   pm.v_edge.assign(3 * (size_t)pm.vs, 0);
   pm.v_cell.assign(3 * (size_t)pm.vs, 0);
   pm.v_kite.assign(3 * (size_t)pm.vs, 0.0);
@@ -800,11 +847,11 @@ double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int n
         } else {
           // the vertex's own data: codes, cells, kites, 1/A_v, f_v; and its
           // edges' d_e, u and cells' h* when not already counted
-          b += 3 * (4 + 4 + 8) + 8 + 8;
+          b += 3 * (4 + 4 + 8) + 8 + 8;   // codes, cells, kites, 1/A_v, f_v
           for (int t = 0; t < 3; ++t) {
             const int e2 = pm.v_edge[(size_t)t * pm.vs + v] >> 1;
-            if (se.mark(e2)) b += 8 + S;
-            else b += 8;                   // d_e of an edge in the range
+            if (se.mark(e2)) b += 8 + S;    // d_e, u
+            else b += 8;                    // d_e of an edge in the range
             if (sc.mark(pm.v_cell[(size_t)t * pm.vs + v])) b += S;
           }
         }
@@ -834,6 +881,34 @@ double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool
       if (sp.mark(pm.e_eoe[(size_t)j * pm.es + e])) b += 4 * S;
     for (int j = 0; j < 2; ++j)
       if (sc.mark(pm.e_cell[(size_t)j * pm.es + e])) b += S + (drag ? S : 0);   // B (+ C_D)
+  }
+  return b;
+}
+
+double bytes_edge_cells_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm) {
+  const double S = 8.0 * nm;
+  double b = 0;
+  Stamp sp(pm.E), sc(pm.N);
+  sp.next();
+  sc.next();
+  for (int e = r.edge.b; e < r.edge.e; ++e) {
+    b += 8 + 4 + 8;                          // cells, slot/degree word, 1/d_e
+    const bool upd = e >= r.edge_upd.b && e < r.edge_upd.e;
+    const bool acc = e >= r.edge_acc.b && e < r.edge_acc.e;
+    if (upd) b += 2 * S;                     // U0, Udst
+    if (acc) b += 2 * S;
+    if (drag || wind) b += S;                // u of the edge
+    if (wind) b += 16;
+    if (sp.mark(e)) b += 4 * S;
+    for (int j = 0; j < 2; ++j) {
+      const int c = pm.e_cell[(size_t)j * pm.es + e];
+      if (sc.mark(c)) {
+        const int n = pm.c_nedge[c];
+        b += S + (drag ? S : 0) + 4 + n * (4.0 + 8.0);   // B (+ C_D), degree, edge codes, R
+        for (int k = 0; k < n; ++k)
+          if (sp.mark(pm.c_edge[(size_t)k * pm.cs + c] >> 1)) b += 4 * S;   // records of the cell's edges
+      }
+    }
   }
   return b;
 }

@@ -70,6 +70,14 @@ struct PermMesh {
   std::vector<double> v_kite, v_invA, v_A, v_f, v_q0;
   std::vector<double> e_wT, c_kite;
   std::vector<int> c_vert;
+  // momentum pass through the cells' edge lists: kite fraction R_{i,v} per
+  // cell slot, and per edge the slot of the edge in each of its two cells and
+  // those cells' degrees (4 bits each: slot0 | deg0<<4 | slot1<<8 | deg1<<12)
+  std::vector<double> c_R;
+  std::vector<int> e_cs;
+  // 2: the mesh's edges_on_edge lists and weights are exactly the cell walks
+  // with w = n_{e,i} n_{e',i} (1/2 - sum R) (bitwise); 1: within 1e-13; 0: not
+  int kite_weights = 0;
 };
 void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm);
 
@@ -80,6 +88,8 @@ double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear,
 double bytes_vert_pass(const PermMesh& pm, const Range& r, int nm);
 double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm, bool fuse_q = false);
 double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm);
+// momentum pass walking the two cells' edge lists (weights from kite fractions)
+double bytes_edge_cells_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm);
 // fast momentum pass of the operator splitting (pressure gradient + frozen slow tendency)
 double bytes_edge_fast_pass(const PermMesh& pm, const StageRanges& r, bool slow, int nm);
 

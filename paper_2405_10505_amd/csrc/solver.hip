@@ -31,7 +31,7 @@ namespace fblts {
 int launch_cell(Launch<CellSeg> L, int mode, int bs, hipStream_t st);
 int launch_vertex(Launch<VertSeg> L, int bs, hipStream_t st);
 int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st);
-int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st);
+int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st, bool cells);
 int launch_edge_fast(Launch<EdgeSeg> L, bool slow, int bs, hipStream_t st);
 int launch_predict(Launch<PredSeg> L, hipStream_t st);
 int launch_assemble(Launch<AsmSeg> L, hipStream_t st);
@@ -126,7 +126,7 @@ struct DevMesh {
   DevBuf c_nedge, c_edge, c_nbr, c_invA, c_A, c_H;
   DevBuf e_cell, e_vert, e_dc, e_dv, e_invdc, e_He, e_neoe, e_eoe, e_w;
   DevBuf v_edge, v_cell, v_kite, v_invA, v_A, v_f, v_q0;
-  DevBuf e_wT, c_vert, c_kite;
+  DevBuf e_wT, c_vert, c_kite, c_R, e_cs;
   DevBuf cell_n2o, edge_n2o, vert_n2o;
   MeshDev md{};
   void upload_from(const PermMesh& pm, const Plan& p) {
@@ -155,6 +155,8 @@ struct DevMesh {
     upload(e_wT, pm.e_wT);
     upload(c_vert, pm.c_vert);
     upload(c_kite, pm.c_kite);
+    upload(c_R, pm.c_R);
+    upload(e_cs, pm.e_cs);
     upload(cell_n2o, p.cell_new2old);
     upload(edge_n2o, p.edge_new2old);
     upload(vert_n2o, p.vert_new2old);
@@ -191,6 +193,8 @@ struct DevMesh {
     md.e_wT = e_wT.as<double>();
     md.c_vert = c_vert.as<int>();
     md.c_kite = c_kite.as<double>();
+    md.c_R = c_R.as<double>();
+    md.e_cs = e_cs.as<int>();
   }
 };
 
@@ -250,6 +254,7 @@ struct Pass {
   bool fuse_q = false;   // PREP: evaluate q_v in the prep pass (no vertex pass)
   int cell_mode = 1;     // CELL: 0 linear, 1 nonlinear, 2 fast terms (k_cell<MODE>)
   bool edge_fast = false;   // EDGE: fast momentum pass (k_edge_fast)
+  bool edge_cells = false;  // EDGE: PV flux through the cells' edge lists (k_edge<., ., true>)
   int bs = kBlock;       // threads per block of the stencil passes
 };
 
@@ -295,7 +300,15 @@ void check_params(const fblts_params* p) {
 }
 
 // Build the pass list of one mesh unit (segments are merged by the caller).
-void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, const Plan* plan = nullptr) {
+// Launch-structure options (results are bitwise identical across them).
+struct LaunchOpts {
+  bool fuse_q = true;        // q_v evaluated inside the prep pass
+  int block = kBlock;        // threads per block of the stencil passes
+  bool edge_cells = false;   // momentum pass through the cells' edge lists
+};
+
+void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, const Plan* plan = nullptr,
+                       bool edge_cells = false) {
   const fblts_params& p = P.p;
   const bool nl = P.nonlinear();
   const MeshDev& md = u.dm.md;
@@ -389,6 +402,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     Pass ps;
     ps.kind = Pass::EDGE;
     ps.edge_fast = fast_pass;
+    ps.edge_cells = edge_cells && !fast_pass;
     ps.edge.nseg = 1;
     EdgeSeg& e = ps.edge.seg[0];
     e.m = md;
@@ -414,7 +428,8 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     e.rho_ratio = p.rho_air / p.rho_water;
     e.slow = fast_pass ? slow : nullptr;
     ps.model_bytes = fast_pass ? bytes_edge_fast_pass(u.pm, r, slow != nullptr, nm)
-                               : bytes_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
+                     : ps.edge_cells ? bytes_edge_cells_pass(u.pm, r, drag_on, s.has_wind, nm)
+                                     : bytes_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
     u.bytes_edge += ps.model_bytes;
     u.edge_items += (int64_t)r.edge.size() * nm;
     ps.tag = cur_tag;
@@ -599,8 +614,11 @@ void add_forcing_passes(MeshUnit& u) {
   u.passes.push_back(t);
 }
 
-void build_passes(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, int bs) {
-  build_passes_impl(u, P, drag_on, fuse_q);
+void build_passes(MeshUnit& u, const Params& P, bool drag_on, const LaunchOpts& o) {
+  const int bs = o.block;
+  if (o.edge_cells && u.pm.kite_weights == 0)
+    throw Err(FBLTS_EINVAL, "the mesh's edges_on_edge weights are not the kite-fraction walks of its cells");
+  build_passes_impl(u, P, drag_on, o.fuse_q, nullptr, o.edge_cells);
   add_forcing_passes(u);
   for (Pass& p : u.passes) p.bs = bs;
 }
@@ -688,7 +706,7 @@ void run_passes(const std::vector<Pass>& passes, bool drag, bool wind, hipStream
       case Pass::PREP: nb = launch_prep(ps.prep, ps.fuse_q, ps.bs, st); break;
       case Pass::EDGE:
         nb = ps.edge_fast ? launch_edge_fast(ps.edge, ps.edge.seg[0].slow != nullptr, ps.bs, st)
-                          : launch_edge(ps.edge, drag, wind, ps.bs, st);
+                          : launch_edge(ps.edge, drag, wind, ps.bs, st, ps.edge_cells);
         break;
       case Pass::PRED: launch_predict(ps.pred, st); break;
       case Pass::ASM: launch_assemble(ps.asmb, st); break;
@@ -949,8 +967,7 @@ struct fblts_solver {
   int device = 0;
   std::unique_ptr<MeshUnit> unit;
   bool have_regions = false, have_state = false, drag_on = false;
-  bool fuse_q = true;
-  int block = kBlock;
+  LaunchOpts opt;
   bool graph_on = false, graph_valid = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -976,8 +993,7 @@ struct fblts_solver {
 
 struct fblts_ensemble {
   Params P;
-  bool fuse_q = true;
-  int block = kBlock;
+  LaunchOpts opt;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<std::unique_ptr<MeshUnit>> units;
@@ -1163,7 +1179,7 @@ int fblts_set_regions(fblts_solver* s, const int8_t* labels, int32_t binary) {
     setup_unit(*u, s->mesh->hm, s->P, labels, binary != 0, 1);
     s->unit = std::move(u);
     s->drag_on = false;
-    build_passes(*s->unit, s->P, s->drag_on, s->fuse_q, s->block);
+    build_passes(*s->unit, s->P, s->drag_on, s->opt);
     s->have_regions = true;
     return FBLTS_OK;
   });
@@ -1215,7 +1231,7 @@ int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device) {
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
       s->drag_on = true;
     }
-    build_passes(u, s->P, s->drag_on, s->fuse_q, s->block);
+    build_passes(u, s->P, s->drag_on, s->opt);
     return FBLTS_OK;
   });
 }
@@ -1254,7 +1270,7 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
       u.st.has_wind = true;
     }
-    build_passes(u, s->P, s->drag_on, s->fuse_q, s->block);
+    build_passes(u, s->P, s->drag_on, s->opt);
     return FBLTS_OK;
   });
 }
@@ -1335,7 +1351,7 @@ int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_e
       launch_cyclone(a, s->stream);
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     }
-    build_passes(u, s->P, s->drag_on, s->fuse_q, s->block);
+    build_passes(u, s->P, s->drag_on, s->opt);
     return FBLTS_OK;
   });
 }
@@ -1365,14 +1381,18 @@ int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->drop_graph();
     if (option == FBLTS_OPT_FUSE_VERTEX) {
-      s->fuse_q = value != 0;
+      s->opt.fuse_q = value != 0;
     } else if (option == FBLTS_OPT_BLOCK) {
       if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
-      s->block = value;
+      s->opt.block = value;
+    } else if (option == FBLTS_OPT_EDGE_CELLS) {
+      if (value && (!s->have_regions || s->unit->pm.kite_weights == 0))
+        throw Err(FBLTS_EINVAL, "edge-via-cells needs set_regions first and kite-derived TRiSK weights");
+      s->opt.edge_cells = value != 0;
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
-    if (s->have_regions) build_passes(*s->unit, s->P, s->drag_on, s->fuse_q, s->block);
+    if (s->have_regions) build_passes(*s->unit, s->P, s->drag_on, s->opt);
     return FBLTS_OK;
   });
 }
@@ -1642,7 +1662,7 @@ int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const 
       es.c_dt = 0;
       es.acc_w = 1;
       es.rho_ratio = s->P.p.rho_air / s->P.p.rho_water;
-      launch_edge(ee, s->drag_on, U.st.has_wind, kBlock, s->stream);
+      launch_edge(ee, s->drag_on, U.st.has_wind, kBlock, s->stream, false);
     }
     const int n = which == 0 ? N : E;
     const int* perm = which == 0 ? U.dm.cell_n2o.as<int>() : U.dm.edge_n2o.as<int>();
@@ -1683,7 +1703,7 @@ int fblts_ensemble_create(const fblts_mesh* const* meshes, const int8_t* const* 
       if (!meshes[k]) throw Err(FBLTS_EINVAL, "mesh is NULL");
       auto u = std::make_unique<MeshUnit>();
       setup_unit(*u, meshes[k]->hm, e->P, cell_labels ? cell_labels[k] : nullptr, binary != 0, nm);
-      build_passes(*u, e->P, e->P.nonlinear(), e->fuse_q, e->block);
+      build_passes(*u, e->P, e->P.nonlinear(), e->opt);
       units.push_back(u.get());
       e->units.push_back(std::move(u));
     }
@@ -1757,16 +1777,21 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
     if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
     hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     if (option == FBLTS_OPT_FUSE_VERTEX) {
-      e->fuse_q = value != 0;
+      e->opt.fuse_q = value != 0;
     } else if (option == FBLTS_OPT_BLOCK) {
       if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
-      e->block = value;
+      e->opt.block = value;
+    } else if (option == FBLTS_OPT_EDGE_CELLS) {
+      for (auto& u : e->units)
+        if (value && u->pm.kite_weights == 0)
+          throw Err(FBLTS_EINVAL, "edge-via-cells needs kite-derived TRiSK weights on every mesh");
+      e->opt.edge_cells = value != 0;
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
     std::vector<MeshUnit*> units;
     for (auto& u : e->units) {
-      build_passes(*u, e->P, e->P.nonlinear(), e->fuse_q, e->block);
+      build_passes(*u, e->P, e->P.nonlinear(), e->opt);
       units.push_back(u.get());
     }
     e->passes = merge_passes(units);

@@ -25,6 +25,7 @@ Conventions (all 0-based):
 """
 from __future__ import annotations
 
+import json
 import math
 from dataclasses import dataclass, field
 
@@ -95,6 +96,26 @@ class Mesh:
             f_vertex=f64(self.f_vertex), f_edge=f64(self.f_edge),
             bottom_depth=f64(self.bottom_depth),
         )
+
+    def save(self, path):
+        """Write the arrays and scalar fields to an .npz file (no pickled objects;
+        ``meta`` entries that are not plain numbers or strings are dropped)."""
+        arrays, scalars = {}, {}
+        for k, v in self.__dict__.items():
+            if isinstance(v, np.ndarray):
+                arrays[k] = v
+            elif k != "meta" and v is not None:
+                scalars[k] = v
+        meta = {k: v for k, v in self.meta.items() if isinstance(v, (int, float, str))}
+        np.savez(path, __scalars__=np.array(json.dumps(scalars)), __meta__=np.array(json.dumps(meta)), **arrays)
+
+    @staticmethod
+    def load(path):
+        with np.load(path, allow_pickle=False) as z:
+            d = {k: z[k] for k in z.files if not k.startswith("__")}
+            d.update(json.loads(str(z["__scalars__"])))
+            meta = json.loads(str(z["__meta__"]))
+        return Mesh(meta=meta, **d)
 
     def copy_with(self, **kw):
         d = dict(self.__dict__)

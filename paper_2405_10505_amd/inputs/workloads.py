@@ -17,6 +17,7 @@ drawn from ``numpy.random.Generator(PCG64(seed))``.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -260,6 +261,16 @@ def sphere_mesh(n=400000, seed_coast=5, iters=20, dx_fine=6e3, dx_coarse=60e3, p
     if key in _SPHERE_CACHE:
         return _SPHERE_CACHE[key]
     coast = Coastline(seed_coast)
+    # optional on-disk cache (directory in FBLTS_MESH_CACHE) of the generated mesh
+    cache_dir = os.environ.get("FBLTS_MESH_CACHE")
+    cache_file = None
+    if cache_dir:
+        cache_file = os.path.join(cache_dir, "sphere_%d_%d_%d_%g_%g.npz" % key)
+        if os.path.exists(cache_file):
+            m = meshgen.Mesh.load(cache_file)
+            m.meta["coast"] = coast
+            _SPHERE_CACHE[key] = m
+            return m
     dx, D = sphere_dx_factory(coast, n, dx_fine=dx_fine, dx_coarse=dx_coarse)
     levels = 0
     n0 = n
@@ -288,6 +299,9 @@ def sphere_mesh(n=400000, seed_coast=5, iters=20, dx_fine=6e3, dx_coarse=60e3, p
     pts = pts[meshgen.morton_order_sphere(pts)]
     m = meshgen.sphere_from_generators(pts)
     m.meta.update(kind="sphere", n=m.n_cells, seed=seed_coast, iters=iters, levels=levels, D=D)
+    if cache_file:
+        os.makedirs(cache_dir, exist_ok=True)
+        m.save(cache_file)
     m.meta["coast"] = coast
     _SPHERE_CACHE[key] = m
     return m

@@ -191,16 +191,19 @@ def test_nonfinite_reported(cvt):
     assert e.value.code == F.FBLTS_ENONFINITE
 
 
-@pytest.mark.parametrize("fuse,bs", [(0, 256), (1, 64), (0, 128), (1, 128)])
+@pytest.mark.parametrize("fuse,bs,cells", [(0, 256, 0), (1, 64, 0), (0, 128, 0), (1, 128, 0), (1, 256, 1),
+                                           (0, 64, 1)])
 @pytest.mark.parametrize("name", ["c1", "cvt"])
-def test_launch_options_bitwise(name, fuse, bs, request):
-    """Tuning options change the launch structure only: results are bitwise equal."""
+def test_launch_options_bitwise(name, fuse, bs, cells, request):
+    """Tuning options change the launch structure only: results are bitwise equal
+    (the generated meshes' weights are exactly the kite-fraction walks)."""
     w, om, lab, fm = request.getfixturevalue(name)
     ref = _solver(fm, w)
     ref.step(4)
     s = _solver(fm, w)
     s.set_option(F.OPT_FUSE_VERTEX, fuse)
     s.set_option(F.OPT_BLOCK, bs)
+    s.set_option(F.OPT_EDGE_CELLS, cells)
     s.step(4)
     hr, ur = ref.get_state()
     hs, us = s.get_state()
@@ -214,12 +217,13 @@ def test_autotuner_restores_state_and_picks_a_candidate(cvt, tmp_path):
     s.step(3)
     h0, u0 = s.get_state()
     choice = autotune.autotune(s, steps=5, repeats=1, cache_path=str(tmp_path / "tune.json"))
-    assert (choice["fuse_vertex"], choice["block"]) in autotune.CANDIDATES
+    assert (choice["fuse_vertex"], choice["block"], choice["edge_cells"]) in autotune.CANDIDATES
     h1, u1 = s.get_state()
     assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
     # cached: a second call returns the same choice without timing
     again = autotune.autotune(s, cache_path=str(tmp_path / "tune.json"))
-    assert (again["fuse_vertex"], again["block"]) == (choice["fuse_vertex"], choice["block"])
+    assert (again["fuse_vertex"], again["block"], again["edge_cells"]) == (
+        choice["fuse_vertex"], choice["block"], choice["edge_cells"])
 
 
 def test_dispatch_timing_mode_counts_launches_and_keeps_results(cvt):
@@ -242,3 +246,35 @@ def test_dispatch_timing_mode_counts_launches_and_keeps_results(cvt):
     hs, us = s.get_state()
     assert np.array_equal(hr, hs) and np.array_equal(ur, us)
     assert info["launches_per_step"] > 0
+
+
+def test_edge_cells_rejected_for_foreign_weights(cvt):
+    """A mesh whose stored weights are not the kite-fraction walks cannot use the
+    cell-walk momentum pass; the default pass still runs on it."""
+    w, om, lab, fm = cvt
+    bad = w.mesh.copy_with(weights_on_edge=w.mesh.weights_on_edge * (1 + 1e-9))
+    s = F.Solver(F.Mesh(bad), w.dt, M=w.M)
+    s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+    with pytest.raises(F.FBLTSError) as e:
+        s.set_option(F.OPT_EDGE_CELLS, 1)
+    assert e.value.code == F.FBLTS_EINVAL
+    s.set_state(w.h0, w.u0)
+    s.step(1)
+
+
+def test_edge_cells_on_the_sphere_with_cyclone_bitwise():
+    import dataclasses
+    w = workloads.small_sphere()
+    fm = F.Mesh(w.mesh)
+    storm = dataclasses.replace(w.meta["storm"], rm=400e3)
+    out = []
+    for cells in (0, 1):
+        s = F.Solver(fm, w.dt, M=w.M)
+        s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+        s.set_drag(w.cd)
+        s.set_state(w.h0, w.u0)
+        s.set_cyclone(w.mesh.x_edge, w.mesh.normal_edge, **storm.cyclone_kwargs())
+        s.set_option(F.OPT_EDGE_CELLS, cells)
+        s.step(5)
+        out.append(s.get_state())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
