@@ -345,6 +345,18 @@ int fblts_ensemble_set_member(fblts_ensemble* e, int32_t mesh, int32_t member, c
                               const double* u, const double* cd, int32_t on_device);
 int fblts_ensemble_get_member(fblts_ensemble* e, int32_t mesh, int32_t member, double* h,
                               double* u, int32_t on_device);
+/* Per-member cyclone forcing (see fblts_set_cyclone): member `member` of mesh
+ * `mesh` gets storm c, or calm air (zero wind, the wind-stress term then acts
+ * on the water's own motion) when c is NULL.  The first call gives every
+ * member of every mesh the atmosphere (calm air until given a storm) and
+ * starts one step clock per mesh: every storm's wind at the k-th coarse step
+ * after that first call is evaluated at t = t0 + k dt (stagger storms with
+ * t0).  x_edge[3*n_edges] / n_edge[3*n_edges] (host, caller order of that
+ * mesh) are required the first time a storm is given on a mesh and may be
+ * NULL afterwards.  Drops any captured graph.  Errors: FBLTS_EINVAL (linear
+ * physics, bad index or parameters, missing positions). */
+int fblts_ensemble_set_cyclone(fblts_ensemble* e, int32_t mesh, int32_t member, const fblts_cyclone* c,
+                               const double* x_edge, const double* n_edge);
 int fblts_ensemble_step(fblts_ensemble* e, int32_t n_coarse_steps);
 int fblts_ensemble_set_graph(fblts_ensemble* e, int32_t enable);
 /* Tuning option of the ensemble's passes (see fblts_set_option). */

@@ -86,6 +86,7 @@ _SIGS = {
     "fblts_set_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_set_cyclone": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fblts_get_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fblts_ensemble_set_cyclone": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fblts_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
@@ -222,6 +223,27 @@ def _stream_handle(stream):
     return C.c_void_p(int(stream))
 
 
+def _cyclone(center, axis, v_trans=5.0, dp=6000.0, rm=40e3, b=1.5, rho_air=1.15, radius=6.371229e6,
+             omega=7.292e-5, t0=0.0):
+    c = fblts_cyclone()
+    for k in range(3):
+        c.center[k] = float(center[k])
+        c.axis[k] = float(axis[k])
+    c.v_trans, c.dp, c.rm, c.b, c.rho_air = v_trans, dp, rm, b, rho_air
+    c.radius, c.omega, c.t0 = radius, omega, t0
+    return c
+
+
+def _edge_vectors(mesh, x_edge, n_edge):
+    if x_edge is None:
+        return None, None, None
+    x = np.ascontiguousarray(x_edge, dtype=np.float64).reshape(-1)
+    n = np.ascontiguousarray(n_edge, dtype=np.float64).reshape(-1)
+    if x.size != 3 * mesh.n_edges or n.size != 3 * mesh.n_edges:
+        raise ValueError("x_edge and n_edge must hold 3 values per edge")
+    return x, n, (x.ctypes.data, n.ctypes.data)
+
+
 class Solver:
     """fblts_solver: one mesh, one member, one scheme."""
 
@@ -262,20 +284,11 @@ class Solver:
         pt, dt, kt = _ptr(wt, np.float64)
         _check(lib().fblts_set_wind(self.handle, pn, pt, dn))
 
-    def set_cyclone(self, x_edge, n_edge, center, axis, v_trans=5.0, dp=6000.0, rm=40e3, b=1.5,
-                    rho_air=1.15, radius=6.371229e6, omega=7.292e-5, t0=0.0):
+    def set_cyclone(self, x_edge, n_edge, **storm):
         """Moving Holland cyclone as the wind-stress forcing (device-evaluated per coarse step)."""
-        c = fblts_cyclone()
-        for k in range(3):
-            c.center[k] = float(center[k])
-            c.axis[k] = float(axis[k])
-        c.v_trans, c.dp, c.rm, c.b, c.rho_air = v_trans, dp, rm, b, rho_air
-        c.radius, c.omega, c.t0 = radius, omega, t0
-        x = np.ascontiguousarray(x_edge, dtype=np.float64).reshape(-1)
-        n = np.ascontiguousarray(n_edge, dtype=np.float64).reshape(-1)
-        if x.size != 3 * self.mesh.n_edges or n.size != 3 * self.mesh.n_edges:
-            raise ValueError("x_edge and n_edge must hold 3 values per edge")
-        _check(lib().fblts_set_cyclone(self.handle, C.byref(c), x.ctypes.data, n.ctypes.data))
+        c = _cyclone(**storm)
+        x, n, (px, pn) = _edge_vectors(self.mesh, x_edge, n_edge)
+        _check(lib().fblts_set_cyclone(self.handle, C.byref(c), px, pn))
 
     def clear_wind(self):
         _check(lib().fblts_set_cyclone(self.handle, None, None, None))
@@ -401,6 +414,14 @@ class Ensemble:
         _check(lib().fblts_ensemble_get_member(self.handle, int(mesh), int(member), h.ctypes.data_as(C.c_void_p),
                                                u.ctypes.data_as(C.c_void_p), 0))
         return h, u
+
+    def set_cyclone(self, mesh, member, x_edge=None, n_edge=None, storm=None):
+        """Member `member` of mesh `mesh` gets the Holland storm `storm` (a dict of
+        fblts_cyclone fields), or calm air when storm is None."""
+        c = C.byref(_cyclone(**storm)) if storm is not None else None
+        x, n, ptrs = _edge_vectors(self.meshes[mesh], x_edge, n_edge)
+        px, pn = ptrs if ptrs else (None, None)
+        _check(lib().fblts_ensemble_set_cyclone(self.handle, int(mesh), int(member), c, px, pn))
 
     def step(self, n=1):
         _check(lib().fblts_ensemble_step(self.handle, int(n)))

@@ -114,7 +114,7 @@ struct EdgeSeg {
   double* Udst;
   double* acc;
   const double* cd;        // per cell and member, or nullptr
-  const double* wind_n;    // per edge, or nullptr
+  const double* wind_n;    // per edge and member, or nullptr
   const double* wind_t;
   const double* slow;      // fast pass: frozen slow tendency per edge and member, or nullptr
   double c_dt, acc_w, rho_ratio;
@@ -144,17 +144,24 @@ struct AsmSeg {
   double delta;
 };
 
-// Cyclone wind at edges for the wind-stress term: Holland vortex on a
-// great-circle track, evaluated at t = t0 + clock[0] * dt.
-struct CycloneArgs {
-  const double* x;          // [3][E] unit edge positions
-  const double* n;          // [3][E] unit edge normals
-  double* wn;               // [E] W . n_e
-  double* wt;               // [E] W . (x cross n_e)
-  const long long* clock;   // coarse steps since the storm was set
-  int E;
+// Cyclone wind at edges for the wind-stress term: per member a Holland
+// vortex on a great-circle track, evaluated at t = t0 + clock[0] * dt, or calm
+// air (zero wind) for a member without a storm.
+struct CycloneParams {
   double c0[3], axis[3];
-  double v_trans, dp, rm, b, rho_air, radius, omega, t0, dt, omega_track;
+  double v_trans, dp, rm, b, rho_air, radius, omega, t0, omega_track;
+  int enabled;              // 0: calm air
+  int pad;
+};
+struct CycloneArgs {
+  const double* x;          // [3][E] unit edge positions (may be null when no member has a storm)
+  const double* n;          // [3][E] unit edge normals
+  double* wn;               // [E*nm] W . n_e, members innermost
+  double* wt;               // [E*nm] W . (x cross n_e)
+  const long long* clock;   // coarse steps since the storms were set
+  const CycloneParams* p;   // [nm]
+  int E, nm_log2;
+  double dt;
 };
 
 template <class S>

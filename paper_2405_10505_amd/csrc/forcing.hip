@@ -4,9 +4,10 @@
 // The wind is an analytic Holland (1980) gradient-wind vortex whose centre
 // moves along a great circle of the sphere at constant speed.  It is evaluated
 // once per coarse step, before the step's first stage, at model time
-// t = t0 + k dt where k counts the coarse steps since the storm was set.  k
-// lives in device memory (advanced by a one-thread tick kernel at the end of
-// the step) so that a captured step graph replays with the storm moving.
+// t = t0 + k dt where k counts the coarse steps since the storms were set (a
+// solver: its latest storm; an ensemble: its first).  k lives in device memory
+// (advanced by a one-thread tick kernel at the end of the step) so that a
+// captured step graph replays with the storm moving.
 //
 // Per edge: great-circle distance to the centre r = R atan2(|x cross c|, x.c),
 // V(r) = sqrt((B/rho_a)(Rm/r)^B dp exp(-(Rm/r)^B) + (r f/2)^2) - r|f|/2 with
@@ -15,7 +16,10 @@
 // translation part v_trans (V / V(Rm, f_c)) along the track direction projected
 // onto the tangent plane.  Outputs W.n_e and W.t_e with t_e = x cross n_e.
 //
-// Bytes per edge: 6 doubles read (unit position, unit normal), 2 written.
+// Members are innermost (item = edge * nm + member), each member with its
+// own storm parameters, or calm air (zero wind) without a storm.
+//
+// Bytes per edge: 6 doubles read (unit position, unit normal), 2 per member written.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,7 +43,7 @@ __device__ __forceinline__ V3 scale(double s, V3 a) { return v3(s * a.x, s * a.y
 __device__ __forceinline__ double norm(V3 a) { return sqrt(dot(a, a)); }
 
 // Holland gradient-wind speed at distance r (m) and Coriolis parameter f.
-__device__ __forceinline__ double holland_speed(const CycloneArgs& a, double r, double f) {
+__device__ __forceinline__ double holland_speed(const CycloneParams& a, double r, double f) {
   r = fmax(r, 1.0);
   const double s = pow(a.rm / r, a.b);
   const double rf2 = 0.5 * r * f;
@@ -47,14 +51,21 @@ __device__ __forceinline__ double holland_speed(const CycloneArgs& a, double r, 
 }
 
 __global__ void __launch_bounds__(kBlock) k_cyclone(CycloneArgs a) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.E) return;
+  const long item = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= ((long)a.E << a.nm_log2)) return;
+  const int e = (int)(item >> a.nm_log2);
+  const CycloneParams& P = a.p[item & ((1 << a.nm_log2) - 1)];
+  if (!P.enabled) {
+    a.wn[item] = 0.0;
+    a.wt[item] = 0.0;
+    return;
+  }
   // storm centre at this step: c0 rotated about the track axis
   const double t = (double)a.clock[0] * a.dt;
-  const double ang = a.omega_track * (t + a.t0);
+  const double ang = P.omega_track * (t + P.t0);
   const double ca = cos(ang), sa = sin(ang);
-  const V3 c0 = v3(a.c0[0], a.c0[1], a.c0[2]);
-  const V3 k = v3(a.axis[0], a.axis[1], a.axis[2]);
+  const V3 c0 = v3(P.c0[0], P.c0[1], P.c0[2]);
+  const V3 k = v3(P.axis[0], P.axis[1], P.axis[2]);
   const V3 kc = cross(k, c0);
   const double kdc = dot(k, c0);
   const V3 c = v3(c0.x * ca + kc.x * sa + k.x * kdc * (1.0 - ca), c0.y * ca + kc.y * sa + k.y * kdc * (1.0 - ca),
@@ -64,11 +75,11 @@ __global__ void __launch_bounds__(kBlock) k_cyclone(CycloneArgs a) {
 
   const double cosang = dot(x, c);
   const double sinang = norm(cross(x, c));
-  const double r = a.radius * atan2(sinang, cosang);
-  const double f = 2.0 * a.omega * x.z;
-  const double fc = 2.0 * a.omega * c.z;
-  const double V = holland_speed(a, r, f);
-  const double vmax = holland_speed(a, a.rm, fc);
+  const double r = P.radius * atan2(sinang, cosang);
+  const double f = 2.0 * P.omega * x.z;
+  const double fc = 2.0 * P.omega * c.z;
+  const double V = holland_speed(P, r, f);
+  const double vmax = holland_speed(P, P.rm, fc);
 
   const V3 ct = axpy(-cosang, x, c);  // towards the centre, in the tangent plane at x
   const double nrm = norm(ct);
@@ -77,10 +88,10 @@ __global__ void __launch_bounds__(kBlock) k_cyclone(CycloneArgs a) {
   const V3 tau = cross(k, c);
   const V3 tx = axpy(-dot(x, tau), x, tau);
   const V3 th = scale(1.0 / fmax(norm(tx), 1e-300), tx);
-  const V3 W = axpy(a.v_trans * V / vmax, th, sw);
+  const V3 W = axpy(vmax > 0.0 ? P.v_trans * V / vmax : 0.0, th, sw);
 
-  a.wn[e] = dot(W, n);
-  a.wt[e] = dot(W, cross(x, n));
+  a.wn[item] = dot(W, n);
+  a.wt[item] = dot(W, cross(x, n));
 }
 
 __global__ void k_clock_tick(long long* clock) {
@@ -90,8 +101,9 @@ __global__ void k_clock_tick(long long* clock) {
 }  // namespace
 
 void launch_cyclone(const CycloneArgs& a, hipStream_t st) {
-  if (a.E <= 0) return;
-  hipLaunchKernelGGL(k_cyclone, dim3((unsigned)((a.E + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a);
+  const long items = (long)a.E << a.nm_log2;
+  if (items <= 0) return;
+  hipLaunchKernelGGL(k_cyclone, dim3((unsigned)((items + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a);
 }
 
 void launch_clock_tick(long long* clock, hipStream_t st) {

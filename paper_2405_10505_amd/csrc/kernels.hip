@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
       phi -= cde * sqrt(u * u + up * up) * u / pe.w;
     }
     if (WIND) {
-      const double wn = S.wind_n[e], wt = S.wind_t[e];
+      const double wn = S.wind_n[ee], wt = S.wind_t[ee];
       const double cw = S.rho_ratio * (0.75 + 0.067 * sqrt(wn * wn + wt * wt)) * 1e-3;
       const double rn = wn - u, rt = wt - up;
       phi += cw * sqrt(rn * rn + rt * rt) * rn / pe.w;

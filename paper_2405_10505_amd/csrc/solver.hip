@@ -207,7 +207,7 @@ struct DevState {
   bool has_wind = false;
   DevBuf slow;   // operator splitting: frozen slow momentum tendency [E*nm]
   // moving cyclone: wind evaluated on the device once per coarse step
-  DevBuf cyc_x, cyc_n, cyc_clock;
+  DevBuf cyc_x, cyc_n, cyc_clock, cyc_p;
   bool cyclone = false;
   CycloneArgs cyc{};
   void alloc(const PermMesh& pm, const Plan& p, int nm_) {
@@ -245,8 +245,8 @@ struct Pass {
   Launch<EdgeSeg> edge;
   Launch<PredSeg> pred;
   Launch<AsmSeg> asmb;
-  CycloneArgs cyc{};               // WIND
-  long long* clock = nullptr;      // TICK
+  std::vector<CycloneArgs> cycs;   // WIND (one per mesh)
+  std::vector<long long*> clocks;  // TICK (one per mesh)
   // RK4 final: per segment (y, acc, n)
   std::vector<std::tuple<double*, const double*, long>> fin;
   double fin_c = 0.0;
@@ -604,12 +604,12 @@ void add_forcing_passes(MeshUnit& u) {
   Pass w;
   w.kind = Pass::WIND;
   w.tag = -1;
-  w.cyc = u.st.cyc;
+  w.cycs = {u.st.cyc};
   w.model_bytes = (double)u.pm.E * 8.0 * 8.0;
   Pass t;
   t.kind = Pass::TICK;
   t.tag = -2;
-  t.clock = u.st.cyc_clock.as<long long>();
+  t.clocks = {u.st.cyc_clock.as<long long>()};
   u.passes.insert(u.passes.begin(), w);
   u.passes.push_back(t);
 }
@@ -647,9 +647,9 @@ std::vector<Pass> merge_passes(const std::vector<MeshUnit*>& units) {
         case Pass::RK4FIN:
           for (auto& t : q.fin) ps.fin.push_back(t);
           break;
-        case Pass::COPY:
-        case Pass::WIND:
-        case Pass::TICK: break;
+        case Pass::WIND: ps.cycs.insert(ps.cycs.end(), q.cycs.begin(), q.cycs.end()); break;
+        case Pass::TICK: ps.clocks.insert(ps.clocks.end(), q.clocks.begin(), q.clocks.end()); break;
+        case Pass::COPY: break;
       }
       ps.model_bytes += q.model_bytes;
     }
@@ -714,8 +714,12 @@ void run_passes(const std::vector<Pass>& passes, bool drag, bool wind, hipStream
         for (auto& t : ps.fin) launch_axpy_final(std::get<0>(t), std::get<1>(t), ps.fin_c, std::get<2>(t), st);
         break;
       case Pass::COPY: launch_copy(ps.cdst, ps.csrc, ps.cn, st); break;
-      case Pass::WIND: launch_cyclone(ps.cyc, st); break;
-      case Pass::TICK: launch_clock_tick(ps.clock, st); break;
+      case Pass::WIND:
+        for (const CycloneArgs& a : ps.cycs) launch_cyclone(a, st);
+        break;
+      case Pass::TICK:
+        for (long long* c : ps.clocks) launch_clock_tick(c, st);
+        break;
     }
     if (evp.first) {
       arm_launch_events(nullptr, nullptr);
@@ -1275,6 +1279,102 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
   });
 }
 
+// ---------------------------------------------------------- cyclone forcing
+
+static void unit3(const double* v, double* o, const char* what) {
+  const double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  if (!(l > 0) || !std::isfinite(l)) throw Err(FBLTS_EINVAL, std::string("cyclone: zero or non-finite ") + what);
+  for (int k = 0; k < 3; ++k) o[k] = v[k] / l;
+}
+
+// Validated device parameters of one storm (NULL: calm air).
+static CycloneParams cyclone_params(const fblts_cyclone* c) {
+  CycloneParams q{};
+  if (!c) return q;
+  const double vals[] = {c->v_trans, c->dp, c->rm, c->b, c->rho_air, c->radius, c->omega, c->t0};
+  for (double v : vals)
+    if (!std::isfinite(v)) throw Err(FBLTS_EINVAL, "cyclone parameters must be finite");
+  if (!(c->rm > 0) || !(c->b > 0) || !(c->rho_air > 0) || !(c->radius > 0) || !(c->dp >= 0))
+    throw Err(FBLTS_EINVAL, "cyclone: rm, b, rho_air, radius must be positive and dp non-negative");
+  unit3(c->center, q.c0, "centre");
+  unit3(c->axis, q.axis, "track axis");
+  q.v_trans = c->v_trans;
+  q.dp = c->dp;
+  q.rm = c->rm;
+  q.b = c->b;
+  q.rho_air = c->rho_air;
+  q.radius = c->radius;
+  q.omega = c->omega;
+  q.t0 = c->t0;
+  q.omega_track = c->v_trans / c->radius;
+  q.enabled = 1;
+  return q;
+}
+
+// Wind arrays [E*nm], per-member parameters (calm air) and a zero step clock.
+static void cyclone_install(MeshUnit& u, double dt) {
+  const int E = u.pm.E, nm = u.st.nm;
+  if (u.st.wind_n.bytes < (size_t)E * nm * 8) {
+    u.st.wind_n.alloc((size_t)E * nm * 8);
+    u.st.wind_t.alloc((size_t)E * nm * 8);
+  }
+  std::vector<CycloneParams> calm(nm);
+  u.st.cyc_p.alloc(calm.size() * sizeof(CycloneParams));
+  hip_check(hipMemcpy(u.st.cyc_p.p, calm.data(), calm.size() * sizeof(CycloneParams), hipMemcpyHostToDevice),
+            "memcpy");
+  u.st.cyc_clock.alloc(8);
+  const long long zero = 0;
+  hip_check(hipMemcpy(u.st.cyc_clock.p, &zero, 8, hipMemcpyHostToDevice), "memcpy");
+  CycloneArgs a{};
+  a.x = u.st.cyc_x.bytes ? u.st.cyc_x.as<double>() : nullptr;
+  a.n = u.st.cyc_n.bytes ? u.st.cyc_n.as<double>() : nullptr;
+  a.wn = u.st.wind_n.as<double>();
+  a.wt = u.st.wind_t.as<double>();
+  a.clock = u.st.cyc_clock.as<long long>();
+  a.p = static_cast<const CycloneParams*>(u.st.cyc_p.p);
+  a.E = E;
+  a.nm_log2 = u.st.nm_log2;
+  a.dt = dt;
+  u.st.cyc = a;
+  u.st.cyclone = true;
+  u.st.has_wind = true;
+}
+
+// Unit edge positions and normals (caller order, [E][3]) in the library's SoA layout.
+static void cyclone_positions(MeshUnit& u, const double* x_edge, const double* n_edge) {
+  if (!x_edge || !n_edge) throw Err(FBLTS_EINVAL, "edge positions and normals are required");
+  const int E = u.pm.E;
+  std::vector<double> hx((size_t)3 * E), hn((size_t)3 * E);
+  for (int i = 0; i < E; ++i) {
+    const int o = u.plan.edge_new2old[i];
+    double xu[3];
+    unit3(x_edge + 3 * (size_t)o, xu, "edge position");
+    const double* nv = n_edge + 3 * (size_t)o;
+    const double nl = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    const double nx = nv[0] * xu[0] + nv[1] * xu[1] + nv[2] * xu[2];
+    if (!(std::fabs(nl - 1.0) < 1e-6) || !(std::fabs(nx) < 1e-6))
+      throw Err(FBLTS_EINVAL, "cyclone: edge normals must be unit vectors tangent to the sphere");
+    for (int k = 0; k < 3; ++k) {
+      hx[(size_t)k * E + i] = xu[k];
+      hn[(size_t)k * E + i] = nv[k];
+    }
+  }
+  if (u.st.cyc_x.bytes != hx.size() * 8) {
+    u.st.cyc_x.alloc(hx.size() * 8);
+    u.st.cyc_n.alloc(hn.size() * 8);
+  }
+  hip_check(hipMemcpy(u.st.cyc_x.p, hx.data(), hx.size() * 8, hipMemcpyHostToDevice), "memcpy");
+  hip_check(hipMemcpy(u.st.cyc_n.p, hn.data(), hn.size() * 8, hipMemcpyHostToDevice), "memcpy");
+  u.st.cyc.x = u.st.cyc_x.as<double>();
+  u.st.cyc.n = u.st.cyc_n.as<double>();
+}
+
+static void cyclone_member(MeshUnit& u, int member, const CycloneParams& q) {
+  hip_check(hipMemcpy(static_cast<char*>(u.st.cyc_p.p) + (size_t)member * sizeof(CycloneParams), &q,
+                      sizeof(CycloneParams), hipMemcpyHostToDevice),
+            "memcpy");
+}
+
 int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_edge, const double* n_edge) {
   return guarded([&] {
     if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
@@ -1287,68 +1387,12 @@ int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_e
       u.st.has_wind = false;
     } else {
       if (!s->P.nonlinear()) throw Err(FBLTS_EINVAL, "wind stress needs nonlinear physics");
-      if (!x_edge || !n_edge) throw Err(FBLTS_EINVAL, "edge positions and normals are required");
-      const double vals[] = {c->v_trans, c->dp, c->rm, c->b, c->rho_air, c->radius, c->omega, c->t0};
-      for (double v : vals)
-        if (!std::isfinite(v)) throw Err(FBLTS_EINVAL, "cyclone parameters must be finite");
-      if (!(c->rm > 0) || !(c->b > 0) || !(c->rho_air > 0) || !(c->radius > 0) || !(c->dp >= 0))
-        throw Err(FBLTS_EINVAL, "cyclone: rm, b, rho_air, radius must be positive and dp non-negative");
-      auto unit3 = [](const double* v, double* o, const char* what) {
-        const double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        if (!(l > 0) || !std::isfinite(l)) throw Err(FBLTS_EINVAL, std::string("cyclone: zero or non-finite ") + what);
-        for (int k = 0; k < 3; ++k) o[k] = v[k] / l;
-      };
-      CycloneArgs a{};
-      unit3(c->center, a.c0, "centre");
-      unit3(c->axis, a.axis, "track axis");
-      const int E = u.pm.E;
-      std::vector<double> hx((size_t)3 * E), hn((size_t)3 * E);
-      for (int i = 0; i < E; ++i) {
-        const int o = u.plan.edge_new2old[i];
-        double xu[3];
-        unit3(x_edge + 3 * (size_t)o, xu, "edge position");
-        const double* nv = n_edge + 3 * (size_t)o;
-        const double nl = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-        const double nx = nv[0] * xu[0] + nv[1] * xu[1] + nv[2] * xu[2];
-        if (!(std::fabs(nl - 1.0) < 1e-6) || !(std::fabs(nx) < 1e-6))
-          throw Err(FBLTS_EINVAL, "cyclone: edge normals must be unit vectors tangent to the sphere");
-        for (int k = 0; k < 3; ++k) {
-          hx[(size_t)k * E + i] = xu[k];
-          hn[(size_t)k * E + i] = nv[k];
-        }
-      }
-      u.st.cyc_x.alloc(hx.size() * 8);
-      u.st.cyc_n.alloc(hn.size() * 8);
-      u.st.cyc_clock.alloc(8);
-      if (u.st.wind_n.bytes < (size_t)E * 8) {
-        u.st.wind_n.alloc((size_t)E * 8);
-        u.st.wind_t.alloc((size_t)E * 8);
-      }
-      const long long zero = 0;
-      hip_check(hipMemcpy(u.st.cyc_x.p, hx.data(), hx.size() * 8, hipMemcpyHostToDevice), "memcpy");
-      hip_check(hipMemcpy(u.st.cyc_n.p, hn.data(), hn.size() * 8, hipMemcpyHostToDevice), "memcpy");
-      hip_check(hipMemcpy(u.st.cyc_clock.p, &zero, 8, hipMemcpyHostToDevice), "memcpy");
-      a.x = u.st.cyc_x.as<double>();
-      a.n = u.st.cyc_n.as<double>();
-      a.wn = u.st.wind_n.as<double>();
-      a.wt = u.st.wind_t.as<double>();
-      a.clock = u.st.cyc_clock.as<long long>();
-      a.E = E;
-      a.v_trans = c->v_trans;
-      a.dp = c->dp;
-      a.rm = c->rm;
-      a.b = c->b;
-      a.rho_air = c->rho_air;
-      a.radius = c->radius;
-      a.omega = c->omega;
-      a.t0 = c->t0;
-      a.dt = s->P.p.dt;
-      a.omega_track = c->v_trans / c->radius;
-      u.st.cyc = a;
-      u.st.cyclone = true;
-      u.st.has_wind = true;
+      const CycloneParams q = cyclone_params(c);
+      cyclone_positions(u, x_edge, n_edge);
+      cyclone_install(u, s->P.p.dt);
+      cyclone_member(u, 0, q);
       // wind of the first step, so that the state is complete before any step
-      launch_cyclone(a, s->stream);
+      launch_cyclone(u.st.cyc, s->stream);
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     }
     build_passes(u, s->P, s->drag_on, s->opt);
@@ -1758,6 +1802,39 @@ int fblts_ensemble_get_member(fblts_ensemble* e, int32_t mesh, int32_t member, d
   });
 }
 
+int fblts_ensemble_set_cyclone(fblts_ensemble* e, int32_t mesh, int32_t member, const fblts_cyclone* c,
+                               const double* x_edge, const double* n_edge) {
+  return guarded([&] {
+    if (!e || mesh < 0 || mesh >= (int)e->units.size()) throw Err(FBLTS_EINVAL, "bad mesh index");
+    MeshUnit& U = *e->units[mesh];
+    if (member < 0 || member >= U.st.nm) throw Err(FBLTS_EINVAL, "bad member index");
+    if (!e->P.nonlinear()) throw Err(FBLTS_EINVAL, "wind stress needs nonlinear physics");
+    const CycloneParams q = cyclone_params(c);
+    hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    if (c || x_edge) cyclone_positions(U, x_edge, n_edge);
+    // first storm: every member of every mesh gets the atmosphere (calm air
+    // until given a storm), so that all meshes share one pass sequence
+    if (!e->units[0]->st.cyclone)
+      for (auto& u : e->units) cyclone_install(*u, e->P.p.dt);
+    if (q.enabled && !U.st.cyc.x) throw Err(FBLTS_EINVAL, "edge positions and normals are required");
+    cyclone_member(U, member, q);
+    std::vector<MeshUnit*> units;
+    for (auto& u : e->units) {
+      build_passes(*u, e->P, e->P.nonlinear(), e->opt);
+      units.push_back(u.get());
+    }
+    e->passes = merge_passes(units);
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->gexec = nullptr;
+    e->graph = nullptr;
+    e->graph_valid = false;
+    launch_cyclone(U.st.cyc, e->stream);
+    hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
+    return FBLTS_OK;
+  });
+}
+
 int fblts_ensemble_set_graph(fblts_ensemble* e, int32_t enable) {
   return guarded([&] {
     if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
@@ -1813,7 +1890,7 @@ int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
       if (!e->graph_valid) {
         hip_check(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         try {
-          run_passes(e->passes, nl, false, e->stream, nullptr);
+          run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr);
         } catch (...) {
           hipGraph_t g;
           (void)hipStreamEndCapture(e->stream, &g);
@@ -1826,7 +1903,7 @@ int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
       }
       for (int k = 0; k < n; ++k) hip_check(hipGraphLaunch(e->gexec, e->stream), "hipGraphLaunch");
     } else {
-      for (int k = 0; k < n; ++k) run_passes(e->passes, nl, false, e->stream, nullptr);
+      for (int k = 0; k < n; ++k) run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr);
     }
     e->step += n;
     return FBLTS_OK;

@@ -77,3 +77,44 @@ def test_member_matches_oracle(two_meshes):
         he, ue = ens.get_member(0, m)
         assert np.linalg.norm(he - ho) / np.linalg.norm(ho - om.H) <= 1e-10
         assert np.linalg.norm(ue - uo) / np.linalg.norm(uo) <= 1e-10
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_per_member_cyclones_equal_single_solver_bitwise(graph):
+    """Perturbed forcing: members of one spherical mesh carry different storms
+    (track, intensity, size, start time) or calm air; each equals the
+    single-member solver with that storm (calm air: a zero wind field)."""
+    import dataclasses
+    w = workloads.small_sphere()
+    fm = F.Mesh(w.mesh)
+    base = dataclasses.replace(w.meta["storm"], rm=400e3)
+    storms = [base.cyclone_kwargs(),
+              dict(dataclasses.replace(base, dp=9000.0, rm=300e3, v_trans=8.0).cyclone_kwargs()),
+              None,
+              dict(base.cyclone_kwargs(), t0=3 * 3600.0)]
+    nm = len(storms)
+    lab = np.where(w.fine_mask, 0, 1)
+    ens = F.Ensemble([fm], [lab], [nm], w.dt, M=w.M, linear=False)
+    cds = [2.5e-3, 1.5e-3, 3e-3, 2e-3]
+    for m in range(nm):
+        ens.set_member(0, m, w.h0, w.u0, np.full(w.mesh.n_cells, cds[m]))
+    for m, st in enumerate(storms):
+        ens.set_cyclone(0, m, w.mesh.x_edge, w.mesh.normal_edge, st)
+    ens.set_graph(graph)
+    ens.step(8)
+    for m, st in enumerate(storms):
+        s = F.Solver(fm, w.dt, M=w.M, linear=False)
+        s.set_regions(lab, binary=True)
+        s.set_drag(np.full(w.mesh.n_cells, cds[m]))
+        s.set_state(w.h0, w.u0)
+        if st is None:
+            s.set_wind(np.zeros(w.mesh.n_edges), np.zeros(w.mesh.n_edges))
+        else:
+            s.set_cyclone(w.mesh.x_edge, w.mesh.normal_edge, **st)
+        s.step(8)
+        hs, us = s.get_state()
+        he, ue = ens.get_member(0, m)
+        assert np.array_equal(hs, he) and np.array_equal(us, ue), m
+    # the storms really differ
+    a, b = ens.get_member(0, 0)[1], ens.get_member(0, 1)[1]
+    assert np.max(np.abs(a - b)) > 1e-6

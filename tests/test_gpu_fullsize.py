@@ -19,6 +19,10 @@ def c2():
     s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
     s.set_drag(w.cd)
     s.set_state(w.h0, w.u0)
+    # the launch schedule bench.py's autotuner picks on this workload (all
+    # schedules give the same bits)
+    s.set_option(F.OPT_FUSE_VERTEX, 1)
+    s.set_option(F.OPT_BLOCK, 64)
     s.set_graph(True)
     return w, s
 

@@ -50,8 +50,10 @@ def _solver(fm, w, storm=None, graph=False, scheme=F.SCHEME_FBLTS, M=None, dt=No
     return s
 
 
-def test_cyclone_wind_matches_numpy_vortex(sph):
+@pytest.mark.parametrize("t0", [0.0, 5000.0])
+def test_cyclone_wind_matches_numpy_vortex(sph, t0):
     w, om, lab, fm, storm = sph
+    storm = dataclasses.replace(storm, t0=t0)
     s = _solver(fm, w, storm)
     for k_after, k_used in ((0, 0), (4, 3), (3, 6)):
         s.step(k_after)
