@@ -374,10 +374,20 @@ def bench_ensemble(args):
         inputs.append([(w.h0 + fields[m], w.u0, np.full(w.mesh.n_cells, cds[m])) for m in range(nm)])
         for m in range(nm):
             ens.set_member(k, m, *inputs[k][m])
-    tune = autotune.autotune(ens, steps=10, repeats=2)
+    if args.schedule:
+        vals = [int(v) for v in args.schedule.split(",")]
+        tune = dict(fuse_vertex=vals[0], block=vals[1], edge_cells=vals[2] if len(vals) > 2 else 0)
+        autotune.apply(ens, tune)
+    else:
+        tune = autotune.autotune(ens, steps=10, repeats=2)
     log("ensemble schedule: fuse_vertex=%d block=%d edge_cells=%d" % (tune["fuse_vertex"], tune["block"],
                                                                      tune.get("edge_cells", 0)))
     info = ens.info()
+    if args.profile_steps:
+        ens.step(args.profile_steps)
+        torch.cuda.synchronize()
+        log("profile run done: %d ensemble steps" % args.profile_steps)
+        return
     el = time_steps(torch, ens, args.steps, args.warmup)
     members = sum(nm for _, nm in ws)
     ms = el / args.steps * 1e3

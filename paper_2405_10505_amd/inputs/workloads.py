@@ -141,7 +141,16 @@ _MESH_CACHE = {}
 def cvt_mesh(n=50000, seed=2, iters=50):
     key = (n, seed, iters)
     if key not in _MESH_CACHE:
-        _MESH_CACHE[key] = meshgen.cvt_planar_periodic(n, meshgen.gaussian_patch_dx, iters=iters, seed=seed)
+        # optional on-disk cache (directory in FBLTS_MESH_CACHE) of the generated mesh
+        cache_dir = os.environ.get("FBLTS_MESH_CACHE")
+        path = os.path.join(cache_dir, "cvt_%d_%d_%d.npz" % key) if cache_dir else None
+        if path and os.path.exists(path):
+            _MESH_CACHE[key] = meshgen.Mesh.load(path)
+        else:
+            _MESH_CACHE[key] = meshgen.cvt_planar_periodic(n, meshgen.gaussian_patch_dx, iters=iters, seed=seed)
+            if path:
+                os.makedirs(cache_dir, exist_ok=True)
+                _MESH_CACHE[key].save(path)
     return _MESH_CACHE[key]
 
 
