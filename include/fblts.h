@@ -155,7 +155,9 @@ typedef struct {
 typedef struct fblts_solver fblts_solver;
 
 /* Create a solver on the current HIP device, ordered on hip_stream (a
- * hipStream_t; NULL = default stream).  Errors: FBLTS_EINVAL, FBLTS_EDEVICE. */
+ * hipStream_t owned by the caller; NULL: the solver creates, and destroys
+ * with itself, a non-blocking stream of its own, at the default priority).
+ * Errors: FBLTS_EINVAL, FBLTS_EDEVICE. */
 int fblts_solver_create(const fblts_mesh* mesh, const fblts_params* params, void* hip_stream,
                         fblts_solver** out);
 void fblts_solver_destroy(fblts_solver* s);
@@ -331,9 +333,10 @@ int fblts_debug_vjp(fblts_solver* s, int32_t which, const double* h, const doubl
 
 /* A batch of independent FB-LTS members over one or more meshes, advanced by
  * the same kernels with the member index innermost (member-contiguous state),
- * one launch per pass covering every mesh.  members_per_mesh[k] in 1..64.
- * cell_labels[k] as in fblts_set_regions.  Errors as solver_create /
- * set_regions. */
+ * one launch per pass covering every mesh.  n_meshes in 1..4;
+ * members_per_mesh[k] a power of two in 1..64.  cell_labels[k] as in
+ * fblts_set_regions.  hip_stream as in fblts_solver_create.  Errors as
+ * solver_create / set_regions. */
 typedef struct fblts_ensemble fblts_ensemble;
 int fblts_ensemble_create(const fblts_mesh* const* meshes, const int8_t* const* cell_labels,
                           int32_t labels_are_binary, const int32_t* members_per_mesh,

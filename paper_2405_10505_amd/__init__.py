@@ -158,8 +158,11 @@ def _check(rc):
     return rc
 
 
-def _ptr(a, dtype):
-    """(pointer, on_device, keepalive) for a numpy array or a torch tensor."""
+def _ptr(a, dtype, n=None, what="array"):
+    """(pointer, on_device, keepalive) for a numpy array or a torch tensor.
+
+    n: the number of elements the library will read or write through the
+    pointer; a different size raises ValueError (the C ABI cannot check)."""
     if a is None:
         return None, 0, None
     if hasattr(a, "data_ptr"):      # torch tensor
@@ -167,9 +170,20 @@ def _ptr(a, dtype):
         want = torch.float64 if dtype == np.float64 else torch.int32
         if a.dtype != want or not a.is_contiguous():
             raise TypeError("tensor must be contiguous %s" % want)
+        if n is not None and a.numel() != n:
+            raise ValueError("%s must have %d elements, got %d" % (what, n, a.numel()))
         return C.c_void_p(a.data_ptr()), (1 if a.is_cuda else 0), a
     arr = np.ascontiguousarray(a, dtype=dtype)
+    if n is not None and arr.size != n:
+        raise ValueError("%s must have %d elements, got %d" % (what, n, arr.size))
     return arr.ctypes.data_as(C.c_void_p), 0, arr
+
+
+def _host(a, dtype, n, what):
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if arr.size != n:
+        raise ValueError("%s must have %d elements, got %d" % (what, n, arr.size))
+    return arr
 
 
 class Mesh:
@@ -188,7 +202,7 @@ class Mesh:
         self.n_cells, self.n_edges, self.n_vertices = mesh.n_cells, mesh.n_edges, mesh.n_vertices
 
     def layer_regions(self, labels, binary=True, r=2):
-        lab = np.ascontiguousarray(labels, dtype=np.int8)
+        lab = _host(labels, np.int8, self.n_cells, "labels")
         out = np.zeros(self.n_cells, np.int8)
         layer = np.zeros(self.n_cells, np.int32)
         _check(lib().fblts_layer_regions(self.handle, lab.ctypes.data_as(C.POINTER(C.c_int8)), int(binary), int(r),
@@ -255,12 +269,12 @@ class Solver:
         self.handle = h
 
     def set_regions(self, labels, binary=True):
-        lab = np.ascontiguousarray(labels, dtype=np.int8)
+        lab = _host(labels, np.int8, self.mesh.n_cells, "labels")
         _check(lib().fblts_set_regions(self.handle, lab.ctypes.data_as(C.POINTER(C.c_int8)), int(binary)))
 
     def set_state(self, h, u):
-        ph, dh, kh = _ptr(h, np.float64)
-        pu, du, ku = _ptr(u, np.float64)
+        ph, dh, kh = _ptr(h, np.float64, self.mesh.n_cells, "h")
+        pu, du, ku = _ptr(u, np.float64, self.mesh.n_edges, "u")
         if dh != du:
             raise ValueError("h and u must both be host or both be device arrays")
         _check(lib().fblts_set_state(self.handle, ph, pu, dh))
@@ -270,18 +284,22 @@ class Solver:
         if h is None and u is None:
             h = np.empty(self.mesh.n_cells)
             u = np.empty(self.mesh.n_edges)
-        ph, dh, _ = _ptr(h, np.float64)
-        pu, du, _ = _ptr(u, np.float64)
+        if h is not None and hasattr(h, "flags") and not h.flags.c_contiguous:
+            raise ValueError("h must be C-contiguous")
+        if u is not None and hasattr(u, "flags") and not u.flags.c_contiguous:
+            raise ValueError("u must be C-contiguous")
+        ph, dh, _ = _ptr(h, np.float64, self.mesh.n_cells, "h")
+        pu, du, _ = _ptr(u, np.float64, self.mesh.n_edges, "u")
         _check(lib().fblts_get_state(self.handle, ph, pu, dh if h is not None else du))
         return h, u
 
     def set_drag(self, cd):
-        p, d, k = _ptr(cd, np.float64)
+        p, d, k = _ptr(cd, np.float64, self.mesh.n_cells, "cd")
         _check(lib().fblts_set_drag(self.handle, p, d))
 
     def set_wind(self, wn, wt):
-        pn, dn, kn = _ptr(wn, np.float64)
-        pt, dt, kt = _ptr(wt, np.float64)
+        pn, dn, kn = _ptr(wn, np.float64, self.mesh.n_edges, "wind_normal")
+        pt, dt, kt = _ptr(wt, np.float64, self.mesh.n_edges, "wind_tangential")
         _check(lib().fblts_set_wind(self.handle, pn, pt, dn))
 
     def set_cyclone(self, x_edge, n_edge, **storm):
@@ -324,9 +342,10 @@ class Solver:
     def tendency(self, which, h, u):
         n = self.mesh.n_cells if which == 0 else self.mesh.n_edges
         out = np.empty(n)
-        ph, dh, kh = _ptr(h, np.float64)
-        pu, du, ku = _ptr(u, np.float64)
-        po, do, ko = _ptr(out, np.float64)
+        ph, dh, kh = _ptr(h, np.float64, self.mesh.n_cells, "h")
+        pu, du, ku = _ptr(u, np.float64, self.mesh.n_edges, "u")
+        if dh or du:
+            raise ValueError("tendency takes host arrays")
         _check(lib().fblts_debug_tendency(self.handle, int(which), ph, pu, out.ctypes.data_as(C.c_void_p), 0))
         return out
 
@@ -335,7 +354,8 @@ class Solver:
         hb = np.empty(self.mesh.n_cells)
         ub = np.empty(self.mesh.n_edges)
         cb = np.empty(self.mesh.n_cells)
-        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (h, u, cot)]
+        a = [_host(h, np.float64, self.mesh.n_cells, "h"), _host(u, np.float64, self.mesh.n_edges, "u"),
+             _host(cot, np.float64, self.mesh.n_cells if which == 0 else self.mesh.n_edges, "cotangent")]
         _check(lib().fblts_debug_vjp(self.handle, int(which), *[x.ctypes.data_as(C.c_void_p) for x in a],
                                      hb.ctypes.data_as(C.c_void_p), ub.ctypes.data_as(C.c_void_p),
                                      cb.ctypes.data_as(C.c_void_p)))
@@ -348,8 +368,10 @@ class Solver:
         """Gradients (gh0, gu0, gcd) from the final-state cotangent.
 
         Host (numpy) seeds give numpy results; CUDA tensors give tensors."""
-        ph, dh, kh = _ptr(gh_final, np.float64)
-        pu, du, ku = _ptr(gu_final, np.float64)
+        ph, dh, kh = _ptr(gh_final, np.float64, self.mesh.n_cells, "gh_final")
+        pu, du, ku = _ptr(gu_final, np.float64, self.mesh.n_edges, "gu_final")
+        if dh != du:
+            raise ValueError("gh_final and gu_final must both be host or both be device arrays")
         if dh:
             import torch
             gh0 = torch.empty(self.mesh.n_cells, dtype=torch.float64, device=gh_final.device)
@@ -394,7 +416,9 @@ class Ensemble:
         self.params = make_params(dt, M, scheme, linear, **kw)
         n = len(self.meshes)
         mh = (C.c_void_p * n)(*[m.handle.value for m in self.meshes])
-        self._labs = [np.ascontiguousarray(l, dtype=np.int8) for l in labels]
+        if len(labels) != n or len(self.members) != n:
+            raise ValueError("one label array and one member count per mesh")
+        self._labs = [_host(l, np.int8, m.n_cells, "labels") for l, m in zip(labels, self.meshes)]
         lp = (C.POINTER(C.c_int8) * n)(*[l.ctypes.data_as(C.POINTER(C.c_int8)) for l in self._labs])
         mem = np.ascontiguousarray(self.members, dtype=np.int32)
         h = C.c_void_p()
@@ -403,9 +427,12 @@ class Ensemble:
         self.handle = h
 
     def set_member(self, mesh, member, h, u, cd=None):
-        ph, dh, kh = _ptr(h, np.float64)
-        pu, du, ku = _ptr(u, np.float64)
-        pc, dc, kc = _ptr(cd, np.float64)
+        m = self.meshes[mesh]
+        ph, dh, kh = _ptr(h, np.float64, m.n_cells, "h")
+        pu, du, ku = _ptr(u, np.float64, m.n_edges, "u")
+        pc, dc, kc = _ptr(cd, np.float64, m.n_cells, "cd")
+        if dh != du or (cd is not None and dc != dh):
+            raise ValueError("h, u and cd must all be host or all be device arrays")
         _check(lib().fblts_ensemble_set_member(self.handle, int(mesh), int(member), ph, pu, pc, dh))
 
     def get_member(self, mesh, member):

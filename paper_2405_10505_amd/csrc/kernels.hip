@@ -573,7 +573,7 @@ static long asm_items(const AsmSeg& s) {
 // Kernel timing: when a pair of events is armed, the next stencil-pass launch
 // records them from its own dispatch (start and end timestamps of the kernel,
 // no marker packets in between), then the pair is disarmed.
-static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+static thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
 void arm_launch_events(hipEvent_t start, hipEvent_t stop) {
   g_ev_start = start;

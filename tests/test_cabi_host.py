@@ -81,3 +81,19 @@ def test_layering_matches_oracle_and_rejects_bad_labels():
     assert exc.value.code == F.FBLTS_EREGION
     with pytest.raises(F.FBLTSError):
         fm.layer_regions(np.full(w.mesh.n_cells, 7, np.int8), binary=False)
+
+
+def test_binding_rejects_wrong_array_sizes():
+    """The C ABI takes plain pointers; the binding checks every array's length
+    before the library reads or writes through it (no GPU needed to reach the
+    checks: they fail before any library call)."""
+    import paper_2405_10505_amd as F
+    from paper_2405_10505_amd.inputs import meshgen
+    m = meshgen.hex_periodic(8, 8, 1.0e4)
+    fm = F.Mesh(m)
+    with pytest.raises(ValueError):
+        fm.layer_regions(np.zeros(m.n_cells + 1, np.int8))
+    with pytest.raises(ValueError):
+        F._ptr(np.zeros(5), np.float64, 4, "h")
+    with pytest.raises(ValueError):
+        F._host(np.zeros(3), np.int8, 4, "labels")
