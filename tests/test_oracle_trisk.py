@@ -4,7 +4,11 @@ None of these re-derive the oracle's formulas: they check consequences fixed
 by the mathematics -- telescoping of fluxes (Theorem 1's mechanism), the
 divergence theorem, exact values on the regular hexagonal mesh, curl(grad)=0,
 conservation of the discrete energy by the semi-discrete system, and the
-constant-PV compatibility of the vorticity flux (eq. trisk_vorticity).
+constant-PV compatibility of the vorticity flux (eq. trisk_vorticity), the
+energy neutrality of the Coriolis term, the energy skew-symmetry of the linear
+operator, and the discrete inertia-gravity frequency of the regular hexagonal
+mesh from its Bloch matrix (checked against an independent value) with its
+steady geostrophic modes.
 """
 import math
 
@@ -179,3 +183,91 @@ def test_drag_removes_energy(cvt):
     eps = 1e-30
     dE = _energy(om, u + 1j * eps * Fd, h + 1j * eps * P, 9.81).imag / eps
     assert dE < 0
+
+
+def test_linear_energy_is_conserved_by_the_linear_operator(cvt):
+    """Linear TRiSK conserves E = sum_i A_i g eta_i^2 / 2 + sum_e l_e d_e H_e u_e^2 / 2:
+    g sum A eta Psi + sum l d H_e u Phi = 0 for any state (the divergence is the
+    negative adjoint of the gradient and the PV flux is energy-neutral)."""
+    om = trisk.OMesh(cvt)
+    ph = trisk.Physics(linear=True)
+    r = np.random.default_rng(11)
+    u = r.normal(size=om.E)
+    eta = r.normal(size=om.N)
+    psi = trisk.psi(om, u, om.H + eta, ph)
+    phi = trisk.phi(om, u, om.H + eta, ph)
+    a = ph.g * np.sum(om.A * eta * psi)
+    b = np.sum(om.dv * om.dc * om.He * u * phi)
+    assert abs(a + b) <= 1e-13 * (np.sum(np.abs(ph.g * om.A * eta * psi)) + np.sum(np.abs(om.dv * om.dc * om.He * u * phi)))
+
+
+def test_coriolis_term_is_energy_neutral(cvt):
+    """sum_e l_e d_e u_e u_perp_e = 0: the tangential reconstruction through the
+    antisymmetric weights does no work."""
+    om = trisk.OMesh(cvt)
+    u = np.random.default_rng(12).normal(size=om.E)
+    up = trisk.perp(om, u)
+    s = np.sum(om.dv * om.dc * u * up)
+    assert abs(s) <= 1e-13 * np.sum(np.abs(om.dv * om.dc * u * up))
+
+
+def _bloch(m, om, kvec, ph):
+    """4x4 Bloch matrix of the linear operator on the regular hexagonal mesh for
+    wavenumber kvec: one cell mode and three edge-orientation modes, each with
+    phase exp(i k.x); the operator is applied to complex states."""
+    ph_c = np.exp(1j * (m.x_cell @ kvec))
+    ph_e = np.exp(1j * (m.x_edge @ kvec))
+    ang = np.mod(np.arctan2(m.normal_edge[:, 1], m.normal_edge[:, 0]), np.pi)
+    cls = np.round(ang / (np.pi / 3)).astype(int) % 3
+    ref = np.stack([np.cos(np.arange(3) * np.pi / 3), np.sin(np.arange(3) * np.pi / 3)], 1)
+    sgn = np.sign(np.einsum("ij,ij->i", m.normal_edge, ref[cls]))
+    basis = [(ph_c, np.zeros(om.E, complex))] + [
+        (np.zeros(om.N, complex), np.where(cls == c, sgn * ph_e, 0)) for c in range(3)]
+    e0 = [int(np.nonzero(cls == c)[0][0]) for c in range(3)]
+    Lk = np.zeros((4, 4), complex)
+    out = [(trisk.psi(om, u, om.H + eta, ph), trisk.phi(om, u, om.H + eta, ph)) for eta, u in basis]
+    scale = max(max(np.max(np.abs(dh)), np.max(np.abs(du))) for dh, du in out)
+    for b, (dh, du) in enumerate(out):
+        Lk[0, b] = dh[0] / ph_c[0]
+        for c in range(3):
+            Lk[1 + c, b] = du[e0[c]] / (sgn[e0[c]] * ph_e[e0[c]])
+        # the result is the Bloch combination everywhere (translation invariance)
+        rh = Lk[0, b] * ph_c
+        ru = sum(Lk[1 + c, b] * basis[1 + c][1] for c in range(3))
+        assert np.max(np.abs(dh - rh)) <= 1e-12 * scale
+        assert np.max(np.abs(du - ru)) <= 1e-12 * scale
+    return Lk, basis
+
+
+def test_discrete_inertia_gravity_frequency_and_geostrophic_modes():
+    """Configuration 1's mesh and wavenumber (2, 1): the Bloch eigenvalues of the
+    linear TRiSK operator are {0, 0, +-i omega_d} with omega_d = 4.46348e-3 1/s
+    (the survey's independent computation; the continuous f-plane value is
+    4.49233e-3), and the two zero-frequency (geostrophically balanced) modes are
+    steady states of FB-RK(3,2)."""
+    from oracle import schemes
+    w = workloads.config1()
+    m = w.mesh
+    om = trisk.OMesh(m)
+    ph = trisk.Physics(linear=True)
+    kvec = np.array([2 * math.pi * 2 / m.lx, 2 * math.pi * 1 / m.ly])
+    Lk, basis = _bloch(m, om, kvec, ph)
+    lam = np.linalg.eigvals(Lk)
+    lam = lam[np.argsort(np.abs(lam))]
+    omega_c = math.sqrt(1e-4 ** 2 + 9.81 * 1000.0 * float(kvec @ kvec))
+    assert abs(omega_c - 4.49233e-3) <= 5e-9
+    assert np.max(np.abs(lam[:2])) <= 1e-12 * omega_c
+    assert np.max(np.abs(lam[2:].real)) <= 1e-12 * omega_c
+    assert abs(np.abs(lam[2].imag) - 4.46348e-3) <= 5e-9 and abs(lam[2] + lam[3]) <= 1e-12 * omega_c
+    # a real zero mode: Re of the null vector's Bloch combination
+    vals, vecs = np.linalg.eig(Lk)
+    v = vecs[:, int(np.argmin(np.abs(vals)))]
+    eta = np.real(v[0] * basis[0][0])
+    u = np.real(sum(v[1 + c] * basis[1 + c][1] for c in range(3)))
+    scale = 0.1 / max(np.max(np.abs(eta)), np.max(np.abs(u)))
+    eta, u = eta * scale, u * scale
+    uu, hh = u.copy(), om.H + eta
+    for _ in range(10):
+        uu, hh = schemes.fbrk32_step(om, uu, hh, 60.0, ph)
+    assert np.max(np.abs(uu - u)) <= 1e-12 * np.max(np.abs(u)) + 1e-15
+    assert np.max(np.abs(hh - om.H - eta)) <= 1e-9 * max(np.max(np.abs(eta)), 1e-3)
