@@ -118,3 +118,31 @@ def test_per_member_cyclones_equal_single_solver_bitwise(graph):
     # the storms really differ
     a, b = ens.get_member(0, 0)[1], ens.get_member(0, 1)[1]
     assert np.max(np.abs(a - b)) > 1e-6
+
+
+@pytest.mark.parametrize("kw", [dict(split=1), dict(split=2), dict(physics=F.PHYS_GRAVITY_WAVE)])
+def test_split_and_gravity_wave_members_equal_single_solver_bitwise(two_meshes, kw):
+    ws = two_meshes
+    dt = min(w.dt for w in ws)
+    nms = [2, 4]
+    fms = [F.Mesh(w.mesh) for w in ws]
+    labels = [np.where(w.fine_mask, 0, 1) for w in ws]
+    ens = F.Ensemble(fms, labels, nms, dt, M=4, **kw)
+    inputs = [_members(w, nm, k) for k, (w, nm) in enumerate(zip(ws, nms))]
+    gw = kw.get("physics") == F.PHYS_GRAVITY_WAVE
+    for k, mem in enumerate(inputs):
+        for m, (h, u, cd) in enumerate(mem):
+            ens.set_member(k, m, h, u, None if gw else cd)
+    ens.set_graph(True)
+    ens.step(5)
+    for k, (w, mem) in enumerate(zip(ws, inputs)):
+        for m, (h, u, cd) in enumerate(mem):
+            s = F.Solver(fms[k], dt, M=4, **kw)
+            s.set_regions(labels[k], binary=True)
+            if not gw:
+                s.set_drag(cd)
+            s.set_state(h, u)
+            s.step(5)
+            hs, us = s.get_state()
+            he, ue = ens.get_member(k, m)
+            assert np.array_equal(hs, he) and np.array_equal(us, ue), (k, m)
