@@ -221,8 +221,9 @@ int fblts_get_wind(fblts_solver* s, double* wind_normal, double* wind_tangential
 
 /* Advance n coarse steps (async).  Errors: FBLTS_ESTATE before set_state. */
 int fblts_step(fblts_solver* s, int32_t n_coarse_steps);
-/* Capture one coarse step in a hipGraph and replay it in fblts_step (1), or
- * launch kernels directly (0).  The graph is rebuilt after set_regions. */
+/* Capture the step program in hipGraphs and replay them in fblts_step (1), or
+ * launch kernels directly (0); see FBLTS_OPT_GRAPH_STEPS.  The graphs are
+ * rebuilt after any call that changes the step program. */
 int fblts_set_graph(fblts_solver* s, int32_t enable);
 
 /* Tuning options (same results bit for bit, different launch structure);
@@ -241,9 +242,12 @@ int fblts_set_graph(fblts_solver* s, int32_t enable);
  *     cell's edges counter-clockwise after e, the first cell's first); bit for
  *     bit identical when the stored weights equal the walk's FP64 arithmetic
  *     exactly, else within 1e-13 of them.  Default 0.
+ *   FBLTS_OPT_GRAPH_STEPS: coarse steps captured per hipGraph (1..64, default
+ *     8); fblts_step(n) replays the multi-step graph n / G times and a one-step
+ *     graph for the remainder (each graph launch costs a fixed boundary).
  * Errors: FBLTS_EINVAL for an unknown option or value, or EDGE_CELLS on a
  * mesh whose weights are not the kite-fraction walks. */
-enum { FBLTS_OPT_FUSE_VERTEX = 1, FBLTS_OPT_BLOCK = 2, FBLTS_OPT_EDGE_CELLS = 3 };
+enum { FBLTS_OPT_FUSE_VERTEX = 1, FBLTS_OPT_BLOCK = 2, FBLTS_OPT_EDGE_CELLS = 3, FBLTS_OPT_GRAPH_STEPS = 4 };
 int fblts_set_option(fblts_solver* s, int32_t option, int32_t value);
 
 typedef struct {

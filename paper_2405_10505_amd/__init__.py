@@ -20,7 +20,7 @@ SCHEME_FBLTS, SCHEME_FBRK32, SCHEME_RK4 = 0, 1, 2
 PHYS_LINEAR, PHYS_NONLINEAR, PHYS_GRAVITY_WAVE = 0, 1, 2
 SPLIT_NONE, SPLIT_COARSE, SPLIT_FINE = 0, 1, 2
 BETA = (0.531, 0.531, 0.313)
-OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS = 1, 2, 3
+OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS, OPT_GRAPH_STEPS = 1, 2, 3, 4
 
 _P_i32 = C.POINTER(C.c_int32)
 _P_f64 = C.POINTER(C.c_double)

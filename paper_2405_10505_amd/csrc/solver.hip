@@ -305,6 +305,7 @@ struct LaunchOpts {
   bool fuse_q = true;        // q_v evaluated inside the prep pass
   int block = kBlock;        // threads per block of the stencil passes
   bool edge_cells = false;   // momentum pass through the cells' edge lists
+  int graph_steps = 8;       // coarse steps per replayed hipGraph
 };
 
 void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, const Plan* plan = nullptr,
@@ -959,6 +960,56 @@ struct Rev {
 
 // ------------------------------------------------------------------ objects
 
+// The step program captured as hipGraphs: one coarse step, and `G` coarse
+// steps back to back (each graph launch has a fixed cost at its boundary, so
+// longer runs replay the G-step graph and finish with single steps).
+struct StepGraphs {
+  hipGraph_t g1 = nullptr, gG = nullptr;
+  hipGraphExec_t x1 = nullptr, xG = nullptr;
+  int G = 0;
+  StepGraphs() = default;
+  StepGraphs(const StepGraphs&) = delete;
+  StepGraphs& operator=(const StepGraphs&) = delete;
+  ~StepGraphs() { reset(); }
+  void reset() {
+    if (x1) (void)hipGraphExecDestroy(x1);
+    if (g1) (void)hipGraphDestroy(g1);
+    if (xG) (void)hipGraphExecDestroy(xG);
+    if (gG) (void)hipGraphDestroy(gG);
+    x1 = xG = nullptr;
+    g1 = gG = nullptr;
+    G = 0;
+  }
+  template <class F>
+  static void capture(hipStream_t st, int steps, F&& run_one, hipGraph_t& g, hipGraphExec_t& x) {
+    hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      for (int k = 0; k < steps; ++k) run_one();
+    } catch (...) {
+      hipGraph_t bad = nullptr;
+      (void)hipStreamEndCapture(st, &bad);
+      if (bad) (void)hipGraphDestroy(bad);
+      throw;
+    }
+    hip_check(hipStreamEndCapture(st, &g), "hipStreamEndCapture");
+    hip_check(hipGraphInstantiate(&x, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  }
+  // replay n coarse steps, capturing first when needed
+  template <class F>
+  void run(hipStream_t st, int n, int steps_per_graph, F&& run_one) {
+    if (!x1 || G != steps_per_graph) {
+      reset();
+      capture(st, 1, run_one, g1, x1);
+      if (steps_per_graph > 1) capture(st, steps_per_graph, run_one, gG, xG);
+      G = steps_per_graph;
+    }
+    int k = 0;
+    if (G > 1)
+      for (; k + G <= n; k += G) hip_check(hipGraphLaunch(xG, st), "hipGraphLaunch");
+    for (; k < n; ++k) hip_check(hipGraphLaunch(x1, st), "hipGraphLaunch");
+  }
+};
+
 struct fblts_mesh {
   HostMesh hm;
 };
@@ -972,9 +1023,8 @@ struct fblts_solver {
   std::unique_ptr<MeshUnit> unit;
   bool have_regions = false, have_state = false, drag_on = false;
   LaunchOpts opt;
-  bool graph_on = false, graph_valid = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  bool graph_on = false;
+  StepGraphs graphs;
   Timing timing;
   DevBuf diag_partial, diag_out;
   DevBuf stage_h, stage_u;   // caller-order staging
@@ -986,13 +1036,7 @@ struct fblts_solver {
     drop_graph();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
-  void drop_graph() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    gexec = nullptr;
-    graph = nullptr;
-    graph_valid = false;
-  }
+  void drop_graph() { graphs.reset(); }
 };
 
 struct fblts_ensemble {
@@ -1002,14 +1046,12 @@ struct fblts_ensemble {
   bool own_stream = false;
   std::vector<std::unique_ptr<MeshUnit>> units;
   std::vector<Pass> passes;
-  bool graph_on = false, graph_valid = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  bool graph_on = false;
+  StepGraphs graphs;
   DevBuf diag_partial, diag_out, stage_h, stage_u;
   int64_t step = 0;
   ~fblts_ensemble() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
+    graphs.reset();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -1429,6 +1471,9 @@ int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
     } else if (option == FBLTS_OPT_BLOCK) {
       if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
       s->opt.block = value;
+    } else if (option == FBLTS_OPT_GRAPH_STEPS) {
+      if (value < 1 || value > 64) throw Err(FBLTS_EINVAL, "steps per graph must be in 1..64");
+      s->opt.graph_steps = value;
     } else if (option == FBLTS_OPT_EDGE_CELLS) {
       if (value && (!s->have_regions || s->unit->pm.kite_weights == 0))
         throw Err(FBLTS_EINVAL, "edge-via-cells needs set_regions first and kite-derived TRiSK weights");
@@ -1459,21 +1504,8 @@ int fblts_step(fblts_solver* s, int32_t n) {
     MeshUnit& u = *s->unit;
     const bool nl = s->P.nonlinear();
     if (s->graph_on && !s->timing.on) {
-      if (!s->graph_valid) {
-        hip_check(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        try {
-          run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, nullptr);
-        } catch (...) {
-          hipGraph_t g;
-          (void)hipStreamEndCapture(s->stream, &g);
-          if (g) (void)hipGraphDestroy(g);
-          throw;
-        }
-        hip_check(hipStreamEndCapture(s->stream, &s->graph), "hipStreamEndCapture");
-        hip_check(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-        s->graph_valid = true;
-      }
-      for (int k = 0; k < n; ++k) hip_check(hipGraphLaunch(s->gexec, s->stream), "hipGraphLaunch");
+      s->graphs.run(s->stream, n, s->opt.graph_steps,
+                    [&] { run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, nullptr); });
     } else {
       if (s->timing.on) s->timing.reset();
       for (int k = 0; k < n; ++k) run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, &s->timing);
@@ -1824,11 +1856,7 @@ int fblts_ensemble_set_cyclone(fblts_ensemble* e, int32_t mesh, int32_t member, 
       units.push_back(u.get());
     }
     e->passes = merge_passes(units);
-    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
-    e->gexec = nullptr;
-    e->graph = nullptr;
-    e->graph_valid = false;
+    e->graphs.reset();
     launch_cyclone(U.st.cyc, e->stream);
     hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     return FBLTS_OK;
@@ -1839,11 +1867,7 @@ int fblts_ensemble_set_graph(fblts_ensemble* e, int32_t enable) {
   return guarded([&] {
     if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
     hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
-    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
-    e->gexec = nullptr;
-    e->graph = nullptr;
-    e->graph_valid = false;
+    e->graphs.reset();
     e->graph_on = enable != 0;
     return FBLTS_OK;
   });
@@ -1858,6 +1882,9 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
     } else if (option == FBLTS_OPT_BLOCK) {
       if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
       e->opt.block = value;
+    } else if (option == FBLTS_OPT_GRAPH_STEPS) {
+      if (value < 1 || value > 64) throw Err(FBLTS_EINVAL, "steps per graph must be in 1..64");
+      e->opt.graph_steps = value;
     } else if (option == FBLTS_OPT_EDGE_CELLS) {
       for (auto& u : e->units)
         if (value && u->pm.kite_weights == 0)
@@ -1872,11 +1899,7 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
       units.push_back(u.get());
     }
     e->passes = merge_passes(units);
-    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
-    if (e->graph) (void)hipGraphDestroy(e->graph);
-    e->gexec = nullptr;
-    e->graph = nullptr;
-    e->graph_valid = false;
+    e->graphs.reset();
     return FBLTS_OK;
   });
 }
@@ -1887,21 +1910,8 @@ int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
     if (n < 0) throw Err(FBLTS_EINVAL, "negative step count");
     const bool nl = e->P.nonlinear();
     if (e->graph_on) {
-      if (!e->graph_valid) {
-        hip_check(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        try {
-          run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr);
-        } catch (...) {
-          hipGraph_t g;
-          (void)hipStreamEndCapture(e->stream, &g);
-          if (g) (void)hipGraphDestroy(g);
-          throw;
-        }
-        hip_check(hipStreamEndCapture(e->stream, &e->graph), "hipStreamEndCapture");
-        hip_check(hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-        e->graph_valid = true;
-      }
-      for (int k = 0; k < n; ++k) hip_check(hipGraphLaunch(e->gexec, e->stream), "hipGraphLaunch");
+      e->graphs.run(e->stream, n, e->opt.graph_steps,
+                    [&] { run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr); });
     } else {
       for (int k = 0; k < n; ++k) run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr);
     }

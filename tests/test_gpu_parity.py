@@ -278,3 +278,21 @@ def test_edge_cells_on_the_sphere_with_cyclone_bitwise():
         s.step(5)
         out.append(s.get_state())
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("G", [1, 3, 8])
+def test_multi_step_graphs_bitwise(cvt, G):
+    """Several coarse steps per captured graph: any mix of multi-step and single
+    step replays gives the bits of direct launches."""
+    w, om, lab, fm = cvt
+    a = _solver(fm, w)
+    b = _solver(fm, w, graph=True)
+    b.set_option(F.OPT_GRAPH_STEPS, G)
+    for n in (11, 2, 7):
+        a.step(n)
+        b.step(n)
+        ha, ua = a.get_state()
+        hb, ub = b.get_state()
+        assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+    with pytest.raises(F.FBLTSError):
+        b.set_option(F.OPT_GRAPH_STEPS, 0)

@@ -130,3 +130,17 @@ def test_cyclone_argument_errors(sph):
     with pytest.raises(F.FBLTSError) as e:
         s.get_wind()
     assert e.value.code == F.FBLTS_ESTATE
+
+
+def test_cyclone_clock_advances_inside_multi_step_graphs(sph):
+    w, om, lab, fm, storm = sph
+    a = _solver(fm, w, storm, graph=False)
+    b = _solver(fm, w, storm, graph=True)
+    b.set_option(F.OPT_GRAPH_STEPS, 4)
+    a.step(9)
+    b.step(9)
+    ha, ua = a.get_state()
+    hb, ub = b.get_state()
+    assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+    wa, wb = a.get_wind(), b.get_wind()
+    assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
