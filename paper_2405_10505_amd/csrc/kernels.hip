@@ -31,28 +31,43 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return x * q + (x < r ? x : r) + k;
 }
 
-template <class S>
+// Segment of block b.  ONE: the launch has a single segment (every solver,
+// and ensembles of one mesh), so the segment's fields sit at fixed argument
+// offsets and their scalar loads issue in the kernel's first round instead
+// of after the lookup.
+template <bool ONE, class S>
 __device__ __forceinline__ int find_seg(const Launch<S>& L, int b) {
-  int s = 0;
+  if constexpr (ONE) {
+    return 0;
+  } else {
+    int s = 0;
 #pragma unroll
-  for (int k = 1; k < kMaxSeg; ++k)
-    if (k < L.nseg && b >= L.blk_start[k]) s = k;
-  return s;
+    for (int k = 1; k < kMaxSeg; ++k)
+      if (k < L.nseg && b >= L.blk_start[k]) s = k;
+    return s;
+  }
+}
+
+// First block of segment s (segment 0 starts at block 0).
+template <bool ONE, class S>
+__device__ __forceinline__ int seg_block(const Launch<S>& L, int s) {
+  if constexpr (ONE) return 0;
+  else return L.blk_start[s];
 }
 
 // ---------------------------------------------------------------- cell pass
 // MODE 0: linear TRiSK (flux H_e u, B = g(h* - H)); 1: nonlinear (flux h_e u,
 // B = K + g(h* - H)); 2: fast terms of the operator splitting, eq. fast_terms
 // (flux h_e u, B = g(h* - H), no kinetic energy).
-template <int MODE>
+template <int MODE, bool ONE>
 __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   constexpr bool NONLINEAR = MODE != 0;   // thickness flux with h_e
   constexpr bool KE = MODE == 1;          // kinetic energy in B
   const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int s = find_seg(L, b);
+  const int s = find_seg<ONE>(L, b);
   const CellSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int i = (int)(item >> nm_log2);
   if (i >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -151,12 +166,13 @@ __device__ __forceinline__ double vertex_q(const MeshDev& m, int v, const double
   return (circ * ia + m.v_f[v]) / (hv * ia);
 }
 
+template <bool ONE>
 __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int s = find_seg(L, b);
+  const int s = find_seg<ONE>(L, b);
   const VertSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int v = (int)(item >> nm_log2);
   if (v >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -168,13 +184,13 @@ __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
 // FUSE_Q: evaluate q at the edge's two vertices here instead of reading the
 // vertex pass's output (one launch fewer per stage, each vertex evaluated by
 // its three edges).
-template <bool FUSE_Q>
+template <bool FUSE_Q, bool ONE>
 __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int s = find_seg(L, b);
+  const int s = find_seg<ONE>(L, b);
   const PrepSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -262,13 +278,13 @@ __device__ __forceinline__ void walk_cell(const MeshDev& m, const double4* __res
 // CELLS: the PV flux through the two cells' edge lists and kite fractions
 // (walk_cell) instead of the edges_on_edge list and stored weights; only for
 // meshes whose stored weights are exactly those walks (the planner checks).
-template <bool DRAG, bool WIND, bool CELLS>
+template <bool DRAG, bool WIND, bool CELLS, bool ONE>
 __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int s = find_seg(L, b);
+  const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -325,13 +341,13 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
 // Fast momentum tendency of the operator splitting (eq. fast_terms):
 // Phi = -(B_c1 - B_c0) / d_e with B = g(h* - H), plus (SLOW) the slow tendency
 // frozen at the start of the step or substep (eq. splitting).
-template <bool SLOW>
+template <bool SLOW, bool ONE>
 __global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int s = find_seg(L, b);
+  const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -349,15 +365,16 @@ __global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
 }
 
 // ---------------------------------------------------------- prediction pass
+template <bool ONE>
 __global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
   const int b = blockIdx.x;
-  const int s = find_seg(L, b);
+  const int s = find_seg<ONE>(L, b);
   const PredSeg& S = L.seg[s];
   const int nm_log2 = S.nm_log2;
   const int nm = 1 << nm_log2;
   const long nc = (long)(S.c_end - S.c_begin) * nm;
   const long ne = (long)(S.e_end - S.e_begin) * nm;
-  const long t = (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const long t = (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   if (t < nc) {
     const long i = (long)S.c_begin * nm + t;
     double hn, h1, h2, h3;
@@ -388,14 +405,15 @@ __global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
 }
 
 // ------------------------------------------------------------ assembly pass
+template <bool ONE>
 __global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
   const int b = blockIdx.x;
-  const int s = find_seg(L, b);
+  const int s = find_seg<ONE>(L, b);
   const AsmSeg& S = L.seg[s];
   const int nm = 1 << S.nm_log2;
   const long ncell = (long)(S.N - S.if1_c_begin) * nm;
   const long nedge = (long)(S.E - S.if1_e_begin) * nm;
-  const long t = (long)(b - L.blk_start[s]) * blockDim.x + threadIdx.x;
+  const long t = (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   if (t < ncell) {
     const long i = (long)S.if1_c_begin * nm + t;
     const long c = i >> S.nm_log2;
@@ -590,37 +608,45 @@ static void launch_timed(F kernel, int nb, int bs, hipStream_t st, A... args) {
   }
 }
 
+// Launch the one-segment instance of a kernel when the table has a single
+// segment, the general one otherwise.
+template <typename K1, typename KN, class S>
+static void launch_segs(K1 one, KN many, int nb, int bs, hipStream_t st, const Launch<S>& L) {
+  if (L.nseg == 1) launch_timed(one, nb, bs, st, L);
+  else launch_timed(many, nb, bs, st, L);
+}
+
 // Each launcher returns the number of blocks launched (0: nothing to do).
 int launch_cell(Launch<CellSeg> L, int mode, int bs, hipStream_t st) {
   const int nb = blocks_for(L, cell_items, bs);
   if (nb == 0) return 0;
-  if (mode == 1) launch_timed(k_cell<1>, nb, bs, st, L);
-  else if (mode == 2) launch_timed(k_cell<2>, nb, bs, st, L);
-  else launch_timed(k_cell<0>, nb, bs, st, L);
+  if (mode == 1) launch_segs(k_cell<1, true>, k_cell<1, false>, nb, bs, st, L);
+  else if (mode == 2) launch_segs(k_cell<2, true>, k_cell<2, false>, nb, bs, st, L);
+  else launch_segs(k_cell<0, true>, k_cell<0, false>, nb, bs, st, L);
   return nb;
 }
 
 int launch_vertex(Launch<VertSeg> L, int bs, hipStream_t st) {
   const int nb = blocks_for(L, vert_items, bs);
   if (nb == 0) return 0;
-  launch_timed(k_vertex, nb, bs, st, L);
+  launch_segs(k_vertex<true>, k_vertex<false>, nb, bs, st, L);
   return nb;
 }
 
 int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st) {
   const int nb = blocks_for(L, prep_items, bs);
   if (nb == 0) return 0;
-  if (fuse_q) launch_timed(k_prep<true>, nb, bs, st, L);
-  else launch_timed(k_prep<false>, nb, bs, st, L);
+  if (fuse_q) launch_segs(k_prep<true, true>, k_prep<true, false>, nb, bs, st, L);
+  else launch_segs(k_prep<false, true>, k_prep<false, false>, nb, bs, st, L);
   return nb;
 }
 
 template <bool CELLS>
 static void launch_edge_t(const Launch<EdgeSeg>& L, bool drag, bool wind, int nb, int bs, hipStream_t st) {
-  if (drag && wind) launch_timed(k_edge<true, true, CELLS>, nb, bs, st, L);
-  else if (drag) launch_timed(k_edge<true, false, CELLS>, nb, bs, st, L);
-  else if (wind) launch_timed(k_edge<false, true, CELLS>, nb, bs, st, L);
-  else launch_timed(k_edge<false, false, CELLS>, nb, bs, st, L);
+  if (drag && wind) launch_segs(k_edge<true, true, CELLS, true>, k_edge<true, true, CELLS, false>, nb, bs, st, L);
+  else if (drag) launch_segs(k_edge<true, false, CELLS, true>, k_edge<true, false, CELLS, false>, nb, bs, st, L);
+  else if (wind) launch_segs(k_edge<false, true, CELLS, true>, k_edge<false, true, CELLS, false>, nb, bs, st, L);
+  else launch_segs(k_edge<false, false, CELLS, true>, k_edge<false, false, CELLS, false>, nb, bs, st, L);
 }
 
 int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st, bool cells) {
@@ -634,22 +660,24 @@ int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st,
 int launch_edge_fast(Launch<EdgeSeg> L, bool slow, int bs, hipStream_t st) {
   const int nb = blocks_for(L, edge_items, bs);
   if (nb == 0) return 0;
-  if (slow) launch_timed(k_edge_fast<true>, nb, bs, st, L);
-  else launch_timed(k_edge_fast<false>, nb, bs, st, L);
+  if (slow) launch_segs(k_edge_fast<true, true>, k_edge_fast<true, false>, nb, bs, st, L);
+  else launch_segs(k_edge_fast<false, true>, k_edge_fast<false, false>, nb, bs, st, L);
   return nb;
 }
 
 int launch_predict(Launch<PredSeg> L, hipStream_t st) {
   const int nb = blocks_for(L, pred_items, kBlock);
   if (nb == 0) return 0;
-  hipLaunchKernelGGL(k_predict, dim3(nb), dim3(kBlock), 0, st, L);
+  if (L.nseg == 1) hipLaunchKernelGGL(k_predict<true>, dim3(nb), dim3(kBlock), 0, st, L);
+  else hipLaunchKernelGGL(k_predict<false>, dim3(nb), dim3(kBlock), 0, st, L);
   return nb;
 }
 
 int launch_assemble(Launch<AsmSeg> L, hipStream_t st) {
   const int nb = blocks_for(L, asm_items, kBlock);
   if (nb == 0) return 0;
-  hipLaunchKernelGGL(k_assemble, dim3(nb), dim3(kBlock), 0, st, L);
+  if (L.nseg == 1) hipLaunchKernelGGL(k_assemble<true>, dim3(nb), dim3(kBlock), 0, st, L);
+  else hipLaunchKernelGGL(k_assemble<false>, dim3(nb), dim3(kBlock), 0, st, L);
   return nb;
 }
 
