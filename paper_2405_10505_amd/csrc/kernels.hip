@@ -55,6 +55,20 @@ __device__ __forceinline__ int seg_block(const Launch<S>& L, int s) {
   else return L.blk_start[s];
 }
 
+// Force kernel-argument values into scalar registers at this point.  Placed
+// before a kernel's range check, it makes the segment's pointers load in the
+// same scalar round as its bounds, ahead of the first gather; left alone, the
+// compiler sinks each load next to its first use and the kernel waits for
+// several dependent rounds.  The asm is empty: it only consumes the values.
+template <typename T>
+__device__ __forceinline__ void sgpr_ready1(const T& v) {
+  asm volatile("" ::"s"(v));
+}
+template <typename... T>
+__device__ __forceinline__ void sgpr_ready(const T&... v) {
+  (sgpr_ready1(v), ...);
+}
+
 // ---------------------------------------------------------------- cell pass
 // MODE 0: linear TRiSK (flux H_e u, B = g(h* - H)); 1: nonlinear (flux h_e u,
 // B = K + g(h* - H)); 2: fast terms of the operator splitting, eq. fast_terms
@@ -66,6 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const CellSeg& S = L.seg[s];
+  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.c_edge, S.m.c_nbr, S.m.cs, S.m.c_nedge, S.Hsrc, S.Usrc, S.m.e_dv, S.m.e_dc);
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int i = (int)(item >> nm_log2);
@@ -171,6 +186,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const VertSeg& S = L.seg[s];
+  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.v_edge, S.m.v_cell, S.m.vs, S.Usrc, S.hs, S.m.e_dc, S.q);
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int v = (int)(item >> nm_log2);
@@ -189,6 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const PrepSeg& S = L.seg[s];
+  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.e_cell, S.m.e_vert, S.m.es, S.Usrc, S.m.e_dv, S.hs, S.linear, S.P);
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
@@ -283,6 +300,11 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
+  if constexpr (ONE) {
+    sgpr_ready(blockDim.x, S.P, S.B, S.m.es, S.m.e_cell, S.m.e_invdc);
+    if constexpr (CELLS) sgpr_ready(S.m.e_cs, S.m.c_edge, S.m.c_R, S.m.cs);
+    else sgpr_ready(S.m.e_eoe, S.m.e_w, S.m.e_neoe);
+  }
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
@@ -346,6 +368,7 @@ __global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
+  if constexpr (ONE) sgpr_ready(blockDim.x, S.B, S.m.es, S.m.e_cell, S.m.e_invdc, S.Udst, S.U0);
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
