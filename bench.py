@@ -234,7 +234,7 @@ def main():
     from paper_2405_10505_amd import autotune
     # the profiled run replays the schedule the timed run chose (cached by shape)
     os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+    cache = os.path.join(ROOT, "gpurun_out", "autotune_schedules.json")
     if args.schedule:
         vals = [int(v) for v in args.schedule.split(",")]
         tune = dict(fuse_vertex=vals[0], block=vals[1], edge_cells=vals[2] if len(vals) > 2 else 0,

@@ -170,7 +170,9 @@ void fblts_solver_destroy(fblts_solver* s);
 int fblts_set_regions(fblts_solver* s, const int8_t* labels, int32_t binary);
 
 /* State in caller numbering: h[n_cells] thickness (m), u[n_edges] normal
- * velocity (m/s).  on_device selects device or host pointers. */
+ * velocity (m/s).  on_device selects device or host pointers.  set_state
+ * starts a new trajectory: model time, step count and the storm clock of
+ * fblts_set_cyclone restart at zero. */
 int fblts_set_state(fblts_solver* s, const double* h, const double* u, int32_t on_device);
 int fblts_get_state(fblts_solver* s, double* h, double* u, int32_t on_device);
 /* Per-cell quadratic bottom drag coefficient C_D[n_cells] (nonlinear physics). */
@@ -189,8 +191,10 @@ int fblts_set_wind(fblts_solver* s, const double* wind_normal, const double* win
  * counter-clockwise about the centre where the centre's f > 0, plus a
  * translation part v_trans V(r)/V(rm, f_centre) along the track.  The centre
  * starts at `center` and moves about the unit `axis` at angular speed
- * v_trans/radius.  The wind of the k-th coarse step after this call is
- * evaluated on the device at t = t0 + k dt before that step's first stage and
+ * v_trans/radius.  The wind of the k-th coarse step after this call (or
+ * after the latest fblts_set_state, which starts a new trajectory at model
+ * time zero) is evaluated on the device at t = t0 + k dt before that step's
+ * first stage and
  * held for the whole step (coarse advancement and every fine substep); the
  * step counter lives on the device, so captured graphs replay correctly.
  * Components at edges: W.n_e and W.(x_e cross n_e) (the tangent convention of
@@ -372,6 +376,48 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value);
 int fblts_ensemble_diagnostics(fblts_ensemble* e, fblts_diag* out);
 int fblts_ensemble_info(fblts_ensemble* e, int64_t* member_cells, int64_t* cell_substeps_per_step,
                         double* model_bytes_per_step);
+
+/* -------------------------------------------------------- autotuning --- */
+
+/* Launch-schedule search for a solver or an ensemble.  Times every candidate
+ * schedule -- q_v fused into the prep pass or not (FBLTS_OPT_FUSE_VERTEX),
+ * blocks of 256, 128 or 64 threads (FBLTS_OPT_BLOCK), and, where every mesh
+ * allows it, the momentum pass through the cells' edge lists
+ * (FBLTS_OPT_EDGE_CELLS) -- on graph-replayed coarse steps, and leaves the
+ * fastest set.  Every candidate computes the same bits, so tuning never
+ * changes results.  Before the search the state, the model time and step
+ * count, and with a moving storm its step clock and wind, are saved; they
+ * are restored afterwards, as are the graph and timing settings.
+ *   handle, handle_kind: a solver with a state (FBLTS_HANDLE_SOLVER) or an
+ *     ensemble (FBLTS_HANDLE_ENSEMBLE);
+ *   steps (1..10000), repeats (1..100): after two warm-up steps, each
+ *     candidate runs `repeats` times `steps` coarse steps between two events
+ *     on the handle's stream; its best run counts;
+ *   cache_json_path: NULL, or a JSON file of earlier results with one
+ *     workload per line, keyed by what sets the pass program and its sizes
+ *     (mesh and region sizes, scheme, M, physics, splitting, drag, wind,
+ *     steps per graph).  A hit sets the stored schedule without timing
+ *     (from_cache = 1); a miss adds the result and rewrites the file through
+ *     a temporary file and a rename.  A missing file counts as empty;
+ *   out: the chosen schedule (may be NULL);
+ *   tried[max_tried]: the timed candidates in search order (may be NULL when
+ *     max_tried is 0); *n_tried (may be NULL) receives how many were timed,
+ *     0 on a cache hit.
+ * Synchronises the handle's stream and blocks until the search ends.  The
+ * handle must not be used from another thread meanwhile.
+ * Errors: FBLTS_EINVAL (NULL handle, unknown kind, counts out of range, a
+ * cache file in another format, an unwritable cache), FBLTS_ESTATE (solver
+ * without state), FBLTS_EDEVICE, FBLTS_ENOMEM. */
+enum { FBLTS_HANDLE_SOLVER = 0, FBLTS_HANDLE_ENSEMBLE = 1 };
+typedef struct fblts_schedule {
+  int32_t fuse_vertex;   /* FBLTS_OPT_FUSE_VERTEX value */
+  int32_t block;         /* FBLTS_OPT_BLOCK value */
+  int32_t edge_cells;    /* FBLTS_OPT_EDGE_CELLS value */
+  int32_t from_cache;    /* 1: read from the cache file, not timed */
+  double ms_per_step;    /* best time per coarse step (ms), measured or cached */
+} fblts_schedule;
+int fblts_autotune(void* handle, int32_t handle_kind, int32_t steps, int32_t repeats, const char* cache_json_path,
+                   fblts_schedule* out, fblts_schedule* tried, int32_t max_tried, int32_t* n_tried);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,7 @@ PHYS_LINEAR, PHYS_NONLINEAR, PHYS_GRAVITY_WAVE = 0, 1, 2
 SPLIT_NONE, SPLIT_COARSE, SPLIT_FINE = 0, 1, 2
 BETA = (0.531, 0.531, 0.313)
 OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS, OPT_GRAPH_STEPS = 1, 2, 3, 4
+HANDLE_SOLVER, HANDLE_ENSEMBLE = 0, 1
 
 _P_i32 = C.POINTER(C.c_int32)
 _P_f64 = C.POINTER(C.c_double)
@@ -48,6 +49,14 @@ class fblts_diag(C.Structure):
     _fields_ = [("mass", C.c_double), ("abs_vorticity", C.c_double), ("abs_vorticity_scale", C.c_double),
                 ("energy", C.c_double), ("min_h", C.c_double), ("time", C.c_double),
                 ("n_nonfinite", C.c_int64), ("step", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fblts_schedule(C.Structure):
+    _fields_ = [("fuse_vertex", C.c_int32), ("block", C.c_int32), ("edge_cells", C.c_int32),
+                ("from_cache", C.c_int32), ("ms_per_step", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -114,6 +123,8 @@ _SIGS = {
     "fblts_ensemble_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
     "fblts_ensemble_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double)]),
+    "fblts_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.POINTER(fblts_schedule),
+                                 C.POINTER(fblts_schedule), C.c_int32, _P_i32]),
 }
 
 
@@ -156,6 +167,22 @@ def _check(rc):
     if rc != FBLTS_OK:
         raise FBLTSError(rc, lib().fblts_last_error().decode())
     return rc
+
+
+# at most 2 x 2 x 3 candidate schedules (cells, fused q, block)
+_MAX_CANDIDATES = 12
+
+
+def _autotune(handle, kind, steps, repeats, cache_path):
+    out = fblts_schedule()
+    tried = (fblts_schedule * _MAX_CANDIDATES)()
+    n = C.c_int32()
+    path = os.fsencode(cache_path) if cache_path is not None else None
+    _check(lib().fblts_autotune(handle, int(kind), int(steps), int(repeats), path, C.byref(out), tried,
+                                _MAX_CANDIDATES, C.byref(n)))
+    d = out.as_dict()
+    d["candidates"] = [tried[k].as_dict() for k in range(n.value)]
+    return d
 
 
 def _ptr(a, dtype, n=None, what="array"):
@@ -400,6 +427,10 @@ class Solver:
         _check(lib().fblts_kernel_time(self.handle, int(cls), C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def autotune(self, steps=20, repeats=3, cache_path=None):
+        """fblts_autotune: set the fastest launch schedule; returns it (dict)."""
+        return _autotune(self.handle, HANDLE_SOLVER, steps, repeats, cache_path)
+
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.fblts_solver_destroy(self.handle)
@@ -464,6 +495,10 @@ class Ensemble:
         arr = (fblts_diag * tot)()
         _check(lib().fblts_ensemble_diagnostics(self.handle, arr))
         return [a.as_dict() for a in arr]
+
+    def autotune(self, steps=10, repeats=2, cache_path=None):
+        """fblts_autotune: set the fastest launch schedule; returns it (dict)."""
+        return _autotune(self.handle, HANDLE_ENSEMBLE, steps, repeats, cache_path)
 
     def info(self):
         mc, cs, mb = C.c_int64(), C.c_int64(), C.c_double()

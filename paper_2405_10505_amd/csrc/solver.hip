@@ -16,7 +16,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <tuple>
 #include <stdexcept>
@@ -1162,6 +1164,215 @@ static int fill_diag(const double* q, double time, int64_t step, fblts_diag* o) 
   return (q[6] > 0 || q[7] > 0) ? FBLTS_ENONFINITE : FBLTS_OK;
 }
 
+// ------------------------------------------------------------ step drivers
+
+static void solver_run(fblts_solver* s, int n) {
+  MeshUnit& u = *s->unit;
+  if (s->graph_on && !s->timing.on) {
+    s->graphs.run(s->stream, n, s->opt.graph_steps,
+                  [&] { run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, nullptr); });
+  } else {
+    if (s->timing.on) s->timing.reset();
+    for (int k = 0; k < n; ++k) run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, &s->timing);
+  }
+  s->step += n;
+  s->time += n * s->P.p.dt;
+}
+
+static void ensemble_run(fblts_ensemble* e, int n) {
+  const bool nl = e->P.nonlinear();
+  if (e->graph_on) {
+    e->graphs.run(e->stream, n, e->opt.graph_steps,
+                  [&] { run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr); });
+  } else {
+    for (int k = 0; k < n; ++k) run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr);
+  }
+  e->step += n;
+}
+
+// Rebuild the pass lists after a change of launch options (drops the graphs).
+static void solver_rebuild(fblts_solver* s) {
+  s->drop_graph();
+  if (s->have_regions) build_passes(*s->unit, s->P, s->drag_on, s->opt);
+}
+
+static void ensemble_rebuild(fblts_ensemble* e) {
+  std::vector<MeshUnit*> units;
+  for (auto& u : e->units) {
+    build_passes(*u, e->P, e->P.nonlinear(), e->opt);
+    units.push_back(u.get());
+  }
+  e->passes = merge_passes(units);
+  e->graphs.reset();
+}
+
+// ------------------------------------------------------------- autotuning
+// Everything a coarse step changes besides the counters, per mesh unit: the
+// state, and with a moving storm its step clock and the wind it evaluated.
+struct SnapUnit {
+  DevBuf h, u, wn, wt;
+  long long clock = 0;
+  bool cyclone = false;
+};
+
+static std::vector<std::unique_ptr<SnapUnit>> snapshot_take(const std::vector<MeshUnit*>& units, hipStream_t st) {
+  std::vector<std::unique_ptr<SnapUnit>> snap;
+  for (MeshUnit* u : units) {
+    auto q = std::make_unique<SnapUnit>();
+    const long Nc = (long)u->pm.N * u->st.nm, Ne = (long)u->pm.E * u->st.nm;
+    q->h.alloc((size_t)Nc * 8);
+    q->u.alloc((size_t)Ne * 8);
+    launch_copy(q->h.as<double>(), u->st.H[0].as<double>(), Nc, st);
+    launch_copy(q->u.as<double>(), u->st.U[0].as<double>(), Ne, st);
+    if (u->st.cyclone) {
+      q->cyclone = true;
+      q->wn.alloc((size_t)Ne * 8);
+      q->wt.alloc((size_t)Ne * 8);
+      launch_copy(q->wn.as<double>(), u->st.wind_n.as<double>(), Ne, st);
+      launch_copy(q->wt.as<double>(), u->st.wind_t.as<double>(), Ne, st);
+      hip_check(hipMemcpyAsync(&q->clock, u->st.cyc_clock.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+    }
+    snap.push_back(std::move(q));
+  }
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return snap;
+}
+
+static void snapshot_restore(const std::vector<MeshUnit*>& units, const std::vector<std::unique_ptr<SnapUnit>>& snap,
+                             hipStream_t st) {
+  for (size_t k = 0; k < units.size(); ++k) {
+    MeshUnit& u = *units[k];
+    const SnapUnit& q = *snap[k];
+    const long Nc = (long)u.pm.N * u.st.nm, Ne = (long)u.pm.E * u.st.nm;
+    launch_copy(u.st.H[0].as<double>(), q.h.as<double>(), Nc, st);
+    launch_copy(u.st.U[0].as<double>(), q.u.as<double>(), Ne, st);
+    init_scratch(u, st);
+    if (q.cyclone) {
+      launch_copy(u.st.wind_n.as<double>(), q.wn.as<double>(), Ne, st);
+      launch_copy(u.st.wind_t.as<double>(), q.wt.as<double>(), Ne, st);
+      hip_check(hipMemcpyAsync(u.st.cyc_clock.p, &q.clock, 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    }
+  }
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+struct Schedule {
+  int fuse = 1, block = kBlock, cells = 0;
+  double ms = 0.0;
+};
+using ScheduleCache = std::vector<std::pair<std::string, Schedule>>;
+
+static std::string trim(const char* c) {
+  std::string s(c);
+  const size_t a = s.find_first_not_of(" \t\r\n");
+  if (a == std::string::npos) return std::string();
+  const size_t b = s.find_last_not_of(" \t\r\n");
+  return s.substr(a, b - a + 1);
+}
+
+// The schedule cache is a JSON object with one workload per line,
+//   "<key>": {"fuse_vertex": F, "block": B, "edge_cells": C, "ms_per_step": T}
+// and is read and written only in that form.
+static ScheduleCache cache_read(const char* path) {
+  ScheduleCache v;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return v;  // no cache yet
+  char buf[1024];
+  bool ok = true;
+  while (ok && std::fgets(buf, sizeof buf, f)) {
+    std::string s = trim(buf);
+    if (s.empty() || s == "{" || s == "}") continue;
+    if (s.back() == ',') s.pop_back();
+    const size_t q = (s.size() > 1 && s[0] == '"') ? s.find('"', 1) : std::string::npos;
+    Schedule t;
+    int end = 0;
+    ok = q != std::string::npos &&
+         std::sscanf(s.c_str() + q + 1,
+                     " : {\"fuse_vertex\": %d, \"block\": %d, \"edge_cells\": %d, \"ms_per_step\": %lf }%n", &t.fuse,
+                     &t.block, &t.cells, &t.ms, &end) == 4 &&
+         end > 0 && s.c_str()[q + 1 + end] == '\0' && (t.fuse == 0 || t.fuse == 1) &&
+         (t.block == 64 || t.block == 128 || t.block == 256) && (t.cells == 0 || t.cells == 1) &&
+         std::isfinite(t.ms) && t.ms >= 0.0;
+    if (ok) v.emplace_back(s.substr(1, q - 1), t);
+  }
+  std::fclose(f);
+  if (!ok) throw Err(FBLTS_EINVAL, std::string("autotune cache ") + path + " is not a schedule cache of this library");
+  return v;
+}
+
+static void cache_write(const char* path, const ScheduleCache& v) {
+  const std::string tmp = std::string(path) + ".tmp";
+  std::FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) throw Err(FBLTS_EINVAL, "autotune cache: cannot write " + tmp);
+  std::fprintf(f, "{\n");
+  for (size_t k = 0; k < v.size(); ++k) {
+    const Schedule& t = v[k].second;
+    std::fprintf(f, "\"%s\": {\"fuse_vertex\": %d, \"block\": %d, \"edge_cells\": %d, \"ms_per_step\": %.6f}%s\n",
+                 v[k].first.c_str(), t.fuse, t.block, t.cells, t.ms, k + 1 < v.size() ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  const bool closed = std::fclose(f) == 0;
+  if (!closed || std::rename(tmp.c_str(), path) != 0) throw Err(FBLTS_EINVAL, std::string("autotune cache: cannot write ") + path);
+}
+
+// Workload keys: everything that changes the pass program or its sizes.
+static int wind_kind(const MeshUnit& u) { return u.st.cyclone ? 2 : (u.st.has_wind ? 1 : 0); }
+
+static std::string solver_key(const fblts_solver& s) {
+  const MeshUnit& u = *s.unit;
+  char b[256];
+  std::snprintf(b, sizeof b, "solver:N%d:E%d:F%d:IF%d:scheme%d:M%d:phys%d:split%d:drag%d:wind%d:G%d", u.pm.N, u.pm.E,
+                u.plan.nF, u.plan.nIF1, s.P.p.scheme, s.P.p.M, s.P.p.physics, s.P.p.split, s.drag_on ? 1 : 0,
+                wind_kind(u), s.opt.graph_steps);
+  return b;
+}
+
+static std::string ensemble_key(const fblts_ensemble& e) {
+  std::string k = "ensemble";
+  char b[160];
+  for (const auto& u : e.units) {
+    std::snprintf(b, sizeof b, ":N%dF%dm%d", u->pm.N, u->plan.nF, u->st.nm);
+    k += b;
+  }
+  std::snprintf(b, sizeof b, ":scheme%d:M%d:phys%d:split%d:wind%d:G%d", e.P.p.scheme, e.P.p.M, e.P.p.physics,
+                e.P.p.split, wind_kind(*e.units[0]), e.opt.graph_steps);
+  return k + b;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    hip_check(hipEventCreate(&a), "hipEventCreate");
+    hip_check(hipEventCreate(&b), "hipEventCreate");
+  }
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// Two warm-up steps (they capture the graphs), then `repeats` runs of `steps`
+// steps between stream events; the best run's time per step in ms.
+template <class Run>
+static double time_schedule(hipStream_t st, int steps, int repeats, Run&& run) {
+  run(2);
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  EventPair ev;
+  double best = std::numeric_limits<double>::infinity();
+  for (int r = 0; r < repeats; ++r) {
+    hip_check(hipEventRecord(ev.a, st), "hipEventRecord");
+    run(steps);
+    hip_check(hipEventRecord(ev.b, st), "hipEventRecord");
+    hip_check(hipEventSynchronize(ev.b), "hipEventSynchronize");
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+    best = std::min(best, (double)ms / steps);
+  }
+  return best;
+}
+
 // ------------------------------------------------------------------- C ABI
 
 extern "C" {
@@ -1236,8 +1447,15 @@ int fblts_set_state(fblts_solver* s, const double* h, const double* u, int32_t o
     if (!s || !h || !u) throw Err(FBLTS_EINVAL, "NULL argument");
     if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
     if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    state_in(*s->unit, s->stage_h, s->stage_u, h, u, 0, on_device != 0, s->stream);
-    init_scratch(*s->unit, s->stream);
+    MeshUnit& un = *s->unit;
+    state_in(un, s->stage_h, s->stage_u, h, u, 0, on_device != 0, s->stream);
+    init_scratch(un, s->stream);
+    if (un.st.cyclone) {
+      // a new trajectory starts at model time zero: so does the storm
+      static const long long zero = 0;
+      hip_check(hipMemcpyAsync(un.st.cyc_clock.p, &zero, 8, hipMemcpyHostToDevice, s->stream), "hipMemcpyAsync");
+      launch_cyclone(un.st.cyc, s->stream);
+    }
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->have_state = true;
     s->time = 0.0;
@@ -1481,7 +1699,7 @@ int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
-    if (s->have_regions) build_passes(*s->unit, s->P, s->drag_on, s->opt);
+    solver_rebuild(s);
     return FBLTS_OK;
   });
 }
@@ -1501,17 +1719,7 @@ int fblts_step(fblts_solver* s, int32_t n) {
     if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
     if (n < 0) throw Err(FBLTS_EINVAL, "negative step count");
     if (!s->have_state) throw Err(FBLTS_ESTATE, "set_state must come first");
-    MeshUnit& u = *s->unit;
-    const bool nl = s->P.nonlinear();
-    if (s->graph_on && !s->timing.on) {
-      s->graphs.run(s->stream, n, s->opt.graph_steps,
-                    [&] { run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, nullptr); });
-    } else {
-      if (s->timing.on) s->timing.reset();
-      for (int k = 0; k < n; ++k) run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, &s->timing);
-    }
-    s->step += n;
-    s->time += n * s->P.p.dt;
+    solver_run(s, n);
     return FBLTS_OK;
   });
 }
@@ -1893,13 +2101,7 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
-    std::vector<MeshUnit*> units;
-    for (auto& u : e->units) {
-      build_passes(*u, e->P, e->P.nonlinear(), e->opt);
-      units.push_back(u.get());
-    }
-    e->passes = merge_passes(units);
-    e->graphs.reset();
+    ensemble_rebuild(e);
     return FBLTS_OK;
   });
 }
@@ -1908,14 +2110,7 @@ int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
   return guarded([&] {
     if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
     if (n < 0) throw Err(FBLTS_EINVAL, "negative step count");
-    const bool nl = e->P.nonlinear();
-    if (e->graph_on) {
-      e->graphs.run(e->stream, n, e->opt.graph_steps,
-                    [&] { run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr); });
-    } else {
-      for (int k = 0; k < n; ++k) run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr);
-    }
-    e->step += n;
+    ensemble_run(e, n);
     return FBLTS_OK;
   });
 }
@@ -1951,6 +2146,110 @@ int fblts_ensemble_info(fblts_ensemble* e, int64_t* member_cells, int64_t* cell_
     if (member_cells) *member_cells = mc;
     if (cell_substeps) *cell_substeps = cs;
     if (model_bytes) *model_bytes = b;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_autotune(void* handle, int32_t handle_kind, int32_t steps, int32_t repeats, const char* cache_json_path,
+                   fblts_schedule* out, fblts_schedule* tried, int32_t max_tried, int32_t* n_tried) {
+  return guarded([&] {
+    if (!handle) throw Err(FBLTS_EINVAL, "handle is NULL");
+    if (steps < 1 || steps > 10000 || repeats < 1 || repeats > 100)
+      throw Err(FBLTS_EINVAL, "steps must be in 1..10000 and repeats in 1..100");
+    if (max_tried < 0 || (max_tried > 0 && !tried)) throw Err(FBLTS_EINVAL, "bad candidate output array");
+    fblts_solver* s = handle_kind == FBLTS_HANDLE_SOLVER ? static_cast<fblts_solver*>(handle) : nullptr;
+    fblts_ensemble* e = handle_kind == FBLTS_HANDLE_ENSEMBLE ? static_cast<fblts_ensemble*>(handle) : nullptr;
+    if (!s && !e) throw Err(FBLTS_EINVAL, "unknown handle kind");
+    if (s && !s->have_state) throw Err(FBLTS_ESTATE, "set_state must come first");
+    hipStream_t st = s ? s->stream : e->stream;
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    std::vector<MeshUnit*> units;
+    if (s) units.push_back(s->unit.get());
+    else
+      for (auto& u : e->units) units.push_back(u.get());
+    LaunchOpts& opt = s ? s->opt : e->opt;
+    bool& graph_on = s ? s->graph_on : e->graph_on;
+    bool cells_ok = true;
+    for (MeshUnit* u : units) cells_ok = cells_ok && u->pm.kite_weights != 0;
+    auto rebuild = [&] {
+      if (s) solver_rebuild(s);
+      else ensemble_rebuild(e);
+    };
+    auto run = [&](int n) {
+      if (s) solver_run(s, n);
+      else ensemble_run(e, n);
+    };
+    const std::string key = s ? solver_key(*s) : ensemble_key(*e);
+
+    ScheduleCache cache;
+    if (cache_json_path) cache = cache_read(cache_json_path);
+    Schedule best;
+    bool hit = false;
+    for (const auto& kv : cache)
+      if (kv.first == key && (!kv.second.cells || cells_ok)) {
+        best = kv.second;
+        hit = true;
+      }
+    int ntried = 0;
+    if (!hit) {
+      const bool graph_was = graph_on, timing_was = s && s->timing.on;
+      const double time0 = s ? s->time : 0.0;
+      const int64_t step0 = s ? s->step : e->step;
+      const auto snap = snapshot_take(units, st);
+      auto restore = [&] {
+        snapshot_restore(units, snap, st);
+        if (s) {
+          s->time = time0;
+          s->step = step0;
+          s->timing.on = timing_was;
+        } else {
+          e->step = step0;
+        }
+        graph_on = graph_was;
+      };
+      if (s) s->timing.on = false;
+      best.ms = std::numeric_limits<double>::infinity();
+      try {
+        for (int cells = 0; cells <= 1; ++cells)
+          for (int fuse = 1; fuse >= 0; --fuse)
+            for (int bs : {256, 128, 64}) {
+              if (cells && !cells_ok) continue;
+              opt.fuse_q = fuse != 0;
+              opt.block = bs;
+              opt.edge_cells = cells != 0;
+              graph_on = true;
+              rebuild();
+              const double ms = time_schedule(st, steps, repeats, run);
+              if (ntried < max_tried) tried[ntried] = fblts_schedule{fuse, bs, cells, 0, ms};
+              ++ntried;
+              if (ms < best.ms) best = Schedule{fuse, bs, cells, ms};
+            }
+      } catch (...) {
+        try {
+          hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+          restore();
+        } catch (...) {
+        }
+        throw;
+      }
+      restore();
+    }
+    opt.fuse_q = best.fuse != 0;
+    opt.block = best.block;
+    opt.edge_cells = best.cells != 0;
+    rebuild();
+    if (!hit && cache_json_path) {
+      bool replaced = false;
+      for (auto& kv : cache)
+        if (kv.first == key) {
+          kv.second = best;
+          replaced = true;
+        }
+      if (!replaced) cache.emplace_back(key, best);
+      cache_write(cache_json_path, cache);
+    }
+    if (out) *out = fblts_schedule{best.fuse, best.block, best.cells, hit ? 1 : 0, best.ms};
+    if (n_tried) *n_tried = ntried;
     return FBLTS_OK;
   });
 }

@@ -36,6 +36,13 @@ def test_version_and_error_string():
     assert e.value.code == F.FBLTS_EINVAL
 
 
+def test_autotune_argument_checks_need_no_device():
+    L = F.lib()
+    for args in ((None, F.HANDLE_SOLVER, 5, 1), (None, F.HANDLE_ENSEMBLE, 5, 1)):
+        rc = L.fblts_autotune(*args, None, None, None, 0, None)
+        assert rc == F.FBLTS_EINVAL and b"NULL" in L.fblts_last_error()
+
+
 @pytest.fixture(scope="module")
 def hexm():
     return meshgen.hex_periodic(16, 16, 1.0e4)

@@ -146,3 +146,39 @@ def test_split_and_gravity_wave_members_equal_single_solver_bitwise(two_meshes, 
             hs, us = s.get_state()
             he, ue = ens.get_member(k, m)
             assert np.array_equal(hs, he) and np.array_equal(us, ue), (k, m)
+
+
+def test_autotune_keeps_every_member_and_the_step_count(two_meshes):
+    ws = two_meshes
+    dt = min(w.dt for w in ws)
+    nms = [4, 2]
+    fms = [F.Mesh(w.mesh) for w in ws]
+    labels = [np.where(w.fine_mask, 0, 1) for w in ws]
+    inputs = [_members(w, nm, k) for k, (w, nm) in enumerate(zip(ws, nms))]
+
+    def make():
+        e = F.Ensemble(fms, labels, nms, dt, M=4, linear=False)
+        for k, mem in enumerate(inputs):
+            for m, (h, u, cd) in enumerate(mem):
+                e.set_member(k, m, h, u, cd)
+        e.set_graph(True)
+        return e
+
+    a = make()
+    a.step(2)
+    before = [[a.get_member(k, m) for m in range(nm)] for k, nm in enumerate(nms)]
+    choice = a.autotune(steps=2, repeats=1)
+    assert choice["candidates"] and choice["from_cache"] == 0
+    assert all(d["step"] == 2 for d in a.diagnostics())
+    for k, nm in enumerate(nms):
+        for m in range(nm):
+            h, u = a.get_member(k, m)
+            assert np.array_equal(h, before[k][m][0]) and np.array_equal(u, before[k][m][1])
+    a.step(3)
+    b = make()
+    b.step(5)
+    for k, nm in enumerate(nms):
+        for m in range(nm):
+            ha, ua = a.get_member(k, m)
+            hb, ub = b.get_member(k, m)
+            assert np.array_equal(ha, hb) and np.array_equal(ua, ub), (k, m)

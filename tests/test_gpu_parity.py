@@ -211,19 +211,50 @@ def test_launch_options_bitwise(name, fuse, bs, cells, request):
 
 
 def test_autotuner_restores_state_and_picks_a_candidate(cvt, tmp_path):
+    import json
     from paper_2405_10505_amd import autotune
     w, om, lab, fm = cvt
     s = _solver(fm, w)
     s.step(3)
     h0, u0 = s.get_state()
-    choice = autotune.autotune(s, steps=5, repeats=1, cache_path=str(tmp_path / "tune.json"))
+    d0 = s.diagnostics()
+    path = str(tmp_path / "tune.json")
+    choice = autotune.autotune(s, steps=5, repeats=1, cache_path=path)
     assert (choice["fuse_vertex"], choice["block"], choice["edge_cells"]) in autotune.CANDIDATES
+    assert choice["from_cache"] == 0 and choice["ms_per_step"] > 0
+    timed = [(c["fuse_vertex"], c["block"], c["edge_cells"]) for c in choice["candidates"]]
+    # every schedule without the cells variant, then (where the mesh allows it) every one with it
+    assert len(timed) in (6, 12) and timed == autotune.CANDIDATES[:len(timed)]
+    assert choice["ms_per_step"] == min(c["ms_per_step"] for c in choice["candidates"])
     h1, u1 = s.get_state()
     assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
-    # cached: a second call returns the same choice without timing
-    again = autotune.autotune(s, cache_path=str(tmp_path / "tune.json"))
+    d1 = s.diagnostics()
+    assert (d1["time"], d1["step"]) == (d0["time"], d0["step"])
+    # the cache is JSON with one entry, and a second call reads it without timing
+    entries = json.load(open(path))
+    assert len(entries) == 1 and list(entries.values())[0]["block"] == choice["block"]
+    again = autotune.autotune(s, cache_path=path)
+    assert again["from_cache"] == 1 and again["candidates"] == []
     assert (again["fuse_vertex"], again["block"], again["edge_cells"]) == (
         choice["fuse_vertex"], choice["block"], choice["edge_cells"])
+    # stepping after tuning continues the trajectory bit for bit
+    ref = _solver(fm, w)
+    ref.step(5)
+    s.step(2)
+    hr, ur = ref.get_state()
+    h2, u2 = s.get_state()
+    assert np.array_equal(hr, h2) and np.array_equal(ur, u2)
+
+
+def test_autotuner_rejects_foreign_cache_files(cvt, tmp_path):
+    w, om, lab, fm = cvt
+    s = _solver(fm, w)
+    path = tmp_path / "other.json"
+    path.write_text('{\n "solver": {\n  "block": 64\n }\n}\n')
+    with pytest.raises(F.FBLTSError) as e:
+        s.autotune(steps=1, repeats=1, cache_path=str(path))
+    assert e.value.code == F.FBLTS_EINVAL and "schedule cache" in str(e.value)
+    assert path.read_text().startswith('{\n "solver"')   # left untouched
 
 
 def test_dispatch_timing_mode_counts_launches_and_keeps_results(cvt):

@@ -144,3 +144,37 @@ def test_cyclone_clock_advances_inside_multi_step_graphs(sph):
     assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
     wa, wb = a.get_wind(), b.get_wind()
     assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
+
+
+def test_set_state_restarts_the_storm(sph):
+    w, om, lab, fm, storm = sph
+    a = _solver(fm, w, storm, graph=True)
+    a.step(4)
+    a.set_state(w.h0, w.u0)
+    a.step(3)
+    b = _solver(fm, w, storm, graph=True)
+    b.step(3)
+    ha, ua = a.get_state()
+    hb, ub = b.get_state()
+    assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+    wa, wb = a.get_wind(), b.get_wind()
+    assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
+
+
+def test_autotune_leaves_the_storm_where_it_was(sph):
+    w, om, lab, fm, storm = sph
+    a = _solver(fm, w, storm, graph=True)
+    a.step(3)
+    wind0 = a.get_wind()
+    choice = a.autotune(steps=2, repeats=1)
+    assert choice["candidates"]
+    w1 = a.get_wind()
+    assert np.array_equal(wind0[0], w1[0]) and np.array_equal(wind0[1], w1[1])
+    a.step(2)
+    b = _solver(fm, w, storm, graph=True)
+    b.step(5)
+    ha, ua = a.get_state()
+    hb, ub = b.get_state()
+    assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+    wa, wb = a.get_wind(), b.get_wind()
+    assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
