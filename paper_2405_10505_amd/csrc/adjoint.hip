@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fblts_internal.h"
+#include "prep_record.h"
 
 namespace fblts {
 
@@ -71,13 +72,12 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int drag, cons
   const double g = fb[e] * m.e_invdc[e];
   G[e] = g;
   if (!drag) return;
-  const double4* P4 = reinterpret_cast<const double4*>(P);
   const int n = m.e_neoe[e];
   double su = 0.0;
-  for (int j = 0; j < n; ++j) su = fma(m.e_w[j * m.es + e], P4[m.e_eoe[j * m.es + e]].z, su);
+  for (int j = 0; j < n; ++j) su = fma(m.e_w[j * m.es + e], rec_lu(P, m.E, m.e_eoe[j * m.es + e]), su);
   const double up = su * m.e_invdc[e];
   const double ue = u[e];
-  const double he = P4[e].w;
+  const double he = rec_he(P, m.E, e);
   const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
   const double cde = 0.5 * (cd[c0] + cd[c1]);
   const double sp = sqrt(ue * ue + up * up);
@@ -114,15 +114,14 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int linear, in
                                                        double* ub) {
   const int e = tid_global();
   if (e >= m.E) return;
-  const double4* P4 = reinterpret_cast<const double4*>(P);
-  const double4 pe = P4[e];
+  const double2 pe = rec_fq(P, e);
   const int n = m.e_neoe[e];
   double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
   for (int j = 0; j < n; ++j) {
     const int e2 = m.e_eoe[j * m.es + e];
     const double wT = m.e_wT[j * m.es + e];
     const double w = m.e_w[j * m.es + e];
-    const double4 p2 = P4[e2];
+    const double2 p2 = rec_fq(P, e2);
     const double g2 = G[e2];
     s1 = fma(wT * g2, p2.y + pe.y, s1);   // d/d(lF)_e of the neighbours' Q_perp
     s2 = fma(w, p2.x, s2);                 // d Q_perp_e / d q_e (own sum)
@@ -136,7 +135,7 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int linear, in
   double acc = ub[e];
   if (!linear) {
     QB[e] = 0.5 * (G[e] * s2 + pe.x * s3);
-    acc = fma(Fb, pe.w, acc);                                  // F = h_e u
+    acc = fma(Fb, rec_he(P, m.E, e), acc);                     // F = h_e u
     HE[e] = Fb * ue + (drag ? HD[e] : 0.0);                    // h_e's cotangent
     const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
     const double kb = BB[c0] * m.c_invA[c0] + BB[c1] * m.c_invA[c1];

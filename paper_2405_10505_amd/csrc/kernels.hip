@@ -6,7 +6,9 @@
 //   cell pass   : Psi (eq. trisk_thickness), the FB stage update of h, the
 //                 FB-averaged thickness h*, and B = K + g(h* - H);
 //   vertex pass : potential vorticity q_v = (zeta_v + f_v) / h*_v;
-//   prep pass   : per-edge (l F, q_e, l u, h_e) packed as one double4;
+//   prep pass   : per-edge (l F, q_e, l u, h_e), stored split by use (the
+//                 (l F, q_e) pair, then l u, then h_e: neighbours read 16 or
+//                 24 bytes of it, not 32);
 //   edge pass   : Phi (PV flux through the TRiSK weights, eq. trisk_vorticity,
 //                 Bernoulli gradient, quadratic drag and wind stress of
 //                 eq. hurricane_model), the FB stage update of u.
@@ -19,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fblts_internal.h"
+#include "prep_record.h"
 
 namespace fblts {
 
@@ -205,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const PrepSeg& S = L.seg[s];
-  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.e_cell, S.m.e_vert, S.m.es, S.Usrc, S.m.e_dv, S.hs, S.linear, S.P);
+  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.e_cell, S.m.e_vert, S.m.es, S.m.E, S.Usrc, S.m.e_dv, S.hs, S.linear, S.P);
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
   const int e = (int)(item >> nm_log2);
@@ -229,12 +232,10 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
       qe = 0.5 * (S.q[(long)v0 * nm + mem] + S.q[(long)v1 * nm + mem]);
     }
   }
-  double4 p;
-  p.x = dv * (he * u);
-  p.y = qe;
-  p.z = dv * u;
-  p.w = he;
-  reinterpret_cast<double4*>(S.P)[(long)e * nm + mem] = p;
+  const long k = (long)e * nm + mem, np = (long)m.E << nm_log2;
+  reinterpret_cast<double2*>(S.P)[k] = make_double2(dv * (he * u), qe);
+  S.P[2 * np + k] = dv * u;
+  S.P[3 * np + k] = he;
 }
 
 // ---------------------------------------------------------------- edge pass
@@ -244,7 +245,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
 // the same weights, in the same order, as the cell's part of e's
 // edges_on_edge list.  w = (slot << 0) | (degree << 4) of e in this cell.
 template <bool NEED_U>
-__device__ __forceinline__ void walk_cell(const MeshDev& m, const double4* __restrict__ P, int i, int w,
+__device__ __forceinline__ void walk_cell(const MeshDev& m, const double* __restrict__ P, long np, int i, int w,
                                           double pey, int nm, int mem, double& sq, double& su) {
   constexpr int U = kUnrollCell - 1;   // walk positions whose loads issue together
   const int j0 = w & 15, n = (w >> 4) & 15;
@@ -263,9 +264,14 @@ __device__ __forceinline__ void walk_cell(const MeshDev& m, const double4* __res
     R[t] = m.c_R[jp * m.cs + i];
     code[t] = m.c_edge[j * m.cs + i];
   }
-  double4 p2[U];
+  double2 p2[U];
+  double lu[U];
 #pragma unroll
-  for (int t = 0; t < U; ++t) p2[t] = P[(long)(code[t] >> 1) * nm + mem];
+  for (int t = 0; t < U; ++t) {
+    const long k = (long)(code[t] >> 1) * nm + mem;
+    p2[t] = rec_fq(P, k);
+    lu[t] = NEED_U ? rec_lu(P, np, k) : 0.0;
+  }
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < U; ++t) {
@@ -274,7 +280,7 @@ __device__ __forceinline__ void walk_cell(const MeshDev& m, const double4* __res
       double wt = 0.5 - acc;
       wt = (code[t] & 1) != se ? -wt : wt;
       sq = fma(wt * p2[t].x, pey + p2[t].y, sq);
-      if (NEED_U) su = fma(wt, p2[t].z, su);
+      if (NEED_U) su = fma(wt, lu[t], su);
     }
   }
   int j = j0 + U;
@@ -286,9 +292,10 @@ __device__ __forceinline__ void walk_cell(const MeshDev& m, const double4* __res
     const int c = m.c_edge[j * m.cs + i];
     double wt = 0.5 - acc;
     wt = (c & 1) != se ? -wt : wt;
-    const double4 q = P[(long)(c >> 1) * nm + mem];
+    const long k = (long)(c >> 1) * nm + mem;
+    const double2 q = rec_fq(P, k);
     sq = fma(wt * q.x, pey + q.y, sq);
-    if (NEED_U) su = fma(wt, q.z, su);
+    if (NEED_U) su = fma(wt, rec_lu(P, np, k), su);
   }
 }
 
@@ -301,7 +308,7 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
   if constexpr (ONE) {
-    sgpr_ready(blockDim.x, S.P, S.B, S.m.es, S.m.e_cell, S.m.e_invdc);
+    sgpr_ready(blockDim.x, S.P, S.B, S.m.es, S.m.E, S.m.e_cell, S.m.e_invdc);
     if constexpr (CELLS) sgpr_ready(S.m.e_cs, S.m.c_edge, S.m.c_R, S.m.cs);
     else sgpr_ready(S.m.e_eoe, S.m.e_w, S.m.e_neoe);
   }
@@ -312,22 +319,25 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int mem = (int)(item & ((1 << nm_log2) - 1));
   const int nm = 1 << nm_log2;
   const MeshDev& m = S.m;
-  const double4* P = reinterpret_cast<const double4*>(S.P);
+  const double* P = S.P;
+  const long np = (long)m.E << nm_log2;
   const long ee = (long)e * nm + mem;
-  const double4 pe = P[ee];
+  const double pey = rec_q(P, ee);
+  const double he = (DRAG || WIND) ? rec_he(P, np, ee) : 1.0;
   double sq = 0.0, su = 0.0;
   if (CELLS) {
     const int w = m.e_cs[e];
-    walk_cell<DRAG || WIND>(m, P, m.e_cell[e], w & 0xff, pe.y, nm, mem, sq, su);
-    walk_cell<DRAG || WIND>(m, P, m.e_cell[m.es + e], (w >> 8) & 0xff, pe.y, nm, mem, sq, su);
+    walk_cell<DRAG || WIND>(m, P, np, m.e_cell[e], w & 0xff, pey, nm, mem, sq, su);
+    walk_cell<DRAG || WIND>(m, P, np, m.e_cell[m.es + e], (w >> 8) & 0xff, pey, nm, mem, sq, su);
   } else {
     const int n = m.e_neoe[e];
     auto slot = [&](int j) {
       const int e2 = m.e_eoe[j * m.es + e];
       const double w = m.e_w[j * m.es + e];
-      const double4 p2 = P[(long)e2 * nm + mem];
-      sq = fma(w * p2.x, pe.y + p2.y, sq);
-      if (DRAG || WIND) su = fma(w, p2.z, su);
+      const long k2 = (long)e2 * nm + mem;
+      const double2 p2 = rec_fq(P, k2);
+      sq = fma(w * p2.x, pey + p2.y, sq);
+      if (DRAG || WIND) su = fma(w, rec_lu(P, np, k2), su);
     };
     // the first kUnrollEOE slots exist for every edge (padded with the edge
     // itself at weight 0, an exact no-op): their loads issue together
@@ -343,13 +353,13 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
     const double up = su * idc;
     if (DRAG) {
       const double cde = 0.5 * (S.cd[(long)c0 * nm + mem] + S.cd[(long)c1 * nm + mem]);
-      phi -= cde * sqrt(u * u + up * up) * u / pe.w;
+      phi -= cde * sqrt(u * u + up * up) * u / he;
     }
     if (WIND) {
       const double wn = S.wind_n[ee], wt = S.wind_t[ee];
       const double cw = S.rho_ratio * (0.75 + 0.067 * sqrt(wn * wn + wt * wt)) * 1e-3;
       const double rn = wn - u, rt = wt - up;
-      phi += cw * sqrt(rn * rn + rt * rt) * rn / pe.w;
+      phi += cw * sqrt(rn * rn + rt * rt) * rn / he;
     }
   }
   if (e >= S.upd_begin && e < S.upd_end) S.Udst[ee] = fma(S.c_dt, phi, S.U0[ee]);

@@ -861,11 +861,28 @@ double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int n
   return b;
 }
 
+// Prep-record components a momentum pass references, each counted once per
+// launch: the edge's own q_e (and h_e with drag or wind), each neighbour's
+// l F and q_e (and l u with drag or wind).
+struct RecordStamps {
+  Stamp F, q, lu, he;
+  explicit RecordStamps(int E) : F(E), q(E), lu(E), he(E) {
+    F.next();
+    q.next();
+    lu.next();
+    he.next();
+  }
+  double own(int e, bool need_u, double S) { return (q.mark(e) ? S : 0) + (need_u && he.mark(e) ? S : 0); }
+  double nbr(int e, bool need_u, double S) {
+    return (F.mark(e) ? S : 0) + (q.mark(e) ? S : 0) + (need_u && lu.mark(e) ? S : 0);
+  }
+};
+
 double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm) {
   const double S = 8.0 * nm;
   double b = 0;
-  Stamp sp(pm.E), sc(pm.N);
-  sp.next();
+  RecordStamps rs(pm.E);
+  Stamp sc(pm.N);
   sc.next();
   for (int e = r.edge.b; e < r.edge.e; ++e) {
     const int n = pm.e_neoe[e];
@@ -876,9 +893,8 @@ double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool
     if (acc) b += 2 * S;
     if (drag || wind) b += S;                // u of the edge
     if (wind) b += 16;
-    if (sp.mark(e)) b += 4 * S;
-    for (int j = 0; j < n; ++j)
-      if (sp.mark(pm.e_eoe[(size_t)j * pm.es + e])) b += 4 * S;
+    b += rs.own(e, drag || wind, S);
+    for (int j = 0; j < n; ++j) b += rs.nbr(pm.e_eoe[(size_t)j * pm.es + e], drag || wind, S);
     for (int j = 0; j < 2; ++j)
       if (sc.mark(pm.e_cell[(size_t)j * pm.es + e])) b += S + (drag ? S : 0);   // B (+ C_D)
   }
@@ -888,8 +904,8 @@ double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool
 double bytes_edge_cells_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm) {
   const double S = 8.0 * nm;
   double b = 0;
-  Stamp sp(pm.E), sc(pm.N);
-  sp.next();
+  RecordStamps rs(pm.E);
+  Stamp sc(pm.N);
   sc.next();
   for (int e = r.edge.b; e < r.edge.e; ++e) {
     b += 8 + 4 + 8;                          // cells, slot/degree word, 1/d_e
@@ -899,14 +915,16 @@ double bytes_edge_cells_pass(const PermMesh& pm, const StageRanges& r, bool drag
     if (acc) b += 2 * S;
     if (drag || wind) b += S;                // u of the edge
     if (wind) b += 16;
-    if (sp.mark(e)) b += 4 * S;
+    b += rs.own(e, drag || wind, S);
     for (int j = 0; j < 2; ++j) {
       const int c = pm.e_cell[(size_t)j * pm.es + e];
       if (sc.mark(c)) {
         const int n = pm.c_nedge[c];
         b += S + (drag ? S : 0) + 4 + n * (4.0 + 8.0);   // B (+ C_D), degree, edge codes, R
-        for (int k = 0; k < n; ++k)
-          if (sp.mark(pm.c_edge[(size_t)k * pm.cs + c] >> 1)) b += 4 * S;   // records of the cell's edges
+        for (int k = 0; k < n; ++k) {   // the walk reads the cell's other edges
+          const int e2 = pm.c_edge[(size_t)k * pm.cs + c] >> 1;
+          if (e2 != e) b += rs.nbr(e2, drag || wind, S);
+        }
       }
     }
   }

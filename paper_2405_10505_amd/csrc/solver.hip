@@ -827,7 +827,6 @@ struct Rev {
     const double* u = TE(0);
     const double* u1 = TE(1);
     const double* u2 = TE(2);
-    const double* u3 = TE(3);
     double** c = C;
     double** e = Ed;
     for (int k : {hb, h1b, h2b, h3b, H0b, H1b, H2b, H3b, ahb}) zero(c[k], 0, N);
@@ -2392,7 +2391,6 @@ int fblts_adjoint_forward(fblts_solver* s, int32_t n_steps, int32_t ckpt_every) 
     const int nck = (n_steps + ckpt_every - 1) / ckpt_every;
     if (A.ckpt.bytes < (size_t)nck * (N + E) * 8) A.ckpt.alloc((size_t)nck * (N + E) * 8);
     if (A.final_state.bytes < (size_t)(N + E) * 8) A.final_state.alloc((size_t)(N + E) * 8);
-    const bool nl = s->P.nonlinear();
     for (int t = 0; t < n_steps; ++t) {
       if (t % ckpt_every == 0) {
         double* c = A.ckpt.as<double>() + (size_t)(t / ckpt_every) * (N + E);
@@ -2441,7 +2439,6 @@ int fblts_adjoint_backward(fblts_solver* s, const double* gh_final, const double
     launch_permute(r.C[hNb], sh, u.dm.cell_n2o.as<int>(), N, 0, 0, 1, s->stream);
     launch_permute(r.Ed[uNb], su, u.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
     r.zero(r.C[cdb], 0, N);
-    const bool nl = s->P.nonlinear();
     const int nseg = (A.n_steps + K - 1) / K;
     const size_t per = A.tape_c + A.tape_e;
     for (int seg = nseg - 1; seg >= 0; --seg) {
