@@ -403,6 +403,7 @@ __global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
   const int b = blockIdx.x;
   const int s = find_seg<ONE>(L, b);
   const PredSeg& S = L.seg[s];
+  if constexpr (ONE) sgpr_ready(blockDim.x, S.save, S.c_begin, S.c_end, S.e_begin, S.e_end, S.a, S.invM);
   const int nm_log2 = S.nm_log2;
   const int nm = 1 << nm_log2;
   const long nc = (long)(S.c_end - S.c_begin) * nm;
@@ -443,6 +444,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
   const int b = blockIdx.x;
   const int s = find_seg<ONE>(L, b);
   const AsmSeg& S = L.seg[s];
+  if constexpr (ONE) sgpr_ready(blockDim.x, S.if1_c_begin, S.if1_c_end, S.if2_c_end, S.N, S.if1_e_begin, S.if1_e_end,
+                                S.if2_e_end, S.E);
   const int nm = 1 << S.nm_log2;
   const long ncell = (long)(S.N - S.if1_c_begin) * nm;
   const long nedge = (long)(S.E - S.if1_e_begin) * nm;
