@@ -55,6 +55,9 @@ struct MeshDev {
   // momentum pass through the cells' edge lists
   const double* c_R;       // [maxE][cs]    kite fraction R_{i,v} = kite / A_i (0 on padding)
   const int* e_cs;         // [E] slot0 | deg0 << 4 | slot1 << 8 | deg1 << 12
+  // the lists of each edge's two vertices, copied per edge (fused q_v)
+  const int* e_vq_edge;    // [6][es]  v0's three edge codes, then v1's
+  const int* e_vq_cell;    // [6][es]  v0's three cells, then v1's
 };
 
 // Thickness pass: Psi, FB stage update, FB-averaged thickness and Bernoulli
@@ -167,6 +170,7 @@ struct CycloneArgs {
 template <class S>
 struct Launch {
   int nseg;
+  int block;                 // threads per block of the launch
   int blk_start[kMaxSeg + 1];
   S seg[kMaxSeg];
 };

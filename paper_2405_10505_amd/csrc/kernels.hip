@@ -83,9 +83,9 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const CellSeg& S = L.seg[s];
-  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.c_edge, S.m.c_nbr, S.m.cs, S.m.c_nedge, S.Hsrc, S.Usrc, S.m.e_dv, S.m.e_dc);
+  if constexpr (ONE) sgpr_ready(L.block, S.m.c_edge, S.m.c_nbr, S.m.cs, S.m.c_nedge, S.Hsrc, S.Usrc, S.m.e_dv, S.m.e_dc);
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   const int i = (int)(item >> nm_log2);
   if (i >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -189,9 +189,9 @@ __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const VertSeg& S = L.seg[s];
-  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.v_edge, S.m.v_cell, S.m.vs, S.Usrc, S.hs, S.m.e_dc, S.q);
+  if constexpr (ONE) sgpr_ready(L.block, S.m.v_edge, S.m.v_cell, S.m.vs, S.Usrc, S.hs, S.m.e_dc, S.q);
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   const int v = (int)(item >> nm_log2);
   if (v >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -199,18 +199,52 @@ __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
   S.q[(long)v * nm + mem] = vertex_q(S.m, v, S.Usrc, S.hs, nm, mem);
 }
 
+// q at an edge's two vertices v0, v1 from the per-edge copies of their lists:
+// the same operations, in the same order, as vertex_q.
+__device__ __forceinline__ void edge_vertices_q(const MeshDev& m, int e, int v0, int v1, const double* __restrict__ Usrc,
+                                                const double* __restrict__ hs, int nm, int mem, double& q0,
+                                                double& q1) {
+  int code[6], cell[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    code[k] = m.e_vq_edge[k * m.es + e];
+    cell[k] = m.e_vq_cell[k * m.es + e];
+  }
+  double q[2];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int v = side ? v1 : v0;
+    double circ = 0.0, hv = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int k = 3 * side + j;
+      const int ed = code[k] >> 1;
+      const double c = m.e_dc[ed] * Usrc[(long)ed * nm + mem];
+      circ = (code[k] & 1) ? circ - c : circ + c;
+      hv = fma(m.v_kite[j * m.vs + v], hs[(long)cell[k] * nm + mem], hv);
+    }
+    const double ia = m.v_invA[v];
+    q[side] = (circ * ia + m.v_f[v]) / (hv * ia);
+  }
+  q0 = q[0];
+  q1 = q[1];
+}
+
 // ---------------------------------------------------------------- prep pass
 // FUSE_Q: evaluate q at the edge's two vertices here instead of reading the
 // vertex pass's output (one launch fewer per stage, each vertex evaluated by
 // its three edges).
-template <bool FUSE_Q, bool ONE>
+template <bool LINEAR, bool FUSE_Q, bool ONE>
 __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const PrepSeg& S = L.seg[s];
-  if constexpr (ONE) sgpr_ready(blockDim.x, S.m.e_cell, S.m.e_vert, S.m.es, S.m.E, S.Usrc, S.m.e_dv, S.hs, S.linear, S.P);
+  if constexpr (ONE) {
+    sgpr_ready(L.block, S.m.e_cell, S.m.e_vert, S.m.es, S.m.E, S.Usrc, S.m.e_dv, S.hs, S.P);
+    if constexpr (FUSE_Q) sgpr_ready(S.m.e_vq_edge, S.m.e_vq_cell, S.m.e_dc, S.m.v_kite, S.m.vs);
+  }
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -221,13 +255,15 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
   const double u = S.Usrc[(long)e * nm + mem];
   const double dv = m.e_dv[e];
   double he, qe;
-  if (S.linear) {
+  if constexpr (LINEAR) {
     he = m.e_He[e];
     qe = 0.5 * (S.q[v0] + S.q[v1]);
   } else {
     he = 0.5 * (S.hs[(long)c0 * nm + mem] + S.hs[(long)c1 * nm + mem]);
     if (FUSE_Q) {
-      qe = 0.5 * (vertex_q(m, v0, S.Usrc, S.hs, nm, mem) + vertex_q(m, v1, S.Usrc, S.hs, nm, mem));
+      double q0, q1;
+      edge_vertices_q(m, e, v0, v1, S.Usrc, S.hs, nm, mem, q0, q1);
+      qe = 0.5 * (q0 + q1);
     } else {
       qe = 0.5 * (S.q[(long)v0 * nm + mem] + S.q[(long)v1 * nm + mem]);
     }
@@ -308,12 +344,12 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
   if constexpr (ONE) {
-    sgpr_ready(blockDim.x, S.P, S.B, S.m.es, S.m.E, S.m.e_cell, S.m.e_invdc);
+    sgpr_ready(L.block, S.P, S.B, S.m.es, S.m.E, S.m.e_cell, S.m.e_invdc);
     if constexpr (CELLS) sgpr_ready(S.m.e_cs, S.m.c_edge, S.m.c_R, S.m.cs);
     else sgpr_ready(S.m.e_eoe, S.m.e_w, S.m.e_neoe);
   }
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -378,9 +414,9 @@ __global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
-  if constexpr (ONE) sgpr_ready(blockDim.x, S.B, S.m.es, S.m.e_cell, S.m.e_invdc, S.Udst, S.U0);
+  if constexpr (ONE) sgpr_ready(L.block, S.B, S.m.es, S.m.e_cell, S.m.e_invdc, S.Udst, S.U0);
   const int nm_log2 = S.nm_log2;
-  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
+  const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   const int e = (int)(item >> nm_log2);
   if (e >= S.end) return;
   const int mem = (int)(item & ((1 << nm_log2) - 1));
@@ -403,12 +439,12 @@ __global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
   const int b = blockIdx.x;
   const int s = find_seg<ONE>(L, b);
   const PredSeg& S = L.seg[s];
-  if constexpr (ONE) sgpr_ready(blockDim.x, S.save, S.c_begin, S.c_end, S.e_begin, S.e_end, S.a, S.invM);
+  if constexpr (ONE) sgpr_ready(L.block, S.save, S.c_begin, S.c_end, S.e_begin, S.e_end, S.a, S.invM);
   const int nm_log2 = S.nm_log2;
   const int nm = 1 << nm_log2;
   const long nc = (long)(S.c_end - S.c_begin) * nm;
   const long ne = (long)(S.e_end - S.e_begin) * nm;
-  const long t = (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
+  const long t = (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   if (t < nc) {
     const long i = (long)S.c_begin * nm + t;
     double hn, h1, h2, h3;
@@ -444,12 +480,12 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
   const int b = blockIdx.x;
   const int s = find_seg<ONE>(L, b);
   const AsmSeg& S = L.seg[s];
-  if constexpr (ONE) sgpr_ready(blockDim.x, S.if1_c_begin, S.if1_c_end, S.if2_c_end, S.N, S.if1_e_begin, S.if1_e_end,
+  if constexpr (ONE) sgpr_ready(L.block, S.if1_c_begin, S.if1_c_end, S.if2_c_end, S.N, S.if1_e_begin, S.if1_e_end,
                                 S.if2_e_end, S.E);
   const int nm = 1 << S.nm_log2;
   const long ncell = (long)(S.N - S.if1_c_begin) * nm;
   const long nedge = (long)(S.E - S.if1_e_begin) * nm;
-  const long t = (long)(b - seg_block<ONE>(L, s)) * blockDim.x + threadIdx.x;
+  const long t = (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   if (t < ncell) {
     const long i = (long)S.if1_c_begin * nm + t;
     const long c = i >> S.nm_log2;
@@ -604,6 +640,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_final(const double* partial, in
 // ------------------------------------------------------------- host launchers
 template <class S>
 static int blocks_for(Launch<S>& L, long (*items)(const S&), int bs) {
+  L.block = bs;
   int acc = 0;
   for (int s = 0; s < L.nseg; ++s) {
     L.blk_start[s] = acc;
@@ -669,11 +706,13 @@ int launch_vertex(Launch<VertSeg> L, int bs, hipStream_t st) {
   return nb;
 }
 
+// Every segment of a launch has the same physics (linear or not).
 int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st) {
   const int nb = blocks_for(L, prep_items, bs);
   if (nb == 0) return 0;
-  if (fuse_q) launch_segs(k_prep<true, true>, k_prep<true, false>, nb, bs, st, L);
-  else launch_segs(k_prep<false, true>, k_prep<false, false>, nb, bs, st, L);
+  if (L.seg[0].linear) launch_segs(k_prep<true, false, true>, k_prep<true, false, false>, nb, bs, st, L);
+  else if (fuse_q) launch_segs(k_prep<false, true, true>, k_prep<false, true, false>, nb, bs, st, L);
+  else launch_segs(k_prep<false, false, true>, k_prep<false, false, false>, nb, bs, st, L);
   return nb;
 }
 

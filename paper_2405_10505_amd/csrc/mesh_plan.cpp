@@ -834,6 +834,7 @@ double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int n
   for (int e = r.b; e < r.e; ++e) {
     b += 8 + 8 + 8 + S + 4 * S;   // cells, vertices, l_e, u, P write
     if (!nonlinear) b += 8;       // H_e
+    if (nonlinear && fuse_q) b += 6 * (4 + 4);   // the vertices' edge codes and cells, copied per edge
     if (fuse_q) se.mark(e);
     for (int j = 0; j < 2; ++j) {
       const int c = pm.e_cell[(size_t)j * pm.es + e];
@@ -847,7 +848,7 @@ double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int n
         } else {
           // the vertex's own data: codes, cells, kites, 1/A_v, f_v; and its
           // edges' d_e, u and cells' h* when not already counted
-          b += 3 * (4 + 4 + 8) + 8 + 8;   // codes, cells, kites, 1/A_v, f_v
+          b += 3 * 8 + 8 + 8;   // kites, 1/A_v, f_v
           for (int t = 0; t < 3; ++t) {
             const int e2 = pm.v_edge[(size_t)t * pm.vs + v] >> 1;
             if (se.mark(e2)) b += 8 + S;    // d_e, u

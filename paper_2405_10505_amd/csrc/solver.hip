@@ -128,7 +128,7 @@ struct DevMesh {
   DevBuf c_nedge, c_edge, c_nbr, c_invA, c_A, c_H;
   DevBuf e_cell, e_vert, e_dc, e_dv, e_invdc, e_He, e_neoe, e_eoe, e_w;
   DevBuf v_edge, v_cell, v_kite, v_invA, v_A, v_f, v_q0;
-  DevBuf e_wT, c_vert, c_kite, c_R, e_cs;
+  DevBuf e_wT, c_vert, c_kite, c_R, e_cs, e_vq_edge, e_vq_cell;
   DevBuf cell_n2o, edge_n2o, vert_n2o;
   MeshDev md{};
   void upload_from(const PermMesh& pm, const Plan& p) {
@@ -159,6 +159,21 @@ struct DevMesh {
     upload(c_kite, pm.c_kite);
     upload(c_R, pm.c_R);
     upload(e_cs, pm.e_cs);
+    {
+      // each edge's two vertex lists, slot-major per edge: the prep pass with
+      // fused q_v then finds the vertices' edges and cells in its first round
+      std::vector<int> vqe((size_t)6 * pm.es, 0), vqc((size_t)6 * pm.es, 0);
+      for (int e = 0; e < pm.E; ++e)
+        for (int side = 0; side < 2; ++side) {
+          const int v = pm.e_vert[(size_t)side * pm.es + e];
+          for (int j = 0; j < 3; ++j) {
+            vqe[(size_t)(3 * side + j) * pm.es + e] = pm.v_edge[(size_t)j * pm.vs + v];
+            vqc[(size_t)(3 * side + j) * pm.es + e] = pm.v_cell[(size_t)j * pm.vs + v];
+          }
+        }
+      upload(e_vq_edge, vqe);
+      upload(e_vq_cell, vqc);
+    }
     upload(cell_n2o, p.cell_new2old);
     upload(edge_n2o, p.edge_new2old);
     upload(vert_n2o, p.vert_new2old);
@@ -197,6 +212,8 @@ struct DevMesh {
     md.c_kite = c_kite.as<double>();
     md.c_R = c_R.as<double>();
     md.e_cs = e_cs.as<int>();
+    md.e_vq_edge = e_vq_edge.as<int>();
+    md.e_vq_cell = e_vq_cell.as<int>();
   }
 };
 
