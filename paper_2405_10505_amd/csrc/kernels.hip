@@ -338,7 +338,13 @@ __device__ __forceinline__ void walk_cell(const MeshDev& m, const double* __rest
 // CELLS: the PV flux through the two cells' edge lists and kite fractions
 // (walk_cell) instead of the edges_on_edge list and stored weights; only for
 // meshes whose stored weights are exactly those walks (the planner checks).
-template <bool DRAG, bool WIND, bool CELLS, bool ONE>
+// GROUP (every segment has at least 16 members and at most 16 edges_on_edge
+// slots): the members of an edge fill whole 16-lane groups of the wavefront,
+// so lane r of each group loads slot r's index and weight once and the group
+// shares them through cross-lane permutes instead of every lane loading every
+// slot; all maxEOE slots are taken (the padding slots are exact no-ops), so
+// every lane of the group takes part in every permute.
+template <bool DRAG, bool WIND, bool CELLS, bool ONE, bool GROUP>
 __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
@@ -346,7 +352,7 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   if constexpr (ONE) {
     sgpr_ready(L.block, S.P, S.B, S.m.es, S.m.E, S.m.e_cell, S.m.e_invdc);
     if constexpr (CELLS) sgpr_ready(S.m.e_cs, S.m.c_edge, S.m.c_R, S.m.cs);
-    else sgpr_ready(S.m.e_eoe, S.m.e_w, S.m.e_neoe);
+    else sgpr_ready(S.m.e_eoe, S.m.e_w, S.m.e_neoe, S.m.maxEOE);
   }
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
@@ -365,6 +371,25 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
     const int w = m.e_cs[e];
     walk_cell<DRAG || WIND>(m, P, np, m.e_cell[e], w & 0xff, pey, nm, mem, sq, su);
     walk_cell<DRAG || WIND>(m, P, np, m.e_cell[m.es + e], (w >> 8) & 0xff, pey, nm, mem, sq, su);
+  } else if (GROUP) {
+    const int lane = threadIdx.x & 63, base = lane & ~15, r = lane & 15;
+    int idx_r = e;
+    double w_r = 0.0;
+    if (r < m.maxEOE) {
+      idx_r = m.e_eoe[r * m.es + e];
+      w_r = m.e_w[r * m.es + e];
+    }
+    auto slot = [&](int j) {
+      const int e2 = __shfl(idx_r, base + j);
+      const double w = __shfl(w_r, base + j);
+      const long k2 = (long)e2 * nm + mem;
+      const double2 p2 = rec_fq(P, k2);
+      sq = fma(w * p2.x, pey + p2.y, sq);
+      if (DRAG || WIND) su = fma(w, rec_lu(P, np, k2), su);
+    };
+#pragma unroll
+    for (int j = 0; j < kUnrollEOE; ++j) slot(j);
+    for (int j = kUnrollEOE; j < m.maxEOE; ++j) slot(j);
   } else {
     const int n = m.e_neoe[e];
     auto slot = [&](int j) {
@@ -716,19 +741,32 @@ int launch_prep(Launch<PrepSeg> L, bool fuse_q, int bs, hipStream_t st) {
   return nb;
 }
 
-template <bool CELLS>
+template <bool CELLS, bool GROUP>
 static void launch_edge_t(const Launch<EdgeSeg>& L, bool drag, bool wind, int nb, int bs, hipStream_t st) {
-  if (drag && wind) launch_segs(k_edge<true, true, CELLS, true>, k_edge<true, true, CELLS, false>, nb, bs, st, L);
-  else if (drag) launch_segs(k_edge<true, false, CELLS, true>, k_edge<true, false, CELLS, false>, nb, bs, st, L);
-  else if (wind) launch_segs(k_edge<false, true, CELLS, true>, k_edge<false, true, CELLS, false>, nb, bs, st, L);
-  else launch_segs(k_edge<false, false, CELLS, true>, k_edge<false, false, CELLS, false>, nb, bs, st, L);
+  if (drag && wind)
+    launch_segs(k_edge<true, true, CELLS, true, GROUP>, k_edge<true, true, CELLS, false, GROUP>, nb, bs, st, L);
+  else if (drag)
+    launch_segs(k_edge<true, false, CELLS, true, GROUP>, k_edge<true, false, CELLS, false, GROUP>, nb, bs, st, L);
+  else if (wind)
+    launch_segs(k_edge<false, true, CELLS, true, GROUP>, k_edge<false, true, CELLS, false, GROUP>, nb, bs, st, L);
+  else
+    launch_segs(k_edge<false, false, CELLS, true, GROUP>, k_edge<false, false, CELLS, false, GROUP>, nb, bs, st, L);
+}
+
+// Slot sharing within 16-lane groups: every segment has >= 16 members (an
+// edge's members then fill whole, aligned 16-lane groups) and <= 16 slots.
+static bool group_slots(const Launch<EdgeSeg>& L) {
+  for (int s = 0; s < L.nseg; ++s)
+    if (L.seg[s].nm_log2 < 4 || L.seg[s].m.maxEOE > 16) return false;
+  return true;
 }
 
 int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st, bool cells) {
   const int nb = blocks_for(L, edge_items, bs);
   if (nb == 0) return 0;
-  if (cells) launch_edge_t<true>(L, drag, wind, nb, bs, st);
-  else launch_edge_t<false>(L, drag, wind, nb, bs, st);
+  if (cells) launch_edge_t<true, false>(L, drag, wind, nb, bs, st);
+  else if (group_slots(L)) launch_edge_t<false, true>(L, drag, wind, nb, bs, st);
+  else launch_edge_t<false, false>(L, drag, wind, nb, bs, st);
   return nb;
 }
 

@@ -182,3 +182,30 @@ def test_autotune_keeps_every_member_and_the_step_count(two_meshes):
             ha, ua = a.get_member(k, m)
             hb, ub = b.get_member(k, m)
             assert np.array_equal(ha, hb) and np.array_equal(ua, ub), (k, m)
+
+
+@pytest.mark.parametrize("nms", [[16, 32], [16]])
+def test_wide_members_share_slots_and_equal_single_solver_bitwise(two_meshes, nms):
+    """With 16 or more members per mesh the momentum pass shares each edge's
+    edges_on_edge slots across its members' lanes; results stay bitwise."""
+    ws = two_meshes[:len(nms)]
+    dt = min(w.dt for w in ws)
+    fms = [F.Mesh(w.mesh) for w in ws]
+    ens = F.Ensemble(fms, [np.where(w.fine_mask, 0, 1) for w in ws], nms, dt, M=4, linear=False)
+    inputs = [_members(w, nm, k) for k, (w, nm) in enumerate(zip(ws, nms))]
+    for k, mem in enumerate(inputs):
+        for m, (h, u, cd) in enumerate(mem):
+            ens.set_member(k, m, h, u, cd)
+    ens.set_graph(True)
+    ens.step(5)
+    for k, (w, mem) in enumerate(zip(ws, inputs)):
+        for m in sorted({0, 7, nms[k] - 1}):
+            h, u, cd = mem[m]
+            s = F.Solver(fms[k], dt, M=4, linear=False)
+            s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+            s.set_drag(cd)
+            s.set_state(h, u)
+            s.step(5)
+            hs, us = s.get_state()
+            he, ue = ens.get_member(k, m)
+            assert np.array_equal(he, hs) and np.array_equal(ue, us), (k, m)
