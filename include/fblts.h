@@ -134,6 +134,27 @@ void fblts_mesh_destroy(fblts_mesh* mesh);
  * (fine: -hops to the coarse set, coarse: +hops to the fine set; may be NULL).
  * Errors: FBLTS_EINVAL (bad values), FBLTS_EREGION (adjacent cells more than
  * one region apart, the stencil condition of Sec 2.2). */
+/* Region plan (Sec 2.2 and the library's pass ranges; host only, no device):
+ * what fblts_set_regions builds for FB-LTS from these labels.  Cells are
+ * renumbered region by region (fine, interface one, interface two,
+ * interior), edges by their lower cell; every pass runs on an index range of
+ * that numbering.  Per FB-RK(3,2) stage s = 0, 1, 2: the coarse advancement
+ * updates cells [coarse_cell_begin[s], n_cells) and edges
+ * [coarse_edge_begin[s], n_edges); a fine substep's passes cover cells
+ * [0, fine_cell_end[s]) and edges [0, fine_edge_end[s]) (each range closed
+ * under the stencils of the stages after it).  nonlinear selects the
+ * nonlinear stencils, which are wider than the linear ones.
+ * Errors as fblts_layer_regions. */
+typedef struct fblts_plan_info {
+  int32_t n_cells, n_edges;
+  int32_t n_fine, n_if1, n_if2, n_int;          /* cells per region */
+  int32_t n_fine_e, n_if1_e, n_if2_e, n_int_e;  /* edges per region */
+  int32_t coarse_cell_begin[3], coarse_edge_begin[3];
+  int32_t fine_cell_end[3], fine_edge_end[3];
+} fblts_plan_info;
+int fblts_plan(const fblts_mesh* mesh, const int8_t* labels, int32_t binary, int32_t r, int32_t nonlinear,
+               fblts_plan_info* out);
+
 int fblts_layer_regions(const fblts_mesh* mesh, const int8_t* labels, int32_t binary, int32_t r,
                         int8_t* out_labels, int32_t* out_layer);
 

@@ -54,6 +54,16 @@ class fblts_diag(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class fblts_plan_info(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_cells", "n_edges", "n_fine", "n_if1", "n_if2", "n_int",
+                                         "n_fine_e", "n_if1_e", "n_if2_e", "n_int_e")] + \
+               [(n, C.c_int32 * 3) for n in ("coarse_cell_begin", "coarse_edge_begin", "fine_cell_end",
+                                             "fine_edge_end")]
+
+    def as_dict(self):
+        return {k: (getattr(self, k) if t is C.c_int32 else list(getattr(self, k))) for k, t in self._fields_}
+
+
 class fblts_schedule(C.Structure):
     _fields_ = [("fuse_vertex", C.c_int32), ("block", C.c_int32), ("edge_cells", C.c_int32),
                 ("from_cache", C.c_int32), ("ms_per_step", C.c_double)]
@@ -86,6 +96,8 @@ _SIGS = {
     "fblts_mesh_destroy": (None, [C.c_void_p]),
     "fblts_layer_regions": (C.c_int, [C.c_void_p, C.POINTER(C.c_int8), C.c_int32, C.c_int32,
                                       C.POINTER(C.c_int8), _P_i32]),
+    "fblts_plan": (C.c_int, [C.c_void_p, C.POINTER(C.c_int8), C.c_int32, C.c_int32, C.c_int32,
+                             C.POINTER(fblts_plan_info)]),
     "fblts_solver_create": (C.c_int, [C.c_void_p, C.POINTER(fblts_params), C.c_void_p, C.POINTER(C.c_void_p)]),
     "fblts_solver_destroy": (None, [C.c_void_p]),
     "fblts_set_regions": (C.c_int, [C.c_void_p, C.POINTER(C.c_int8), C.c_int32]),
@@ -235,6 +247,14 @@ class Mesh:
         _check(lib().fblts_layer_regions(self.handle, lab.ctypes.data_as(C.POINTER(C.c_int8)), int(binary), int(r),
                                          out.ctypes.data_as(C.POINTER(C.c_int8)), layer.ctypes.data_as(_P_i32)))
         return out, layer
+
+    def plan(self, labels, binary=True, r=2, nonlinear=True):
+        """fblts_plan: region counts and pass ranges (host only)."""
+        lab = _host(labels, np.int8, self.n_cells, "labels")
+        out = fblts_plan_info()
+        _check(lib().fblts_plan(self.handle, lab.ctypes.data_as(C.POINTER(C.c_int8)), int(binary), int(r),
+                                int(nonlinear), C.byref(out)))
+        return out.as_dict()
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -1422,6 +1422,37 @@ int fblts_layer_regions(const fblts_mesh* mesh, const int8_t* labels, int32_t bi
   });
 }
 
+int fblts_plan(const fblts_mesh* mesh, const int8_t* labels, int32_t binary, int32_t r, int32_t nonlinear,
+               fblts_plan_info* out) {
+  return guarded([&] {
+    if (!mesh || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (r < 1 || r > 64) throw Err(FBLTS_EINVAL, "r must be in 1..64");
+    std::vector<int8_t> lab4;
+    std::vector<int> layer;
+    layer_regions(mesh->hm, labels, binary != 0, r, lab4, layer);
+    Plan p;
+    build_plan(mesh->hm, lab4, layer, true, nonlinear != 0, r, p);
+    std::memset(out, 0, sizeof(*out));
+    out->n_cells = mesh->hm.N;
+    out->n_edges = mesh->hm.E;
+    out->n_fine = p.nF;
+    out->n_if1 = p.nIF1;
+    out->n_if2 = p.nIF2;
+    out->n_int = p.nINT;
+    out->n_fine_e = p.nFE;
+    out->n_if1_e = p.nIF1E;
+    out->n_if2_e = p.nIF2E;
+    out->n_int_e = p.nINTE;
+    for (int s = 0; s < 3; ++s) {
+      out->coarse_cell_begin[s] = p.coarse[s].cell.b;
+      out->coarse_edge_begin[s] = p.coarse[s].edge.b;
+      out->fine_cell_end[s] = p.fine[s].cell.e;
+      out->fine_edge_end[s] = p.fine[s].edge.e;
+    }
+    return FBLTS_OK;
+  });
+}
+
 int fblts_solver_create(const fblts_mesh* mesh, const fblts_params* params, void* hip_stream, fblts_solver** out) {
   return guarded([&] {
     if (!mesh || !out) throw Err(FBLTS_EINVAL, "NULL argument");

@@ -71,6 +71,34 @@ def test_mesh_validation_rejects(hexm, mutate, msg):
     assert msg in str(e.value) or "vertex j" in str(e.value)
 
 
+@pytest.mark.parametrize("name", ["small_cvt", "config1"])
+def test_plan_ranges_cover_the_regions(name):
+    """fblts_plan (host): region counts equal the oracle's layering; the coarse
+    advancement covers the coarse region and reaches into the fine region by
+    fewer cells at later stages; a fine substep covers the fine region and its
+    third stage the interface accumulations; linear stencils are never wider
+    than nonlinear ones."""
+    w = getattr(workloads, name)()
+    fm = F.Mesh(w.mesh)
+    ref, _ = regions.layer(trisk.OMesh(w.mesh), w.fine_mask, 2)
+    p = fm.plan(np.where(w.fine_mask, 0, 1), nonlinear=True)
+    pl = fm.plan(np.where(w.fine_mask, 0, 1), nonlinear=False)
+    assert [p["n_fine"], p["n_if1"], p["n_if2"], p["n_int"]] == [int(np.sum(ref == k)) for k in range(4)]
+    cells, e = w.mesh.cells_on_edge, ref[w.mesh.cells_on_edge].min(axis=1)   # an edge's region: its finer cell
+    assert [p["n_fine_e"], p["n_if1_e"], p["n_if2_e"], p["n_int_e"]] == [int(np.sum(e == k)) for k in range(4)]
+    nF, nFE = p["n_fine"], p["n_fine_e"]
+    nIF, nIFE = nF + p["n_if1"] + p["n_if2"], nFE + p["n_if1_e"] + p["n_if2_e"]
+    for q in (p, pl):
+        cb, eb = q["coarse_cell_begin"], q["coarse_edge_begin"]
+        assert cb[0] <= cb[1] <= cb[2] <= nF and eb[0] <= eb[1] <= eb[2] <= nFE
+        fc, fe = q["fine_cell_end"], q["fine_edge_end"]
+        assert min(fc) >= nF and fe[0] >= nFE and fe[1] >= nFE
+        assert fc[2] >= nIF and fe[2] >= nIFE
+        assert all(x <= p["n_cells"] for x in fc) and all(x <= p["n_edges"] for x in fe)
+    assert all(a >= b for a, b in zip(pl["coarse_cell_begin"], p["coarse_cell_begin"]))
+    assert all(a <= b for a, b in zip(pl["fine_cell_end"], p["fine_cell_end"]))
+
+
 def test_layering_matches_oracle_and_rejects_bad_labels():
     w = workloads.small_cvt()
     fm = F.Mesh(w.mesh)
