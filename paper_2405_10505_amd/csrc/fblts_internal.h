@@ -13,9 +13,11 @@ namespace fblts {
 constexpr int kMaxSeg = 4;       // meshes (segments) one launch can cover
 constexpr int kBlock = 256;      // threads per block for the stencil passes
 // Gather loops issue the first slots' loads together (no loop-carried
-// address dependence): cells unroll 6 edge slots, edges 10 edges_on_edge slots.
-constexpr int kUnrollCell = 6;
-constexpr int kUnrollEOE = 10;
+// address dependence): cells unroll 7 edge slots (heptagons included), edges
+// 12 edges_on_edge slots (an edge between two heptagons); longer lists, rare
+// on Voronoi meshes, finish in a loop.
+constexpr int kUnrollCell = 7;
+constexpr int kUnrollEOE = 12;
 
 // Permuted mesh, device pointers.  Edge codes carry a sign bit:
 // code = 2*e + (sign < 0 ? 1 : 0).

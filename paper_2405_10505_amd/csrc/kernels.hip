@@ -95,7 +95,14 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   const bool in_upd = i >= S.upd_begin && i < S.upd_end;
   const bool in_acc = i >= S.acc_begin && i < S.acc_end;
   const bool need_psi = in_upd || in_acc;
-  const double h_i = S.Hsrc[(long)i * nm + mem];
+  const long ii = (long)i * nm + mem;
+  const double h_i = S.Hsrc[ii];
+  // the cell's own operands, loaded ahead of the gathers
+  const double h0 = S.H0[ii];
+  const double invA = m.c_invA[i];
+  const double Hrest = m.c_H[i];
+  const double hnew_src = in_upd ? 0.0 : S.Hnew_src[ii];
+  const double acc0 = (in_acc && !S.acc_first) ? S.acc[ii] : 0.0;
   double flux = 0.0, ke = 0.0;
   const int ne = m.c_nedge[i];
   // Phase 1: the first kUnrollCell slots exist for every cell (padded lists),
@@ -140,24 +147,22 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
     acc_slot(c, u, m.e_dv[e], KE ? m.e_dc[e] : 0.0, hnb, true);
   }
   (void)need_psi;
-  const long ii = (long)i * nm + mem;
-  const double psi = -flux * m.c_invA[i];
+  const double psi = -flux * invA;
   double hnew;
-  const double h0 = S.H0[ii];
   if (in_upd) {
     hnew = fma(S.c_dt, psi, h0);
     S.Hdst[ii] = hnew;
   } else {
-    hnew = S.Hnew_src[ii];
+    hnew = hnew_src;
   }
   if (in_acc) {
     const double a = S.acc_w * psi;
-    S.acc[ii] = S.acc_first ? a : S.acc[ii] + a;
+    S.acc[ii] = S.acc_first ? a : acc0 + a;
   }
   const double hs = S.wn * hnew + S.ws * h_i + S.wb * h0;
   S.hs[ii] = hs;
-  const double K = KE ? 0.25 * ke * m.c_invA[i] : 0.0;
-  S.B[ii] = K + S.g * (hs - m.c_H[i]);
+  const double K = KE ? 0.25 * ke * invA : 0.0;
+  S.B[ii] = K + S.g * (hs - Hrest);
 }
 
 // -------------------------------------------------------------- vertex pass
@@ -364,8 +369,19 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   const double* P = S.P;
   const long np = (long)m.E << nm_log2;
   const long ee = (long)e * nm + mem;
+  // the edge's own operands, loaded ahead of the neighbour gathers so that
+  // they share the gathers' rounds instead of following them
+  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  const double idc = m.e_invdc[e];
+  const double B0 = S.B[(long)c0 * nm + mem], B1 = S.B[(long)c1 * nm + mem];
   const double pey = rec_q(P, ee);
   const double he = (DRAG || WIND) ? rec_he(P, np, ee) : 1.0;
+  const double u = (DRAG || WIND) ? S.Usrc[ee] : 0.0;
+  const double cde = DRAG ? 0.5 * (S.cd[(long)c0 * nm + mem] + S.cd[(long)c1 * nm + mem]) : 0.0;
+  const double wn = WIND ? S.wind_n[ee] : 0.0, wt = WIND ? S.wind_t[ee] : 0.0;
+  const bool upd = e >= S.upd_begin && e < S.upd_end, acc = e >= S.acc_begin && e < S.acc_end;
+  const double u0 = upd ? S.U0[ee] : 0.0;
+  const double acc0 = (acc && !S.acc_first) ? S.acc[ee] : 0.0;
   double sq = 0.0, su = 0.0;
   if (CELLS) {
     const int w = m.e_cs[e];
@@ -401,32 +417,26 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
       if (DRAG || WIND) su = fma(w, rec_lu(P, np, k2), su);
     };
     // the first kUnrollEOE slots exist for every edge (padded with the edge
-    // itself at weight 0, an exact no-op): their loads issue together
+    // itself at weight 0, an exact no-op): their loads issue together; the
+    // loop covers the rare longer lists
 #pragma unroll
     for (int j = 0; j < kUnrollEOE; ++j) slot(j);
     for (int j = kUnrollEOE; j < n; ++j) slot(j);
   }
-  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
-  const double idc = m.e_invdc[e];
-  double phi = 0.5 * sq * idc - (S.B[(long)c1 * nm + mem] - S.B[(long)c0 * nm + mem]) * idc;
+  double phi = 0.5 * sq * idc - (B1 - B0) * idc;
   if (DRAG || WIND) {
-    const double u = S.Usrc[ee];
     const double up = su * idc;
-    if (DRAG) {
-      const double cde = 0.5 * (S.cd[(long)c0 * nm + mem] + S.cd[(long)c1 * nm + mem]);
-      phi -= cde * sqrt(u * u + up * up) * u / he;
-    }
+    if (DRAG) phi -= cde * sqrt(u * u + up * up) * u / he;
     if (WIND) {
-      const double wn = S.wind_n[ee], wt = S.wind_t[ee];
       const double cw = S.rho_ratio * (0.75 + 0.067 * sqrt(wn * wn + wt * wt)) * 1e-3;
       const double rn = wn - u, rt = wt - up;
       phi += cw * sqrt(rn * rn + rt * rt) * rn / he;
     }
   }
-  if (e >= S.upd_begin && e < S.upd_end) S.Udst[ee] = fma(S.c_dt, phi, S.U0[ee]);
-  if (e >= S.acc_begin && e < S.acc_end) {
+  if (upd) S.Udst[ee] = fma(S.c_dt, phi, u0);
+  if (acc) {
     const double a = S.acc_w * phi;
-    S.acc[ee] = S.acc_first ? a : S.acc[ee] + a;
+    S.acc[ee] = S.acc_first ? a : acc0 + a;
   }
 }
 
