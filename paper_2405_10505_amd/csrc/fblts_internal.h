@@ -102,7 +102,7 @@ struct PrepSeg {
   const double* Usrc;
   const double* hs;
   const double* q;         // per member (nonlinear) or the static q0 (linear)
-  double* P;               // double4 per edge and member
+  double* P;               // 4 doubles per edge and member, split by use (prep_record.h)
 };
 
 // Momentum pass: Phi_e from P, B, drag and wind over edges; update
