@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fblts_internal.h"
+#include "lincomb.h"
 #include "prep_record.h"
 
 namespace fblts {
@@ -39,6 +40,26 @@ __global__ void __launch_bounds__(kBlock) k_lincomb(double* y, double b, const d
   y[i] = v;
 }
 
+// A run of elementwise combinations in one launch: thread i applies every
+// descriptor whose range holds i, in order.  Each combination reads and writes
+// only index i of its arrays, so this equals launching them one after another.
+__global__ void __launch_bounds__(kBlock) k_lincomb_batch(const LinBatch B) {
+  const int i = tid_global();
+  for (int k = 0; k < B.n; ++k) {
+    const LinDesc& D = B.d[k];
+    if (i < D.begin || i >= D.end) continue;
+    double v = D.b == 0.0 ? 0.0 : D.b * D.y[i];
+    if (D.x0) v = v + D.a0 * D.x0[i];
+    if (D.x1) v = v + D.a1 * D.x1[i];
+    if (D.x2) v = v + D.a2 * D.x2[i];
+    D.y[i] = v;
+  }
+}
+
+// Cell-slot loops: the first kUnrollCell slots exist for every cell (padded
+// lists), so their loads issue together; slots past the cell's degree are
+// skipped (the sums are the plain in-order sums).
+
 // ------------------------------------------------------------ Psi transpose
 // Fbar_e = l_e (-pb_c0/A_c0 + pb_c1/A_c1); ub_e += Fbar_e h_e; T_e = Fbar_e u_e.
 __global__ void __launch_bounds__(kBlock) k_psi_vjp_edge(MeshDev m, int linear, const double* u, const double* h,
@@ -57,9 +78,16 @@ __global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, const double
   const int i = tid_global();
   if (i >= m.N) return;
   const int n = m.c_nedge[i];
+  const double hb0 = hb[i];
+  double t[kUnrollCell];
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j) t[j] = T[m.c_edge[j * m.cs + i] >> 1];
   double s = 0.0;
-  for (int j = 0; j < n; ++j) s += T[m.c_edge[j * m.cs + i] >> 1];
-  hb[i] = fma(0.5, s, hb[i]);
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j)
+    if (j < n) s += t[j];
+  for (int j = kUnrollCell; j < n; ++j) s += T[m.c_edge[j * m.cs + i] >> 1];
+  hb[i] = fma(0.5, s, hb0);
 }
 
 // ------------------------------------------------------------ Phi transpose
@@ -73,18 +101,29 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int drag, cons
   G[e] = g;
   if (!drag) return;
   const int n = m.e_neoe[e];
-  double su = 0.0;
-  for (int j = 0; j < n; ++j) su = fma(m.e_w[j * m.es + e], rec_lu(P, m.E, m.e_eoe[j * m.es + e]), su);
-  const double up = su * m.e_invdc[e];
+  // the edge's own operands first, then every slot's loads together
   const double ue = u[e];
   const double he = rec_he(P, m.E, e);
   const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
   const double cde = 0.5 * (cd[c0] + cd[c1]);
+  const double ub0 = ub[e];
+  double w[kUnrollEOE], lu[kUnrollEOE];
+#pragma unroll
+  for (int j = 0; j < kUnrollEOE; ++j) {
+    w[j] = m.e_w[j * m.es + e];
+    lu[j] = rec_lu(P, m.E, m.e_eoe[j * m.es + e]);
+  }
+  double su = 0.0;
+#pragma unroll
+  for (int j = 0; j < kUnrollEOE; ++j)
+    if (j < n) su = fma(w[j], lu[j], su);
+  for (int j = kUnrollEOE; j < n; ++j) su = fma(m.e_w[j * m.es + e], rec_lu(P, m.E, m.e_eoe[j * m.es + e]), su);
+  const double up = su * m.e_invdc[e];
   const double sp = sqrt(ue * ue + up * up);
   // D = C_D |u| u / h_e, Phi -= D; |u| u is C^1 with zero derivative at |u| = 0
   const double dDdu = sp > 0.0 ? cde * (sp + ue * ue / sp) / he : 0.0;
   const double dDdup = sp > 0.0 ? cde * ue * up / (sp * he) : 0.0;
-  ub[e] = fma(-fb[e], dDdu, ub[e]);
+  ub[e] = fma(-fb[e], dDdu, ub0);
   R[e] = -fb[e] * dDdup * m.e_invdc[e];
   HD[e] = fb[e] * cde * sp * ue / (he * he);
   CDB[e] = -fb[e] * sp * ue / he;
@@ -96,14 +135,25 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, double g, cons
   const int i = tid_global();
   if (i >= m.N) return;
   const int n = m.c_nedge[i];
+  const double hsb0 = hsb[i];
+  int code[kUnrollCell];
+  double x[kUnrollCell];
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j) {
+    code[j] = m.c_edge[j * m.cs + i];
+    x[j] = G[code[j] >> 1];
+  }
   double s = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const int code = m.c_edge[j * m.cs + i];
-    const double x = G[code >> 1];
-    s = (code & 1) ? s - x : s + x;
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j)
+    if (j < n) s = (code[j] & 1) ? s - x[j] : s + x[j];
+  for (int j = kUnrollCell; j < n; ++j) {
+    const int c = m.c_edge[j * m.cs + i];
+    const double y = G[c >> 1];
+    s = (c & 1) ? s - y : s + y;
   }
   BB[i] = s;
-  hsb[i] = fma(g, s, hsb[i]);
+  hsb[i] = fma(g, s, hsb0);
 }
 
 // Pass 3 (edges, edges_on_edge gathers): PV-flux transpose, drag perp transpose,
@@ -116,33 +166,56 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int linear, in
   if (e >= m.E) return;
   const double2 pe = rec_fq(P, e);
   const int n = m.e_neoe[e];
+  // the edge's own operands first, then every slot's loads together
+  const double ue = u[e];
+  const double le = m.e_dv[e];
+  const double ub0 = ub[e];
+  const double Ge = G[e];
+  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  const double kb = linear ? 0.0 : BB[c0] * m.c_invA[c0] + BB[c1] * m.c_invA[c1];
+  const double hde = (!linear && drag) ? HD[e] : 0.0;
+  const double heown = linear ? m.e_He[e] : rec_he(P, m.E, e);
+  const double dce = m.e_dc[e];
   double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const int e2 = m.e_eoe[j * m.es + e];
-    const double wT = m.e_wT[j * m.es + e];
-    const double w = m.e_w[j * m.es + e];
-    const double2 p2 = rec_fq(P, e2);
-    const double g2 = G[e2];
+  auto slot = [&](int e2, double wT, double w, const double2& p2, double g2, double r2) {
     s1 = fma(wT * g2, p2.y + pe.y, s1);   // d/d(lF)_e of the neighbours' Q_perp
     s2 = fma(w, p2.x, s2);                 // d Q_perp_e / d q_e (own sum)
     s3 = fma(wT, g2, s3);                  // d Q_perp_e2 / d q_e (neighbours)
-    if (drag) s4 = fma(wT, R[e2], s4);     // neighbours' |u| through u_perp
+    if (drag) s4 = fma(wT, r2, s4);        // neighbours' |u| through u_perp
+  };
+  int e2[kUnrollEOE];
+  double wT[kUnrollEOE], w[kUnrollEOE], g2[kUnrollEOE], r2[kUnrollEOE];
+  double2 p2[kUnrollEOE];
+#pragma unroll
+  for (int j = 0; j < kUnrollEOE; ++j) {
+    e2[j] = m.e_eoe[j * m.es + e];
+    wT[j] = m.e_wT[j * m.es + e];
+    w[j] = m.e_w[j * m.es + e];
+  }
+#pragma unroll
+  for (int j = 0; j < kUnrollEOE; ++j) {
+    p2[j] = rec_fq(P, e2[j]);
+    g2[j] = G[e2[j]];
+    r2[j] = drag ? R[e2[j]] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < kUnrollEOE; ++j)
+    if (j < n) slot(e2[j], wT[j], w[j], p2[j], g2[j], r2[j]);
+  for (int j = kUnrollEOE; j < n; ++j) {
+    const int f = m.e_eoe[j * m.es + e];
+    slot(f, m.e_wT[j * m.es + e], m.e_w[j * m.es + e], rec_fq(P, f), G[f], drag ? R[f] : 0.0);
   }
   const double lFb = 0.5 * s1;
-  const double ue = u[e];
-  const double le = m.e_dv[e];
   const double Fb = le * lFb;
-  double acc = ub[e];
+  double acc = ub0;
   if (!linear) {
-    QB[e] = 0.5 * (G[e] * s2 + pe.x * s3);
-    acc = fma(Fb, rec_he(P, m.E, e), acc);                     // F = h_e u
-    HE[e] = Fb * ue + (drag ? HD[e] : 0.0);                    // h_e's cotangent
-    const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
-    const double kb = BB[c0] * m.c_invA[c0] + BB[c1] * m.c_invA[c1];
-    acc = fma(0.5 * le * m.e_dc[e] * ue, kb, acc);             // K_i = (1/A_i) sum l d u^2 / 4
+    QB[e] = 0.5 * (Ge * s2 + pe.x * s3);
+    acc = fma(Fb, heown, acc);                                 // F = h_e u
+    HE[e] = Fb * ue + (drag ? hde : 0.0);                      // h_e's cotangent
+    acc = fma(0.5 * le * dce * ue, kb, acc);                   // K_i = (1/A_i) sum l d u^2 / 4
     if (drag) acc = fma(le, s4, acc);
   } else {
-    acc = fma(Fb, m.e_He[e], acc);                             // F = H_e u
+    acc = fma(Fb, heown, acc);                                 // F = H_e u
   }
   ub[e] = acc;
 }
@@ -181,15 +254,33 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_c2(MeshDev m, int drag, cons
   const int i = tid_global();
   if (i >= m.N) return;
   const int n = m.c_nedge[i];
+  const double hsb0 = hsb[i];
+  const double cdb0 = drag ? cdb[i] : 0.0;
+  double he[kUnrollCell], kv[kUnrollCell], hv[kUnrollCell], cb[kUnrollCell];
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j) {
+    const int e = m.c_edge[j * m.cs + i] >> 1;
+    he[j] = HE[e];
+    kv[j] = m.c_kite[j * m.cs + i];
+    hv[j] = HV[m.c_vert[j * m.cs + i]];
+    cb[j] = drag ? CDB[e] : 0.0;
+  }
   double se = 0.0, sv = 0.0, sc = 0.0;
-  for (int j = 0; j < n; ++j) {
+#pragma unroll
+  for (int j = 0; j < kUnrollCell; ++j)
+    if (j < n) {
+      se += he[j];
+      sv = fma(kv[j], hv[j], sv);
+      if (drag) sc += cb[j];
+    }
+  for (int j = kUnrollCell; j < n; ++j) {
     const int e = m.c_edge[j * m.cs + i] >> 1;
     se += HE[e];
     sv = fma(m.c_kite[j * m.cs + i], HV[m.c_vert[j * m.cs + i]], sv);
     if (drag) sc += CDB[e];
   }
-  hsb[i] = hsb[i] + 0.5 * se + sv;
-  if (drag) cdb[i] = fma(0.5, sc, cdb[i]);
+  hsb[i] = hsb0 + 0.5 * se + sv;
+  if (drag) cdb[i] = fma(0.5, sc, cdb0);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -199,6 +290,11 @@ void launch_lincomb(double* y, double b, const double* x0, double a0, const doub
                     double a2, int begin, int end, hipStream_t st) {
   if (end <= begin) return;
   hipLaunchKernelGGL(k_lincomb, grid_for(end - begin), dim3(kBlock), 0, st, y, b, x0, a0, x1, a1, x2, a2, begin, end);
+}
+
+void launch_lincomb_batch(const LinBatch& B, hipStream_t st) {
+  if (B.n == 0 || B.end_max <= 0) return;
+  hipLaunchKernelGGL(k_lincomb_batch, grid_for(B.end_max), dim3(kBlock), 0, st, B);
 }
 
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,

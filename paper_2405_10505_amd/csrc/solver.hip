@@ -27,6 +27,7 @@
 
 #include "../../include/fblts.h"
 #include "fblts_internal.h"
+#include "lincomb.h"
 #include "mesh_plan.h"
 
 namespace fblts {
@@ -762,6 +763,7 @@ void run_passes(const std::vector<Pass>& passes, bool drag, bool wind, hipStream
 // the tape to K steps.
 
 namespace fblts {
+void launch_lincomb_batch(const LinBatch& B, hipStream_t st);
 void launch_lincomb(double* y, double b, const double* x0, double a0, const double* x1, double a1, const double* x2,
                     double a2, int begin, int end, hipStream_t st);
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
@@ -805,18 +807,37 @@ struct Rev {
   double* qf;
   double* P;
   hipStream_t st;
+  // Inside a reverse step the elementwise combinations between two tendency
+  // transposes are collected and launched as one batch (same arithmetic per
+  // element, in the same order); elsewhere each launches at once.
+  bool batching = false;
+  LinBatch pending;
+  void flush() {
+    launch_lincomb_batch(pending, st);
+    pending.n = 0;
+    pending.end_max = 0;
+  }
   void lin(double* y, double b, const double* x0, double a0, const double* x1, double a1, const double* x2, double a2,
            int lo, int hi) {
-    launch_lincomb(y, b, x0, a0, x1, a1, x2, a2, lo, hi, st);
+    if (hi <= lo) return;
+    if (!batching) {
+      launch_lincomb(y, b, x0, a0, x1, a1, x2, a2, lo, hi, st);
+      return;
+    }
+    if (pending.n == kLinBatch) flush();
+    pending.d[pending.n++] = LinDesc{y, x0, x1, x2, b, a0, a1, a2, lo, hi};
+    pending.end_max = std::max(pending.end_max, hi);
   }
   void zero(double* y, int lo, int hi) { lin(y, 0.0, nullptr, 0, nullptr, 0, nullptr, 0, lo, hi); }
   void set(double* y, double a, const double* x, int lo, int hi) { lin(y, 0.0, x, a, nullptr, 0, nullptr, 0, lo, hi); }
   void axpy(double* y, double a, const double* x, int lo, int hi) { lin(y, 1.0, x, a, nullptr, 0, nullptr, 0, lo, hi); }
   void psi_vjp(const double* u, const double* h, const double* pbar, double* ubar, double* hbar) {
+    flush();
     launch_psi_vjp(*m, linear ? 1 : 0, u, h, pbar, ubar, hbar, Ed[Ta], st);
   }
   // cotangent fbar of Phi(u, hs) -> ubar (accumulated), hsbar (overwritten), C_D (accumulated)
   void phi_vjp(const double* u, const double* hs, const double* fbar, double* ubar, double* hsbar) {
+    flush();
     // forward intermediates at the point: q_v and the edge record
     if (!linear) {
       Launch<VertSeg> v{};
@@ -829,6 +850,7 @@ struct Rev {
     pp.seg[0] = PrepSeg{*m, 0, 0, E, linear ? 1 : 0, u, hs, linear ? m->v_q0 : qf, P};
     launch_prep(pp, false, kBlock, st);
     zero(hsbar, 0, N);
+    flush();
     launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, linear ? m->v_q0 : qf, cd, fbar, ubar, hsbar,
                    C[cdb], Ed[Ga], Ed[Ra], Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, st);
   }
@@ -846,6 +868,7 @@ struct Rev {
     const double* u2 = TE(2);
     double** c = C;
     double** e = Ed;
+    batching = true;
     for (int k : {hb, h1b, h2b, h3b, H0b, H1b, H2b, H3b, ahb}) zero(c[k], 0, N);
     for (int k : {ub, u1b, u2b, u3b, U0b, U1b, U2b, U3Fb, aub}) zero(e[k], 0, E);
     const double delta = dt / M;
@@ -971,6 +994,8 @@ struct Rev {
     axpy(c[hb], 1.0, c[h1b], 0, N);
     set(c[pb], dt / 3, c[h1b], 0, N);
     psi_vjp(u, h, c[pb], e[ub], c[hb]);
+    flush();
+    batching = false;
   }
 };
 
