@@ -222,37 +222,47 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int linear, in
 
 // Pass 4 (vertices): qbar_v = (1/2) sum_{e in E_v} QB_e; zeta and h_v cotangents
 // (scaled by 1/A_v): ZA_v = qbar_v / (h_v A_v), HV_v = -qbar_v q_v / (h_v A_v).
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_v1(MeshDev m, const double* hs, const double* q,
+// q_v = (zeta_v + f_v) / h_v is formed here from u and hs with the operations,
+// in the order, of the forward's vertex PV.
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_v1(MeshDev m, const double* u, const double* hs,
                                                        const double* QB, double* ZA, double* HV) {
   const int v = tid_global();
   if (v >= m.V) return;
-  double qb = 0.0, hv = 0.0;
+  int code[3], cell[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    qb += QB[m.v_edge[j * m.vs + v] >> 1];
-    hv = fma(m.v_kite[j * m.vs + v], hs[m.v_cell[j * m.vs + v]], hv);
+    code[j] = m.v_edge[j * m.vs + v];
+    cell[j] = m.v_cell[j * m.vs + v];
+  }
+  double qb = 0.0, circ = 0.0, hv = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int e = code[j] >> 1;
+    qb += QB[e];
+    const double c = m.e_dc[e] * u[e];
+    circ = (code[j] & 1) ? circ - c : circ + c;
+    hv = fma(m.v_kite[j * m.vs + v], hs[cell[j]], hv);
   }
   qb *= 0.5;
   const double ia = m.v_invA[v];
   const double hvv = hv * ia;   // h_v
+  const double q = (circ * ia + m.v_f[v]) / hvv;
   ZA[v] = qb / hvv * ia;
-  HV[v] = -qb * q[v] / hvv * ia;
+  HV[v] = -qb * q / hvv * ia;
 }
 
-// Pass 5 (edges): ub_e += d_e (ZA_{v1} - ZA_{v0})  (circulation sign +1 at v1).
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_e3(MeshDev m, const double* ZA, double* ub) {
-  const int e = tid_global();
-  if (e >= m.E) return;
+// Passes 5 and 6, independent of each other, in one launch: threads [0, E)
+// take the edges, threads [E, E + N) the cells.
+// Edges: ub_e += d_e (ZA_{v1} - ZA_{v0})  (circulation sign +1 at v1).
+// Cells: hsb_i += (1/2) sum_{e in E_i} HE_e + sum_{v in V_i} kite_{i,v} HV_v;
+// cdb_i += (1/2) sum_{e in E_i} CDB_e.
+__device__ __forceinline__ void phi_vjp_e3(const MeshDev& m, int e, const double* ZA, double* ub) {
   const int v0 = m.e_vert[e], v1 = m.e_vert[m.es + e];
   ub[e] = fma(m.e_dc[e], ZA[v1] - ZA[v0], ub[e]);
 }
 
-// Pass 6 (cells): hsb_i += (1/2) sum_{e in E_i} HE_e + sum_{v in V_i} kite_{i,v} HV_v;
-// cdb_i += (1/2) sum_{e in E_i} CDB_e.
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_c2(MeshDev m, int drag, const double* HE, const double* HV,
-                                                       const double* CDB, double* hsb, double* cdb) {
-  const int i = tid_global();
-  if (i >= m.N) return;
+__device__ __forceinline__ void phi_vjp_c2(const MeshDev& m, int i, int drag, const double* HE, const double* HV,
+                                           const double* CDB, double* hsb, double* cdb) {
   const int n = m.c_nedge[i];
   const double hsb0 = hsb[i];
   const double cdb0 = drag ? cdb[i] : 0.0;
@@ -283,6 +293,16 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_c2(MeshDev m, int drag, cons
   if (drag) cdb[i] = fma(0.5, sc, cdb0);
 }
 
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_ec(MeshDev m, int drag, const double* ZA, const double* HE,
+                                                       const double* HV, const double* CDB, double* ub, double* hsb,
+                                                       double* cdb) {
+  const int t = tid_global();
+  if (t < m.E)
+    phi_vjp_e3(m, t, ZA, ub);
+  else if (t < m.E + m.N)
+    phi_vjp_c2(m, t - m.E, drag, HE, HV, CDB, hsb, cdb);
+}
+
 // ----------------------------------------------------------------- launchers
 static dim3 grid_for(long n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
@@ -305,7 +325,7 @@ void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double*
 
 // Scratch: G, R, HD, CDB, HE, QB (edges), BB (cells), ZA, HV (vertices).
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
-                    const double* P, const double* q, const double* cd, const double* fb, double* ub, double* hsb,
+                    const double* P, const double* cd, const double* fb, double* ub, double* hsb,
                     double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
                     double* ZA, double* HV, hipStream_t st) {
   hipLaunchKernelGGL(k_phi_vjp_e1, grid_for(m.E), dim3(kBlock), 0, st, m, drag, u, P, cd, fb, G, R, HD, CDB, ub);
@@ -313,10 +333,9 @@ void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const doub
   hipLaunchKernelGGL(k_phi_vjp_e2, grid_for(m.E), dim3(kBlock), 0, st, m, linear, drag, u, P, (const double*)G,
                      (const double*)R, (const double*)HD, (const double*)BB, QB, HE, ub);
   if (!linear) {
-    hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(m.V), dim3(kBlock), 0, st, m, hs, q, (const double*)QB, ZA, HV);
-    hipLaunchKernelGGL(k_phi_vjp_e3, grid_for(m.E), dim3(kBlock), 0, st, m, (const double*)ZA, ub);
-    hipLaunchKernelGGL(k_phi_vjp_c2, grid_for(m.N), dim3(kBlock), 0, st, m, drag, (const double*)HE,
-                       (const double*)HV, (const double*)CDB, hsb, cdb);
+    hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(m.V), dim3(kBlock), 0, st, m, u, hs, (const double*)QB, ZA, HV);
+    hipLaunchKernelGGL(k_phi_vjp_ec, grid_for((long)m.E + m.N), dim3(kBlock), 0, st, m, drag, (const double*)ZA,
+                       (const double*)HE, (const double*)HV, (const double*)CDB, ub, hsb, cdb);
   }
 }
 

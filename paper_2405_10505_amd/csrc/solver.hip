@@ -769,7 +769,7 @@ void launch_lincomb(double* y, double b, const double* x0, double a0, const doub
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
                     double* hb, double* T, hipStream_t st);
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
-                    const double* P, const double* q, const double* cd, const double* fb, double* ub, double* hsb,
+                    const double* P, const double* cd, const double* fb, double* ub, double* hsb,
                     double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
                     double* ZA, double* HV, hipStream_t st);
 }  // namespace fblts
@@ -804,7 +804,6 @@ struct Rev {
   double* Ed[kNEdgeArr];
   double* ZA;
   double* HV;
-  double* qf;
   double* P;
   hipStream_t st;
   // Inside a reverse step the elementwise combinations between two tendency
@@ -837,22 +836,15 @@ struct Rev {
   }
   // cotangent fbar of Phi(u, hs) -> ubar (accumulated), hsbar (overwritten), C_D (accumulated)
   void phi_vjp(const double* u, const double* hs, const double* fbar, double* ubar, double* hsbar) {
-    flush();
-    // forward intermediates at the point: q_v and the edge record
-    if (!linear) {
-      Launch<VertSeg> v{};
-      v.nseg = 1;
-      v.seg[0] = VertSeg{*m, 0, 0, V, u, hs, qf};
-      launch_vertex(v, kBlock, st);
-    }
-    Launch<PrepSeg> pp{};
-    pp.nseg = 1;
-    pp.seg[0] = PrepSeg{*m, 0, 0, E, linear ? 1 : 0, u, hs, linear ? m->v_q0 : qf, P};
-    launch_prep(pp, false, kBlock, st);
     zero(hsbar, 0, N);
     flush();
-    launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, linear ? m->v_q0 : qf, cd, fbar, ubar, hsbar,
-                   C[cdb], Ed[Ga], Ed[Ra], Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, st);
+    // forward intermediates at the point: the edge record (q_v evaluated inside)
+    Launch<PrepSeg> pp{};
+    pp.nseg = 1;
+    pp.seg[0] = PrepSeg{*m, 0, 0, E, linear ? 1 : 0, u, hs, linear ? m->v_q0 : nullptr, P};
+    launch_prep(pp, !linear, kBlock, st);
+    launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, cd, fbar, ubar, hsbar, C[cdb], Ed[Ga], Ed[Ra],
+                   Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, st);
   }
   // One reverse step: (hNb, uNb) = cotangent of the step's output -> (hb, ub)
   // = cotangent of its input; C_D's cotangent accumulates.  tc / te: tape.
@@ -2364,7 +2356,6 @@ static Rev make_rev(fblts_solver* s, AdjointState& A) {
   for (int k = 0; k < kNEdgeArr; ++k) r.Ed[k] = A.edges.as<double>() + (size_t)k * r.E;
   r.ZA = A.verts.as<double>();
   r.HV = r.ZA + r.V;
-  r.qf = r.HV + r.V;
   r.P = A.Pf.as<double>();
   r.st = s->stream;
   return r;
@@ -2375,7 +2366,7 @@ static void adj_alloc(fblts_solver* s, AdjointState& A) {
   const size_t N = u.pm.N, E = u.pm.E, V = u.pm.V;
   if (A.cells.bytes < kNCellArr * N * 8) A.cells.alloc(kNCellArr * N * 8);
   if (A.edges.bytes < kNEdgeArr * E * 8) A.edges.alloc(kNEdgeArr * E * 8);
-  if (A.verts.bytes < 3 * V * 8) A.verts.alloc(3 * V * 8);
+  if (A.verts.bytes < 2 * V * 8) A.verts.alloc(2 * V * 8);
   if (A.Pf.bytes < 4 * E * 8) A.Pf.alloc(4 * E * 8);
 }
 
@@ -2390,7 +2381,7 @@ static void build_recording(fblts_solver* s, AdjointState& A) {
   std::vector<Pass> keep = u.passes;
   const double kb = u.bytes_edge;
   const int64_t ki = u.edge_items, kc = u.cell_substeps;
-  build_passes_impl(u, s->P, s->drag_on, false, &A.plan_full);
+  build_passes_impl(u, s->P, s->drag_on, s->opt.fuse_q, &A.plan_full);
   std::vector<Pass> def = u.passes;
   u.passes = keep;
   u.bytes_edge = kb;
