@@ -22,8 +22,10 @@ cited by section / equation label:
 * ``regions`` - the LTS regions of Section 2.2 (fine, interface one/two,
   interior coarse; the interface-adjacent fine layers F^l).
 
-Parity pins: see the module headers.  Parity unpinned: the quadratic drag and
-wind-stress terms (eq. ``hurricane_model``) follow a reading of the paper, and
-only their energy sign and the oracle/GPU agreement are checked.
+Parity pins: see the module headers.  The quadratic drag and wind-stress terms
+(eq. ``hurricane_model``) follow a reading of the paper.  Their vector laws are
+pinned by closed forms for uniform flow (tendencies on the regular hexagon, and
+an inertial oscillation with quadratic drag).  Parity unpinned: the wind drag
+coefficient C_W(|u_W|) and the edge value of a varying C_D.
 """
 from . import trisk, schemes, regions  # noqa: F401

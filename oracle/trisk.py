@@ -27,7 +27,9 @@ linear flow; K = |U|^2/2 and the Coriolis force of a uniform flow on the
 regular hexagonal mesh; curl(grad) = 0; the energy identity
 sum l d F Phi + sum A B Psi = 0; B and F as the gradients of the discrete
 energy; constant-PV compatibility of the vorticity flux; the linear operator's
-energy skew-symmetry.  Drag / wind: parity unpinned (energy sign only).
+energy skew-symmetry; the drag and wind-stress vector laws for uniform flow
+and wind on the regular hexagon, and drag's energy sign.  Parity unpinned: the
+wind drag coefficient C_W(|u_W|) and the edge mean of a varying C_D.
 """
 from __future__ import annotations
 

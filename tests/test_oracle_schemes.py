@@ -238,3 +238,36 @@ def test_predictions_exact_for_constant_tendency(M):
     # M = 1: exact pass-through of the coarse data
     H0, H1, H2, H3 = schemes.predictions(hn, hn + 1.0, hn + 2.0, hn + 3.0, 1, 0)
     assert np.array_equal(H0, hn) and np.array_equal(H1, hn + 1.0) and np.array_equal(H2, hn + 2.0)
+
+
+@pytest.mark.parametrize("scheme", ["fbrk32", "fblts"])
+def test_inertial_oscillation_with_quadratic_drag_closed_form(scheme):
+    """A uniform flow over uniform depth H on the regular hexagon stays uniform,
+    with h = H, and its velocity obeys dV/dt = -f k x V - (C_D / H) |V| V.  In
+    complex form V(t) = V0 exp(-i f t) / (1 + C_D |V0| t / H): the speed decays
+    as the quadratic law fixes and the direction turns at the inertial rate.
+    FB-RK(3,2) and FB-LTS (M = 4, fine band with two interface layers) converge
+    to it at second order."""
+    m = meshgen.hex_periodic(16, 16, 1.0e4, depth=10.0)
+    om = trisk.OMesh(m)
+    H, cd, f, T = 10.0, 2.5e-3, 1e-4, 7200.0
+    U0 = np.array([1.3, -0.6])
+    ph = trisk.Physics(linear=False, cd=np.full(om.N, cd))
+    s = 1.0 / (1.0 + cd / H * np.hypot(*U0) * T)
+    c, sn = math.cos(f * T), math.sin(f * T)
+    V = s * np.array([c * U0[0] + sn * U0[1], -sn * U0[0] + c * U0[1]])
+    mask = np.zeros(om.N, bool)
+    mask[:64] = True
+    lab, _ = regions.layer(om, mask, 2)
+    errs = []
+    for n in (48, 96):
+        dt = T / n
+        u, h = m.normal_edge @ U0, np.full(om.N, H)
+        for _ in range(n):
+            if scheme == "fbrk32":
+                u, h = schemes.fbrk32_step(om, u, h, dt, ph)
+            else:
+                u, h = schemes.fblts_step(om, u, h, dt, 4, ph, lab)
+        errs.append(np.max(np.abs(u - m.normal_edge @ V)) / np.hypot(*U0))
+    assert errs[1] < 2e-5, errs
+    assert 3.4 < errs[0] / errs[1] < 4.6, errs

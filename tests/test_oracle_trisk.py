@@ -106,6 +106,30 @@ def test_hex_uniform_flow_kinetic_energy_and_coriolis(hexm):
         np.testing.assert_allclose(got, expect, atol=1e-12 * f * np.abs(U).max())
 
 
+def test_hex_uniform_flow_drag_and_wind_stress(hexm):
+    """Uniform flow U and uniform wind W over uniform depth h on the hexagon: the
+    quadratic drag adds n_e . (-C_D |U| U / h) to Phi and the wind stress adds
+    n_e . (C_W |W - U| (W - U) / h), the vector laws with the full speeds (the
+    tangential components come from the TRiSK reconstruction, exact for uniform
+    flow here).  C_W(|W|) is the oracle's coefficient law, a reading."""
+    m = hexm
+    om = trisk.OMesh(m)
+    U = np.array([1.3, -0.6])
+    W = np.array([-7.0, 18.0])
+    u = m.normal_edge @ U
+    h = np.full(om.N, 37.0)
+    cd = 2.5e-3
+    base = trisk.phi(om, u, h, trisk.Physics(linear=False))
+    drag = trisk.phi(om, u, h, trisk.Physics(linear=False, cd=np.full(om.N, cd))) - base
+    expect = m.normal_edge @ (-cd * np.hypot(*U) * U / 37.0)
+    np.testing.assert_allclose(drag, expect, rtol=1e-10, atol=1e-13 * np.abs(expect).max())
+    ph = trisk.Physics(linear=False, wind=(m.normal_edge @ W, m.tangent_edge @ W))
+    wind = trisk.phi(om, u, h, ph) - base
+    cw = trisk.wind_drag_coefficient(np.hypot(*W), ph)
+    expect = m.normal_edge @ (cw * np.hypot(*(W - U)) * (W - U) / 37.0)
+    np.testing.assert_allclose(wind, expect, rtol=1e-10, atol=1e-13 * np.abs(expect).max())
+
+
 @pytest.mark.parametrize("meshname", ["hexm", "cvt"])
 def test_curl_of_gradient_vanishes(meshname, request):
     m = request.getfixturevalue(meshname)
@@ -174,7 +198,7 @@ def test_constant_pv_compatibility(meshname, request):
 
 
 def test_drag_removes_energy(cvt):
-    """Quadratic drag contributes sum_e l d F_e (-C_D |u| u / h_e) <= 0 to dE/dt (parity unpinned otherwise)."""
+    """Quadratic drag contributes sum_e l d F_e (-C_D |u| u / h_e) <= 0 to dE/dt."""
     om = trisk.OMesh(cvt)
     u, h = _rand_state(om, 11)
     cd = np.full(om.N, 2.5e-3)
