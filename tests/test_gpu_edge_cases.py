@@ -2,7 +2,8 @@
 an MI355X): many fine substeps (M = 16), thicker interfaces (r = 3), a fine
 set of a single cell, a fine band that wraps around the periodic domain, linear
 physics on the sphere, and a state at rest (steady).  Tolerances as in the main
-parity tests: relative L2 <= 1e-10 after the trajectory, total mass to 1e-13."""
+parity tests: relative L2 <= 1e-10 after the trajectory, total mass to 1e-13.
+A uniform flow with quadratic drag also follows its closed form on the GPU."""
 import numpy as np
 import pytest
 
@@ -96,3 +97,39 @@ def test_rest_state_stays_at_rest():
     h, u = s.get_state()
     assert np.max(np.abs(u)) <= 1e-12
     assert np.max(np.abs(h - w.mesh.bottom_depth)) <= 1e-9
+
+
+def test_inertial_oscillation_with_quadratic_drag_closed_form():
+    """The GPU FB-LTS step on a uniform flow with quadratic drag over uniform
+    depth (regular hexagon, fine band, M = 4) follows the closed form
+    V0 exp(-i f t) / (1 + C_D |V0| t / H) to second order, and matches the
+    oracle on the same run."""
+    import math
+    from paper_2405_10505_amd.inputs import meshgen
+    m = meshgen.hex_periodic(16, 16, 1.0e4, depth=10.0)
+    om = trisk.OMesh(m)
+    H, cd, f, T = 10.0, 2.5e-3, 1e-4, 7200.0
+    U0 = np.array([1.3, -0.6])
+    s_ = 1.0 / (1.0 + cd / H * np.hypot(*U0) * T)
+    c, sn = math.cos(f * T), math.sin(f * T)
+    V = s_ * np.array([c * U0[0] + sn * U0[1], -sn * U0[0] + c * U0[1]])
+    fine = np.zeros(om.N, bool)
+    fine[:64] = True
+    lab, _ = regions.layer(om, fine, 2)
+    fm = F.Mesh(m)
+    errs = []
+    for n in (48, 96):
+        s = F.Solver(fm, T / n, M=4, linear=False)
+        s.set_regions(np.where(fine, 0, 1), binary=True)
+        s.set_drag(np.full(om.N, cd))
+        s.set_state(np.full(om.N, H), m.normal_edge @ U0)
+        s.step(n)
+        hg, ug = s.get_state()
+        errs.append(np.max(np.abs(ug - m.normal_edge @ V)) / np.hypot(*U0))
+    assert errs[1] < 2e-5, errs
+    assert 3.4 < errs[0] / errs[1] < 4.6, errs
+    ph = trisk.Physics(linear=False, cd=np.full(om.N, cd))
+    u, h = m.normal_edge @ U0, np.full(om.N, H)
+    for _ in range(96):
+        u, h = schemes.fblts_step(om, u, h, T / 96, 4, ph, lab)
+    assert rel_l2(hg, h) <= 1e-10 and rel_l2(ug, u) <= 1e-10
