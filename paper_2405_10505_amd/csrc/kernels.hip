@@ -580,17 +580,43 @@ __global__ void __launch_bounds__(kBlock) k_fill(double* dst, double v, long n) 
 // cell energy, edge energy, min h, non-finite count, h <= 0 count.
 constexpr int kDiagQ = 8;
 
+// Reduce over the block the values of lanes with equal (tid % nm), nm a power
+// of two; the results land in sh[0..nm).  A butterfly inside each 64-lane
+// wavefront first (lanes l and l ^ s hold the same member when s >= nm), then
+// the per-wavefront results in wavefront order through LDS.  Fixed order, so
+// the result is deterministic.  Every thread of the block must call it.
 __device__ __forceinline__ void block_reduce(double* sh, double v, int nm, bool is_min) {
-  // sh holds kBlock values; lanes with equal (tid % nm) belong to one member
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int stride = kBlock / 2; stride >= nm; stride >>= 1) {
-    if (threadIdx.x < stride) {
-      const double a = sh[threadIdx.x], c = sh[threadIdx.x + stride];
-      sh[threadIdx.x] = is_min ? fmin(a, c) : a + c;
-    }
+  constexpr int kWaves = kBlock / 64;
+  if (nm >= 64) {
+    // one lane per member in each wavefront: a tree over LDS only
+    sh[threadIdx.x] = v;
     __syncthreads();
+    for (int stride = kBlock / 2; stride >= nm; stride >>= 1) {
+      if (threadIdx.x < stride) {
+        const double a = sh[threadIdx.x], c = sh[threadIdx.x + stride];
+        sh[threadIdx.x] = is_min ? fmin(a, c) : a + c;
+      }
+      __syncthreads();
+    }
+    return;
   }
+  for (int s = 32; s >= nm; s >>= 1) {
+    const double o = __shfl_xor(v, s);
+    v = is_min ? fmin(v, o) : v + o;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane < nm) sh[wave * nm + lane] = v;
+  __syncthreads();
+  if (threadIdx.x < nm) {
+    double r = sh[threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) {
+      const double x = sh[w * nm + threadIdx.x];
+      r = is_min ? fmin(r, x) : r + x;
+    }
+    sh[threadIdx.x] = r;
+  }
+  __syncthreads();
 }
 
 struct DiagArgs {
