@@ -11,6 +11,8 @@
 * Full gradient on a small mesh: every component equals the oracle's gradient
   assembled coordinate by coordinate from complex-step derivatives (1e-10 of
   each block's largest component).
+* Full size (the benchmark's 50k mesh, gauges and drag): directional
+  derivatives against the oracle's complex steps (1e-10 relative).
 """
 import numpy as np
 import pytest
@@ -212,3 +214,34 @@ def test_full_gradient_matches_oracle_elementwise(linear):
         oc = np.array([dloss(dc=unit(om.N, j)) for j in range(om.N)])
         assert np.max(np.abs(oc)) > 0
         np.testing.assert_allclose(gc, oc, rtol=0, atol=1e-10 * np.max(np.abs(oc)))
+
+
+def test_adjoint_fullsize_directional_derivatives():
+    """At the benchmark adjoint's full size: the 50k-cell CVT with drag, the
+    loss over its 50 gauges, the momentum-pass schedule bench.py profiles with
+    graph replay, 4 coarse steps with checkpoints every 3 (a short last
+    segment).  For two random directions in (h0, C_D) the gradient's
+    directional derivative equals the oracle's complex-step derivative of the
+    same run to 1e-10 relative."""
+    from paper_2405_10505_amd import autotune
+    w = workloads.config2()
+    om = trisk.OMesh(w.mesh)
+    lab, _ = regions.layer(om, w.fine_mask, 2)
+    gauges = np.sort(workloads.rng_for(9).choice(np.nonzero(w.fine_mask)[0], size=50, replace=False))
+    s = _solver(F.Mesh(w.mesh), w, w.cd)
+    autotune.apply(s, dict(fuse_vertex=1, block=64, edge_cells=0))
+    s.set_state(w.h0, w.u0)
+    s.adjoint_forward(4, 3)
+    hN, _ = s.get_state()
+    ghN = np.zeros(om.N)
+    ghN[gauges] = 2.0 * (hN[gauges] - om.H[gauges])
+    gh, gu, gc = s.adjoint_backward(ghN, np.zeros(om.E))
+    r = np.random.default_rng(5)
+    eps = 1e-30
+    for k in range(2):
+        vh, vc = r.normal(size=om.N), 1e-4 * r.normal(size=om.N)
+        Lc = _loss_oracle(om, lab, w, w.h0 + 1j * eps * vh, w.u0.astype(complex), w.cd + 1j * eps * vc, 4,
+                          gauges, w.M)
+        dL = Lc.imag / eps
+        dA = gh @ vh + gc @ vc
+        assert abs(dA - dL) <= 1e-10 * abs(dL), (k, dA, dL)
