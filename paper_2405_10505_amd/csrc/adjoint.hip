@@ -12,8 +12,8 @@
 // F_e = h_e u_e.  Momentum tendency (eq. trisk_vorticity with eq.
 // nonlinear_swe and the quadratic drag of eq. hurricane_model):
 // Phi_e = (1/d_e) sum w_{e,e'} (lF)_e' (q_e+q_e')/2 - (B_c1-B_c0)/d_e - C_D |u| u / h_e.
-// Intermediates at the point (q_v, and the edge record (lF, q_e, l u, h_e))
-// come from the forward vertex / prep passes.
+// The edge record at the point (lF, q_e, l u, h_e) comes from the forward prep
+// pass (q_v evaluated inside it); the vertex transpose forms q_v itself.
 #include <hip/hip_runtime.h>
 
 #include "fblts_internal.h"
