@@ -71,7 +71,7 @@ def test_mesh_validation_rejects(hexm, mutate, msg):
     assert msg in str(e.value) or "vertex j" in str(e.value)
 
 
-@pytest.mark.parametrize("name", ["small_cvt", "config1"])
+@pytest.mark.parametrize("name", ["small_cvt", "config1", "small_sphere"])
 def test_plan_ranges_cover_the_regions(name):
     """fblts_plan (host): region counts equal the oracle's layering; the coarse
     advancement covers the coarse region and reaches into the fine region by
