@@ -271,3 +271,33 @@ def test_inertial_oscillation_with_quadratic_drag_closed_form(scheme):
         errs.append(np.max(np.abs(u - m.normal_edge @ V)) / np.hypot(*U0))
     assert errs[1] < 2e-5, errs
     assert 3.4 < errs[0] / errs[1] < 4.6, errs
+
+
+def test_theorems_on_the_sphere_with_a_moving_storm():
+    """Theorems 1 and 2 on the small spherical mesh (f varies with latitude)
+    with quadratic drag and the moving cyclone's wind stress: FB-LTS (M = 4)
+    keeps the total mass to 1e-13 relative and the absolute vorticity to
+    1e-13 of its scale over 10 coarse steps; with the interface left
+    uncorrected the mass drifts."""
+    w = workloads.small_sphere()
+    om = trisk.OMesh(w.mesh)
+    lab, _ = regions.layer(om, w.fine_mask, 2)
+    assert {0, 1, 2} <= set(np.unique(lab).tolist())
+    storm = w.meta["storm"]
+
+    def run(correct):
+        u, h = w.u0.copy(), w.h0.copy()
+        for n in range(10):
+            ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_components(w.mesh, n * w.dt))
+            u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab, correct_interface=correct)
+        return u, h
+
+    ph0 = trisk.Physics(linear=False, cd=w.cd)
+    d0 = trisk.diagnostics(om, w.u0, w.h0, ph0)
+    u, h = run(True)
+    d1 = trisk.diagnostics(om, u, h, ph0)
+    assert abs(d1["mass"] - d0["mass"]) <= 1e-13 * d0["mass"]
+    assert abs(d1["abs_vorticity"] - d0["abs_vorticity"]) <= 1e-13 * d1["abs_vorticity_scale"]
+    u, h = run(False)
+    d2 = trisk.diagnostics(om, u, h, ph0)
+    assert abs(d2["mass"] - d0["mass"]) > 1e-11 * d0["mass"]
