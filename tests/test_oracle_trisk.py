@@ -130,6 +130,28 @@ def test_hex_uniform_flow_drag_and_wind_stress(hexm):
     np.testing.assert_allclose(wind, expect, rtol=1e-10, atol=1e-13 * np.abs(expect).max())
 
 
+def test_hex_uniform_state_diagnostics(hexm):
+    """Uniform flow U over uniform thickness h (flat bottom H) on the regular
+    hexagon, total area A: mass = A h, absolute vorticity = A f (zeta = 0),
+    and the energy of Section 2.5 is A (g h (h/2 - H) + h |U|^2 / 2) in the
+    nonlinear form and A (g (h - H)^2 / 2 + H |U|^2 / 2) in the linear one."""
+    m = hexm
+    om = trisk.OMesh(m)
+    U = np.array([1.3, -0.6])
+    u = m.normal_edge @ U
+    H, hv, g, f = 1000.0, 1000.7, 9.81, 1e-4
+    h = np.full(om.N, hv)
+    A = float(np.sum(om.A))
+    d = trisk.diagnostics(om, u, h, trisk.Physics(linear=False, g=g))
+    assert abs(d["mass"] - A * hv) <= 1e-13 * A * hv
+    assert abs(d["abs_vorticity"] - A * f) <= 1e-12 * A * f
+    e = A * (g * hv * (0.5 * hv - H) + 0.5 * hv * (U @ U))
+    assert abs(d["energy"] - e) <= 1e-11 * abs(e)
+    d = trisk.diagnostics(om, u, h, trisk.Physics(linear=True, g=g))
+    e = A * (0.5 * g * (hv - H) ** 2 + 0.5 * H * (U @ U))
+    assert abs(d["energy"] - e) <= 1e-11 * abs(e)
+
+
 @pytest.mark.parametrize("meshname", ["hexm", "cvt"])
 def test_curl_of_gradient_vanishes(meshname, request):
     m = request.getfixturevalue(meshname)
