@@ -11,14 +11,16 @@ resident in HBM.
 value = cell-substeps/s = (N_coarse + M N_fine) * steps / wall time.
 Also reported: the momentum (edge) pass against the HBM roofline, the
 time-to-solution of global FB-RK(3,2) and RK4 at their own largest stable
-steps (the paper's speedup definition), and the oracle timed on the host.
+steps (the paper's speedup definition), and the oracle timed on the host
+(one thread, then one process per host core up to 16).
 
 Other workloads: sphere400k (the ~400k-cell spherical coastline-refined CVT,
 6 -> 60 km, bathymetry field, drag and a moving analytic cyclone, M = 8; by
-default two simulated days), hex32, ensemble, adjoint.
+default two simulated days), hex32, ensemble, adjoint, aquaplanet.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload cvt50k|sphere400k|hex32|ensemble|adjoint]
+                       [--workload cvt50k|sphere400k|hex32|ensemble|adjoint|aquaplanet]
+                       [--split 0|1|2] [--schedule F,B[,C]] [--profile-steps N] [--no-cpu] [--no-compare]
 """
 import argparse
 import hashlib
