@@ -581,7 +581,7 @@ def bench_adjoint(args):
 
 
 def bench_aquaplanet(args):
-    """The paper's temporal-convergence experiment (Section 2.4) at a larger size:
+    """The paper's temporal-convergence experiment (Section 2.3) at a larger size:
     external gravity wave on a non-rotating, constant-depth aquaplanet (spherical
     coastline-refined CVT, ~40k cells, 25 -> 200 km), FB-LTS with M = 4 at coarse
     steps dt, dt/2, dt/4, dt/8 against RK4 at 10 s over 4 simulated hours; RMS

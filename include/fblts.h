@@ -17,7 +17,7 @@
  *   - FB-LTS: Section 2.2 (regions F, IF-1, IF-2, interior coarse; coarse
  *     advancement, interface prediction eq. preds, fine advancement eq.
  *     fine_fbrk32, interface correction eq. if_correction);
- *   - conserved quantities: Section 2.5, Theorems 1 and 2.
+ *   - conserved quantities: Section 2.4, Theorems 1 and 2.
  *
  * Conventions shared by every call:
  *   - Every function returns an int status (FBLTS_OK = 0, negative on error);
@@ -58,7 +58,7 @@ enum { FBLTS_SCHEME_FBLTS = 0, FBLTS_SCHEME_FBRK32 = 1, FBLTS_SCHEME_RK4 = 2 };
 /* Physics: LINEAR = TRiSK linearised about rest; NONLINEAR = eq. nonlinear_swe
  * with optional drag and wind stress (eq. hurricane_model); GRAVITY_WAVE = the
  * fast terms only (eq. fast_terms: Psi = -div(h u), Phi = -g grad(h + z_b)),
- * the external gravity-wave system of Section 2.4 (eq. grav_wave_model). */
+ * the external gravity-wave system of Section 2.3 (eq. grav_wave_model). */
 enum { FBLTS_PHYS_LINEAR = 0, FBLTS_PHYS_NONLINEAR = 1, FBLTS_PHYS_GRAVITY_WAVE = 2 };
 /* Operator splitting of the momentum equation (Section 3.2, eq. splitting):
  * NONE = unsplit; COARSE = slow terms (everything in Phi but the pressure
@@ -80,7 +80,7 @@ int fblts_version(void);
 
 /* MPAS-style Voronoi C-grid, caller numbering, 0-based, host pointers.
  *   cells_on_edge[2E]      (c0,c1) per edge; the normal n_e points c0 -> c1,
- *                          so n_{e,c0} = +1, n_{e,c1} = -1 (Sec 2.5).
+ *                          so n_{e,c0} = +1, n_{e,c1} = -1 (Sec 2.4).
  *   vertices_on_edge[2E]   (v0,v1); the tangent t_e = k x n_e points v0 -> v1.
  *   edges_on_cell (CSR)    counter-clockwise; vertices_on_cell (CSR, same
  *                          offsets): vertex j lies between edge j and j+1.

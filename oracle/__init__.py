@@ -14,7 +14,7 @@ cited by section / equation label:
 * ``trisk``   - TRiSK thickness tendency (eq. ``trisk_thickness``), momentum
   tendency in vorticity-flux form (eq. ``trisk_vorticity``, eq.
   ``nonlinear_swe``; drag and wind stress of eq. ``hurricane_model``),
-  diagnostics of Section 2.5.
+  diagnostics of Section 2.4.
 * ``schemes`` - FB-RK(3,2) (eq. ``fbrk32``), RK4, RK(3,2), and the FB-LTS
   step of Section 2.2 (coarse advancement, interface prediction eq. ``preds``,
   fine advancement eq. ``fine_fbrk32``, interface correction eq.

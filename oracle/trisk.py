@@ -134,7 +134,7 @@ class Physics:
 
     ``gravity_wave=True`` keeps only the fast terms of eq. ``fast_terms``
     (Section 3.2): Psi = -div(h u) and Phi = -g grad(h + z_b) with
-    z_b = -H; the system of eq. ``grav_wave_model`` (Section 2.4).
+    z_b = -H; the system of eq. ``grav_wave_model`` (Section 2.3).
     """
 
     def __init__(self, linear=False, g=9.81, cd=None, wind=None, rho_air=1.15, rho_w=1000.0,
@@ -227,7 +227,7 @@ def wind_drag_coefficient(speed, ph):
 
 
 # ----------------------------------------------------------------------------
-# diagnostics (Section 2.5: discrete mass and absolute vorticity)
+# diagnostics (Section 2.4: discrete mass and absolute vorticity)
 # ----------------------------------------------------------------------------
 
 def neumaier_sum(x):

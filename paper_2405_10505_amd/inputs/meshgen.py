@@ -10,7 +10,7 @@ Conventions (all 0-based):
 
 * ``cells_on_edge[e] = (c0, c1)``; the unit normal ``n_e`` points c0 -> c1, so
   the outward sign of edge e for cell i is ``n_{e,i} = +1`` for c0 and -1 for
-  c1 (paper, Section 2.3, the sign ``n_{e,i}`` in the mass-conservation proof).
+  c1 (paper, Section 2.4, the sign ``n_{e,i}`` in the mass-conservation proof).
 * ``t_e = k x n_e``; ``vertices_on_edge[e] = (v0, v1)`` with t_e pointing
   v0 -> v1.  Traversing the dual edge c0 -> c1 is counter-clockwise about v1.
 * Cells list their edges and vertices counter-clockwise; vertex j of a cell

@@ -351,7 +351,7 @@ def small_sphere(n=3000, M=4, iters=20):
 def aquaplanet(n=2000, M=4, depth=1000.0, amp=1.0, width=600e3, seed=9, iters=20,
                dx_fine=100e3, dx_coarse=800e3):
     """Non-rotating aquaplanet at rest with constant depth and a Gaussian SSH bump
-    (Section 2.4): the coastline-refined spherical CVT with f = 0 everywhere, the
+    (Section 2.3): the coastline-refined spherical CVT with f = 0 everywhere, the
     fine set from the local CFL number, the external gravity-wave system."""
     base = sphere_mesh(n, 5, iters, dx_fine, dx_coarse)
     mesh = base.copy_with(f_vertex=np.zeros(base.n_vertices), f_edge=np.zeros(base.n_edges),

@@ -186,7 +186,7 @@ def test_graph_replay_bitwise_fast_modes(cvt, kw):
 
 
 def test_aquaplanet_convergence_on_gpu(aqua):
-    """Section 2.4's experiment on the device: FB-LTS (M = 4) errors against RK4
+    """Section 2.3's experiment on the device: FB-LTS (M = 4) errors against RK4
     at dt = 10 s, for coarse steps dt, dt/2, dt/4; the same figures as the oracle's."""
     w, om, lab, fm = aqua
     T = 4 * 3600.0

@@ -88,7 +88,7 @@ def test_temporal_order_against_exact_solution(c1, exact_c1, scheme, order):
         step = lambda u, h, dt: schemes.fblts_step(om, u, h, dt, M, ph, lab)
     err = _errors(w, om, step, [60.0, 30.0, 15.0], T, yT, lab)
     slopes = np.log2(err[:-1] / err[1:])
-    # h (all cells), u (all edges), h on interface cells: paper Section 2.4 (second order everywhere)
+    # h (all cells), u (all edges), h on interface cells: paper Section 2.3 (second order everywhere)
     assert np.all(slopes[-1] > order - 0.1), slopes
     assert np.all(slopes[-1] < order + 0.2), slopes
 

@@ -1,12 +1,12 @@
 """Pins of the operator splitting (Section 3.2), its per-substep variant
-(Section 4.2) and the gravity-wave system (Section 2.4) in the oracle (CPU).
+(Section 4.2) and the gravity-wave system (Section 2.3) in the oracle (CPU).
 
 Independent references:
   * the splitting is a decomposition of Phi: fast + slow equals the full
     tendency of the pinned TRiSK operators;
   * order of accuracy: the paper states that the splitting introduces a
     first-order error (Section 3.2) and that FB-LTS without slow terms is
-    second order (Section 2.4); measured against an RK4 reference at a small
+    second order (Section 2.3); measured against an RK4 reference at a small
     step on a rotating problem (split: order 1) and on the non-rotating
     aquaplanet gravity wave (FB-LTS: order 2, the paper's own experiment);
   * reductions that follow from the definitions: M = 1 and an all-coarse
@@ -144,7 +144,7 @@ def test_split_conserves_mass_and_absolute_vorticity(cvt_small, split):
 
 
 def test_aquaplanet_gravity_wave_fblts_second_order():
-    """Section 2.4: FB-LTS (M = 4) on the non-rotating aquaplanet gravity wave,
+    """Section 2.3: FB-LTS (M = 4) on the non-rotating aquaplanet gravity wave,
     errors against RK4 at dt = 10 s, coarse steps dt, dt/2, dt/4."""
     w = workloads.aquaplanet()
     om = trisk.OMesh(w.mesh)

@@ -133,7 +133,7 @@ def test_hex_uniform_flow_drag_and_wind_stress(hexm):
 def test_hex_uniform_state_diagnostics(hexm):
     """Uniform flow U over uniform thickness h (flat bottom H) on the regular
     hexagon, total area A: mass = A h, absolute vorticity = A f (zeta = 0),
-    and the energy of Section 2.5 is A (g h (h/2 - H) + h |U|^2 / 2) in the
+    and the energy of Section 2.4 is A (g h (h/2 - H) + h |U|^2 / 2) in the
     nonlinear form and A (g (h - H)^2 / 2 + H |U|^2 / 2) in the linear one."""
     m = hexm
     om = trisk.OMesh(m)
