@@ -346,9 +346,22 @@ int fblts_time_kernels(fblts_solver* s, int32_t kernel_class, int32_t repeats, d
  * with gather-only transposed kernels (deterministic, no atomics).  The
  * solver is left at the final state.  Device memory: about
  * ckpt_every * ((4+4M) n_cells + (4+3M) n_edges) doubles of tape.
- * Errors: FBLTS_ESTATE without a preceding forward, FBLTS_EINVAL for other
- * schemes or when wind stress is set.  Synchronises. */
+ * One forward run serves any number of backward calls (several cotangents)
+ * as long as nothing changes the trajectory in between: fblts_set_regions,
+ * fblts_set_state, fblts_set_drag, fblts_set_wind, fblts_set_cyclone,
+ * fblts_step, fblts_autotune (which steps) and another fblts_adjoint_forward
+ * each invalidate the recording.
+ * Errors: FBLTS_ESTATE without a preceding forward or after such a call (the
+ * checkpoints, drag and final state would belong to another trajectory),
+ * FBLTS_EINVAL for other schemes or when wind stress is set.  Synchronises. */
 int fblts_adjoint_forward(fblts_solver* s, int32_t n_steps, int32_t ckpt_every);
+/* The identity of the solver's current adjoint recording: *id > 0 names the
+ * recording the last fblts_adjoint_forward made while it is still valid
+ * (nothing above has invalidated it), *id = 0 when there is none.  A caller
+ * that records several runs on one solver (a chain of applications) keeps
+ * the id of each and records a run again when the id no longer matches.
+ * Host only (no device work).  Errors: FBLTS_EINVAL (NULL argument). */
+int fblts_adjoint_recording(fblts_solver* s, uint64_t* id);
 int fblts_adjoint_backward(fblts_solver* s, const double* gh_final, const double* gu_final, double* gh0,
                            double* gu0, double* gcd, int32_t on_device);
 /* Test export: transposed tendency at the point (h, u) (host arrays, caller

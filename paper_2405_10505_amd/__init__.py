@@ -118,6 +118,7 @@ _SIGS = {
     "fblts_time_kernels": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64)]),
     "fblts_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "fblts_adjoint_recording": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "fblts_adjoint_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_int32]),
     "fblts_debug_vjp": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -411,6 +412,12 @@ class Solver:
     def adjoint_forward(self, n_steps, ckpt_every):
         _check(lib().fblts_adjoint_forward(self.handle, int(n_steps), int(ckpt_every)))
 
+    def adjoint_recording(self):
+        """Identity of the current valid adjoint recording (0: none)."""
+        v = C.c_uint64(0)
+        _check(lib().fblts_adjoint_recording(self.handle, C.byref(v)))
+        return v.value
+
     def adjoint_backward(self, gh_final, gu_final, out=None):
         """Gradients (gh0, gu0, gcd) from the final-state cotangent.
 
@@ -544,13 +551,20 @@ def fblts_function():
     class FBLTSSteps(torch.autograd.Function):
         @staticmethod
         def forward(ctx, h0, u0, cd, solver, n_steps, ckpt_every):
-            solver.set_drag(cd.detach().contiguous())
-            solver.set_state(h0.detach().contiguous(), u0.detach().contiguous())
+            ins = (h0.detach().contiguous(), u0.detach().contiguous(), cd.detach().contiguous())
+            solver.set_drag(ins[2])
+            solver.set_state(ins[0], ins[1])
             solver.adjoint_forward(n_steps, ckpt_every)
             hN = torch.empty_like(h0)
             uN = torch.empty_like(u0)
             solver.get_state(hN, uN)
             ctx.solver = solver
+            ctx.rec = solver.adjoint_recording()
+            ctx.run = (n_steps, ckpt_every)
+            # the inputs are kept (autograd checks that they are not modified
+            # in place) to record this call again if a later use of the solver
+            # replaced its recording
+            ctx.save_for_backward(h0, u0, cd)
             ctx.shapes = (h0.shape, u0.shape, h0.device)
             return hN, uN
 
@@ -561,7 +575,16 @@ def fblts_function():
                 ghN = torch.zeros(hs, dtype=torch.float64, device=dev)
             if guN is None:
                 guN = torch.zeros(us, dtype=torch.float64, device=dev)
-            gh0, gu0, gcd = ctx.solver.adjoint_backward(ghN.contiguous(), guN.contiguous())
+            s = ctx.solver
+            if s.adjoint_recording() != ctx.rec:
+                # the solver recorded or ran something else since this call's
+                # forward (a chain of applications on one solver): record this
+                # call's run again
+                h0, u0, cd = (t.detach().contiguous() for t in ctx.saved_tensors)
+                s.set_drag(cd)
+                s.set_state(h0, u0)
+                s.adjoint_forward(*ctx.run)
+            gh0, gu0, gcd = s.adjoint_backward(ghN.contiguous(), guN.contiguous())
             return gh0, gu0, gcd, None, None, None
 
     return FBLTSSteps

@@ -784,6 +784,7 @@ enum EdgeArr { uNb, ub, u1b, u2b, u3b, U0b, U1b, U2b, U3Fb, aub, fb, Ta, Ga, Ra,
 struct AdjointState {
   int n_steps = 0, ckpt_every = 0, M = 0;
   bool recorded = false;
+  uint64_t gen = 0;   // the solver's generation the recording belongs to
   Plan plan_full;
   size_t tape_c = 0, tape_e = 0;   // doubles per step of the cell / edge tape
   DevBuf ckpt, final_state, step_tape, seg_tape;
@@ -1066,6 +1067,10 @@ struct fblts_solver {
   DevBuf dbg_h, dbg_u, dbg_out;
   double time = 0.0;
   int64_t step = 0;
+  // Generation: advanced by every call that changes the trajectory (regions,
+  // state, drag, wind, storm, steps).  An adjoint recording is valid only for
+  // the generation it ended in.
+  uint64_t gen = 0;
   std::unique_ptr<AdjointState> adj;
   ~fblts_solver() {
     drop_graph();
@@ -1210,6 +1215,7 @@ static void solver_run(fblts_solver* s, int n) {
   }
   s->step += n;
   s->time += n * s->P.p.dt;
+  ++s->gen;
 }
 
 static void ensemble_run(fblts_ensemble* e, int n) {
@@ -1494,6 +1500,7 @@ int fblts_set_regions(fblts_solver* s, const int8_t* labels, int32_t binary) {
     if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->drop_graph();
+    ++s->gen;
     s->have_regions = false;
     s->have_state = false;
     auto u = std::make_unique<MeshUnit>();
@@ -1511,6 +1518,7 @@ int fblts_set_state(fblts_solver* s, const double* h, const double* u, int32_t o
     if (!s || !h || !u) throw Err(FBLTS_EINVAL, "NULL argument");
     if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
     if (on_device) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    ++s->gen;
     MeshUnit& un = *s->unit;
     state_in(un, s->stage_h, s->stage_u, h, u, 0, on_device != 0, s->stream);
     init_scratch(un, s->stream);
@@ -1544,6 +1552,7 @@ int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device) {
     MeshUnit& u = *s->unit;
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->drop_graph();
+    ++s->gen;
     if (!cd) {
       s->drag_on = false;
     } else {
@@ -1571,6 +1580,7 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
     MeshUnit& u = *s->unit;
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->drop_graph();
+    ++s->gen;
     u.st.cyclone = false;
     if (!wn || !wt) {
       u.st.has_wind = false;
@@ -1706,6 +1716,7 @@ int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_e
     MeshUnit& u = *s->unit;
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->drop_graph();
+    ++s->gen;
     if (!c) {
       u.st.cyclone = false;
       u.st.has_wind = false;
@@ -2449,6 +2460,7 @@ int fblts_adjoint_forward(fblts_solver* s, int32_t n_steps, int32_t ckpt_every) 
     AdjointState& A = *s->adj;
     MeshUnit& u = *s->unit;
     const int N = u.pm.N, E = u.pm.E;
+    A.recorded = false;
     A.n_steps = n_steps;
     A.ckpt_every = ckpt_every;
     A.M = s->P.p.M;
@@ -2468,7 +2480,16 @@ int fblts_adjoint_forward(fblts_solver* s, int32_t n_steps, int32_t ckpt_every) 
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->step += n_steps;
     s->time += n_steps * s->P.p.dt;
+    A.gen = ++s->gen;
     A.recorded = true;
+    return FBLTS_OK;
+  });
+}
+
+int fblts_adjoint_recording(fblts_solver* s, uint64_t* id) {
+  return guarded([&] {
+    if (!s || !id) throw Err(FBLTS_EINVAL, "NULL argument");
+    *id = (s->adj && s->adj->recorded && s->adj->gen == s->gen) ? s->adj->gen : 0;
     return FBLTS_OK;
   });
 }
@@ -2478,6 +2499,9 @@ int fblts_adjoint_backward(fblts_solver* s, const double* gh_final, const double
   return guarded([&] {
     adj_check(s);
     if (!s->adj || !s->adj->recorded) throw Err(FBLTS_ESTATE, "fblts_adjoint_forward must come first");
+    if (s->adj->gen != s->gen)
+      throw Err(FBLTS_ESTATE, "the solver's regions, state, forcing or step count changed after "
+                              "fblts_adjoint_forward: record the forward run again");
     if (!gh_final || !gu_final) throw Err(FBLTS_EINVAL, "NULL seed");
     AdjointState& A = *s->adj;
     MeshUnit& u = *s->unit;

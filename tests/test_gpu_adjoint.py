@@ -156,6 +156,68 @@ def test_autograd_function(cvt):
     assert np.array_equal(h0.grad.cpu().numpy(), gh) and np.array_equal(cd.grad.cpu().numpy(), gc)
 
 
+def test_recording_invalidated_by_later_calls(cvt):
+    """A backward call after anything that changes the trajectory (new state,
+    drag, steps, another forward) is refused instead of sweeping another
+    run's checkpoints; several backward calls on one recording agree."""
+    w, om, lab, fm = cvt
+    cd = np.full(om.N, 2.5e-3)
+    s = _solver(fm, w, cd)
+    s.set_state(w.h0, w.u0 + 0.01)
+    assert s.adjoint_recording() == 0
+    s.adjoint_forward(3, 2)
+    rec = s.adjoint_recording()
+    assert rec > 0
+    hN, uN = s.get_state()
+    g1 = s.adjoint_backward(2 * (hN - om.H), 2 * uN)
+    assert s.adjoint_recording() == rec
+    g2 = s.adjoint_backward(2 * (hN - om.H), 2 * uN)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+    for change in (lambda: s.set_state(w.h0, w.u0), lambda: s.set_drag(cd), lambda: s.step(1)):
+        s.set_state(w.h0, w.u0 + 0.01)
+        s.adjoint_forward(3, 2)
+        assert s.adjoint_recording() not in (0, rec)
+        change()
+        assert s.adjoint_recording() == 0
+        with pytest.raises(F.FBLTSError) as ei:
+            s.adjoint_backward(2 * (hN - om.H), 2 * uN)
+        assert ei.value.code == F.FBLTS_ESTATE
+
+
+def test_autograd_chained_applications_on_one_solver(cvt):
+    """Two applications on one solver, the second starting from the first's
+    output: the gradient with respect to the first input equals the oracle's
+    complex-step derivative through both runs (the first call's backward
+    records its run again, since the second replaced the recording)."""
+    torch = pytest.importorskip("torch")
+    w, om, lab, fm = cvt
+    cd_np = np.full(om.N, 2.5e-3)
+    s = _solver(fm, w, cd_np)
+    fn = F.fblts_function()
+    r = np.random.default_rng(31)
+    u0_np = w.u0 + 0.02 * r.normal(size=om.E)
+    gauges = np.sort(r.choice(np.nonzero(w.fine_mask)[0], size=20, replace=False))
+    h0 = torch.tensor(w.h0, device="cuda", requires_grad=True)
+    u0 = torch.tensor(u0_np, device="cuda", requires_grad=True)
+    cd = torch.tensor(cd_np, device="cuda", requires_grad=True)
+    h1, u1 = fn.apply(h0, u0, cd, s, 3, 2)
+    h2, u2 = fn.apply(h1, u1, cd, s, 2, 2)
+    g = torch.tensor(gauges, device="cuda")
+    Ht = torch.tensor(om.H, device="cuda")
+    loss = ((h2[g] - Ht[g]) ** 2).sum()
+    loss.backward()
+    eps = 1e-30
+    for k in range(2):
+        vh, vu = r.normal(size=om.N), 1e-3 * r.normal(size=om.E)
+        vc = 1e-4 * r.normal(size=om.N)
+        Lc = _loss_oracle(om, lab, w, w.h0 + 1j * eps * vh, u0_np + 1j * eps * vu, cd_np + 1j * eps * vc, 5,
+                          gauges, w.M)
+        dL = Lc.imag / eps
+        dA = h0.grad.cpu().numpy() @ vh + u0.grad.cpu().numpy() @ vu + cd.grad.cpu().numpy() @ vc
+        assert abs(dA - dL) <= 1e-10 * abs(dL), (k, dA, dL)
+
+
 @pytest.mark.parametrize("linear", [False, True])
 def test_full_gradient_matches_oracle_elementwise(linear):
     """Every component of the gradient, element by element.  On a 12 x 12
