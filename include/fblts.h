@@ -297,9 +297,18 @@ typedef struct {
   int32_t max_edges, max_eoe;
   int64_t cell_substeps_per_step;   /* N_coarse + M N_fine (global schemes: N) */
   int64_t launches_per_step;
-  double model_bytes_per_step;      /* algorithmic byte model of all launched passes */
-  double model_bytes_edge_pass;     /* of the momentum (edge) passes only */
+  /* Two byte models per coarse step, each counting every referenced array
+   * element once per launch.  The per-pass model includes the intermediates
+   * the passes exchange through memory (h*, B, q_v, the edge-prep records);
+   * the compulsory model counts only mesh and state arrays (h, u and their
+   * stage copies, accumulators, drag, wind), as any implementation must. */
+  double model_bytes_per_step;      /* per-pass model, all launched passes */
+  double model_bytes_edge_pass;     /* per-pass model, momentum (edge) passes */
   int64_t edge_pass_items_per_step; /* edges processed by momentum passes per step */
+  double model_bytes_cell_pass;     /* per-pass model, thickness (cell) passes */
+  double compulsory_bytes_per_step; /* compulsory model, all launched passes */
+  double compulsory_bytes_edge_pass;/* compulsory model, momentum passes */
+  double compulsory_bytes_cell_pass;/* compulsory model, thickness passes */
 } fblts_info;
 int fblts_get_info(fblts_solver* s, fblts_info* out);
 

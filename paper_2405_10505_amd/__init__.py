@@ -82,7 +82,9 @@ class fblts_info(C.Structure):
                                          "n_fine_e", "n_if1_e", "n_if2_e", "n_int_e", "max_edges", "max_eoe")] + \
                [("cell_substeps_per_step", C.c_int64), ("launches_per_step", C.c_int64),
                 ("model_bytes_per_step", C.c_double), ("model_bytes_edge_pass", C.c_double),
-                ("edge_pass_items_per_step", C.c_int64)]
+                ("edge_pass_items_per_step", C.c_int64), ("model_bytes_cell_pass", C.c_double),
+                ("compulsory_bytes_per_step", C.c_double), ("compulsory_bytes_edge_pass", C.c_double),
+                ("compulsory_bytes_cell_pass", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -950,4 +950,99 @@ double bytes_edge_fast_pass(const PermMesh& pm, const StageRanges& r, bool slow,
   return b;
 }
 
+// ------------------------------------------------- compulsory byte model
+
+double compulsory_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm, bool ke) {
+  const double S = 8.0 * nm;
+  double b = 0;
+  Stamp se(pm.E), sc(pm.N);
+  se.next();
+  sc.next();
+  for (int i = r.cell.b; i < r.cell.e; ++i) sc.mark(i);
+  for (int i = r.cell.b; i < r.cell.e; ++i) {
+    const bool upd = i >= r.cell_upd.b && i < r.cell_upd.e;
+    const bool acc = i >= r.cell_acc.b && i < r.cell_acc.e;
+    const bool psi = upd || acc;
+    const int n = pm.c_nedge[i];
+    b += 4 + 8 + 8;                                // degree, 1/A, resting depth
+    if (nonlinear || psi) b += 4.0 * n;            // edges (with their orientation signs)
+    if (psi && nonlinear) b += 4.0 * n;            // neighbour cells
+    b += 3 * S;                                    // h of the stage, h^n, the new h (read or written)
+    if (acc) b += 2 * S;
+    for (int j = 0; j < n; ++j) {
+      const int e = pm.c_edge[(size_t)j * pm.cs + i] >> 1;
+      if ((nonlinear || psi) && se.mark(e)) b += S + 8 + ((nonlinear && !ke) ? 0 : 8);  // u, l, d (or H_e)
+      if (psi && nonlinear) {
+        const int nb = pm.c_nbr[(size_t)j * pm.cs + i];
+        if (sc.mark(nb)) b += S;                   // neighbour h
+      }
+    }
+  }
+  return b;
+}
+
+double compulsory_vert_pass(const PermMesh& pm, const Range& r, int nm) {
+  const double S = 8.0 * nm;
+  double b = 0;
+  Stamp se(pm.E);
+  se.next();
+  for (int v = r.b; v < r.e; ++v) {
+    b += 3 * (4 + 4 + 8) + 8 + 8;   // edges, cells, kites, 1/A_v, f_v
+    for (int j = 0; j < 3; ++j)
+      if (se.mark(pm.v_edge[(size_t)j * pm.vs + v] >> 1)) b += 8 + S;   // d_e, u
+  }
+  return b;
+}
+
+double compulsory_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm) {
+  const double S = 8.0 * nm;
+  double b = 0;
+  for (int e = r.b; e < r.e; ++e) {
+    b += 8 + 8 + 8 + S;             // cells, vertices, l_e, u
+    if (!nonlinear) b += 8;         // H_e
+  }
+  return b;
+}
+
+double compulsory_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm) {
+  const double S = 8.0 * nm;
+  const bool tang = drag || wind;   // the tangential velocity reads the neighbours' u
+  double b = 0;
+  Stamp se(pm.E), sc(pm.N);
+  se.next();
+  sc.next();
+  for (int e = r.edge.b; e < r.edge.e; ++e) {
+    const int n = pm.e_neoe[e];
+    b += 4 + n * (4.0 + 8.0) + 8 + 8;       // count, edges_on_edge, weights, cells, 1/d_e
+    const bool upd = e >= r.edge_upd.b && e < r.edge_upd.e;
+    const bool acc = e >= r.edge_acc.b && e < r.edge_acc.e;
+    if (upd) b += 2 * S;                     // u^n, the new u
+    if (acc) b += 2 * S;
+    if (wind) b += 16;
+    if (tang) {
+      if (se.mark(e)) b += S;                // u of the edge
+      for (int j = 0; j < n; ++j)
+        if (se.mark(pm.e_eoe[(size_t)j * pm.es + e])) b += S;
+    }
+    if (drag || wind)
+      for (int j = 0; j < 2; ++j)
+        if (sc.mark(pm.e_cell[(size_t)j * pm.es + e])) b += S + (drag ? S : 0);   // h (+ C_D) of the cells
+  }
+  return b;
+}
+
+double compulsory_edge_fast_pass(const PermMesh& pm, const StageRanges& r, bool slow, int nm) {
+  const double S = 8.0 * nm;
+  double b = 0;
+  for (int e = r.edge.b; e < r.edge.e; ++e) {
+    b += 8 + 8;                              // cells, 1/d_e
+    const bool upd = e >= r.edge_upd.b && e < r.edge_upd.e;
+    const bool acc = e >= r.edge_acc.b && e < r.edge_acc.e;
+    if (upd) b += 2 * S;
+    if (acc) b += 2 * S;
+    if (slow) b += S;                        // the frozen slow tendency (state of the split scheme)
+  }
+  return b;
+}
+
 }  // namespace fblts

@@ -81,9 +81,10 @@ struct PermMesh {
 };
 void permute_mesh(const HostMesh& m, const Plan& p, PermMesh& pm);
 
-// Algorithmic (compulsory) bytes of each pass kind over a range: every mesh
-// array element and state element the pass's mathematics references, once.
-// nm = members; state bytes scale with nm, mesh bytes do not.
+// Per-pass byte model of each pass kind over a range: every mesh array
+// element, state element and intermediate (h*, B, q_v, the edge-prep records)
+// the pass reads or writes, each once per launch.  nm = members; state and
+// intermediate bytes scale with nm, mesh bytes do not.
 double bytes_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm, bool ke = true);
 double bytes_vert_pass(const PermMesh& pm, const Range& r, int nm);
 double bytes_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm, bool fuse_q = false);
@@ -92,5 +93,18 @@ double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool
 double bytes_edge_cells_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm);
 // fast momentum pass of the operator splitting (pressure gradient + frozen slow tendency)
 double bytes_edge_fast_pass(const PermMesh& pm, const StageRanges& r, bool slow, int nm);
+
+// Compulsory (algorithmic) bytes of each pass kind: the mesh arrays and the
+// state arrays (h, u, their stage and time-level copies, accumulators, drag
+// and wind) that the pass's mathematics references, each element once per
+// launch; intermediates that a pass could keep on chip -- the thickness flux,
+// q, K, B, h* and the edge-prep records -- cost nothing in either direction.
+// The momentum pass through the cells' edge lists computes the same
+// mathematics and has the same compulsory bytes as compulsory_edge_pass.
+double compulsory_cell_pass(const PermMesh& pm, const StageRanges& r, bool nonlinear, int nm, bool ke = true);
+double compulsory_vert_pass(const PermMesh& pm, const Range& r, int nm);
+double compulsory_prep_pass(const PermMesh& pm, const Range& r, bool nonlinear, int nm);
+double compulsory_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool wind, int nm);
+double compulsory_edge_fast_pass(const PermMesh& pm, const StageRanges& r, bool slow, int nm);
 
 }  // namespace fblts

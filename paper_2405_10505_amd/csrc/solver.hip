@@ -270,7 +270,8 @@ struct Pass {
   // RK4 final: per segment (y, acc, n)
   std::vector<std::tuple<double*, const double*, long>> fin;
   double fin_c = 0.0;
-  double model_bytes = 0.0;
+  double model_bytes = 0.0;   // per-pass model (intermediates included)
+  double comp_bytes = 0.0;    // compulsory model (intermediates free)
   bool fuse_q = false;   // PREP: evaluate q_v in the prep pass (no vertex pass)
   int cell_mode = 1;     // CELL: 0 linear, 1 nonlinear, 2 fast terms (k_cell<MODE>)
   bool edge_fast = false;   // EDGE: fast momentum pass (k_edge_fast)
@@ -289,7 +290,8 @@ struct MeshUnit {
   DevState st;
   std::vector<Pass> passes;
   int64_t cell_substeps = 0;
-  double bytes_edge = 0.0;
+  double bytes_edge = 0.0, bytes_cell = 0.0;   // per-pass model of the momentum / thickness passes
+  double comp_edge = 0.0, comp_cell = 0.0;     // compulsory model of the same passes
   int64_t edge_items = 0;
 };
 
@@ -340,6 +342,9 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
   u.passes.clear();
   int cur_tag = 0;
   u.bytes_edge = 0;
+  u.bytes_cell = 0;
+  u.comp_edge = 0;
+  u.comp_cell = 0;
   u.edge_items = 0;
   const int nm = s.nm;
 
@@ -379,6 +384,9 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     c.acc_w = acc_w;
     c.g = g;
     ps.model_bytes = bytes_cell_pass(u.pm, r, mode != 0, nm, mode == 1);
+    ps.comp_bytes = compulsory_cell_pass(u.pm, r, mode != 0, nm, mode == 1);
+    u.bytes_cell += ps.model_bytes;
+    u.comp_cell += ps.comp_bytes;
     ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
@@ -396,6 +404,7 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     v.hs = s.hs.as<double>();
     v.q = s.q.as<double>();
     ps.model_bytes = bytes_vert_pass(u.pm, r.vert, nm);
+    ps.comp_bytes = compulsory_vert_pass(u.pm, r.vert, nm);
     ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
@@ -415,6 +424,9 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     q.P = s.P.as<double>();
     ps.fuse_q = nl && fuse_q;
     ps.model_bytes = bytes_prep_pass(u.pm, r.prep, nl, nm, ps.fuse_q);
+    // with q_v fused the prep pass references the vertex pass's arrays too
+    ps.comp_bytes = compulsory_prep_pass(u.pm, r.prep, nl, nm) +
+                    (ps.fuse_q ? compulsory_vert_pass(u.pm, r.vert, nm) : 0.0);
     ps.tag = cur_tag;
     u.passes.push_back(ps);
   };
@@ -451,7 +463,10 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     ps.model_bytes = fast_pass ? bytes_edge_fast_pass(u.pm, r, slow != nullptr, nm)
                      : ps.edge_cells ? bytes_edge_cells_pass(u.pm, r, drag_on, s.has_wind, nm)
                                      : bytes_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
+    ps.comp_bytes = fast_pass ? compulsory_edge_fast_pass(u.pm, r, slow != nullptr, nm)
+                              : compulsory_edge_pass(u.pm, r, drag_on, s.has_wind, nm);
     u.bytes_edge += ps.model_bytes;
+    u.comp_edge += ps.comp_bytes;
     u.edge_items += (int64_t)r.edge.size() * nm;
     ps.tag = cur_tag;
     u.passes.push_back(ps);
@@ -673,6 +688,7 @@ std::vector<Pass> merge_passes(const std::vector<MeshUnit*>& units) {
         case Pass::COPY: break;
       }
       ps.model_bytes += q.model_bytes;
+      ps.comp_bytes += q.comp_bytes;
     }
     out.push_back(ps);
   }
@@ -1832,15 +1848,20 @@ int fblts_get_info(fblts_solver* s, fblts_info* o) {
     o->max_eoe = u.pm.maxEOE;
     o->cell_substeps_per_step = u.cell_substeps;
     int64_t launches = 0;
-    double bytes = 0;
+    double bytes = 0, comp = 0;
     for (const Pass& p : u.passes) {
       launches += p.kind == Pass::RK4FIN ? (int64_t)p.fin.size() : 1;
       bytes += p.model_bytes;
+      comp += p.comp_bytes;
     }
     o->launches_per_step = launches;
     o->model_bytes_per_step = bytes;
     o->model_bytes_edge_pass = u.bytes_edge;
     o->edge_pass_items_per_step = u.edge_items;
+    o->model_bytes_cell_pass = u.bytes_cell;
+    o->compulsory_bytes_per_step = comp;
+    o->compulsory_bytes_edge_pass = u.comp_edge;
+    o->compulsory_bytes_cell_pass = u.comp_cell;
     return FBLTS_OK;
   });
 }
@@ -2390,12 +2411,15 @@ static void build_recording(fblts_solver* s, AdjointState& A) {
     throw Err(FBLTS_EINVAL, "internal: definition-mode plan reordered the mesh");
   // build the definition-mode pass list without disturbing the solver's own
   std::vector<Pass> keep = u.passes;
-  const double kb = u.bytes_edge;
+  const double kb[4] = {u.bytes_edge, u.bytes_cell, u.comp_edge, u.comp_cell};
   const int64_t ki = u.edge_items, kc = u.cell_substeps;
   build_passes_impl(u, s->P, s->drag_on, s->opt.fuse_q, &A.plan_full);
   std::vector<Pass> def = u.passes;
   u.passes = keep;
-  u.bytes_edge = kb;
+  u.bytes_edge = kb[0];
+  u.bytes_cell = kb[1];
+  u.comp_edge = kb[2];
+  u.comp_cell = kb[3];
   u.edge_items = ki;
   u.cell_substeps = kc;
   A.tape_c = (size_t)(4 + 4 * M) * N;

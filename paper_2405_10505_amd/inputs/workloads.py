@@ -119,11 +119,13 @@ def ssh_bumps(mesh, seed=4, n=3, amp=0.5, width=50e3):
     return eta
 
 
-def cfl_fine_mask(mesh, M, nu=0.6 * NU_MAX_FBRK32, g=G):
-    """Fine cells: those whose gravity-wave Courant number at the coarse step exceeds nu.
+def cfl_fine_mask(mesh, M, nu=0.6 * NU_MAX_FBRK32, g=G, margin=1.0):
+    """Fine cells: those whose gravity-wave Courant number at the coarse step exceeds margin * nu.
 
     dt_fine = nu * min_i(dx_i / c_i), dt_coarse = M dt_fine; c_i = sqrt(g H_i),
-    dx_i = the shortest dual edge of the cell.
+    dx_i = the shortest dual edge of the cell.  margin < 1 moves the cells
+    closest to the threshold into the fine set, so that the coarse region
+    keeps a stability margin at the coarse step.
     """
     dx = np.full(mesh.n_cells, np.inf)
     np.minimum.at(dx, mesh.cells_on_edge[:, 0], mesh.dc_edge)
@@ -131,7 +133,7 @@ def cfl_fine_mask(mesh, M, nu=0.6 * NU_MAX_FBRK32, g=G):
     c = np.sqrt(g * mesh.bottom_depth)
     dt_f = nu * float(np.min(dx / c))
     dt_c = M * dt_f
-    fine = c * dt_c / dx > nu
+    fine = c * dt_c / dx > margin * nu
     return fine, dt_c, dt_f
 
 

@@ -12,7 +12,11 @@
   assembled coordinate by coordinate from complex-step derivatives (1e-10 of
   each block's largest component).
 * Full size (the benchmark's 50k mesh, gauges and drag): directional
-  derivatives against the oracle's complex steps (1e-10 relative).
+  derivatives against the oracle's complex steps over 20 coarse steps (1e-10
+  relative), and over the full 200 steps with checkpoints every 20 against
+  central differences of the GPU forward on 20 random directions (1e-6).
+* The recording guard: a backward call after any change of the trajectory is
+  refused, and chained autograd applications on one solver record again.
 """
 import numpy as np
 import pytest
@@ -278,32 +282,86 @@ def test_full_gradient_matches_oracle_elementwise(linear):
         np.testing.assert_allclose(gc, oc, rtol=0, atol=1e-10 * np.max(np.abs(oc)))
 
 
-def test_adjoint_fullsize_directional_derivatives():
-    """At the benchmark adjoint's full size: the 50k-cell CVT with drag, the
-    loss over its 50 gauges, the momentum-pass schedule bench.py profiles with
-    graph replay, 4 coarse steps with checkpoints every 3 (a short last
-    segment).  For two random directions in (h0, C_D) the gradient's
-    directional derivative equals the oracle's complex-step derivative of the
-    same run to 1e-10 relative."""
-    from paper_2405_10505_amd import autotune
+@pytest.fixture(scope="module")
+def c5():
+    """The benchmark adjoint's workload: the 50k-cell CVT with drag, its 50
+    gauges (seed 9) in the fine region, the launch schedule bench.py profiles."""
     w = workloads.config2()
     om = trisk.OMesh(w.mesh)
     lab, _ = regions.layer(om, w.fine_mask, 2)
     gauges = np.sort(workloads.rng_for(9).choice(np.nonzero(w.fine_mask)[0], size=50, replace=False))
-    s = _solver(F.Mesh(w.mesh), w, w.cd)
+    return w, om, lab, gauges, F.Mesh(w.mesh)
+
+
+def _c5_gradient(c5, steps, ckpt):
+    from paper_2405_10505_amd import autotune
+    w, om, lab, gauges, fm = c5
+    s = _solver(fm, w, w.cd)
     autotune.apply(s, dict(fuse_vertex=1, block=64, edge_cells=0))
     s.set_state(w.h0, w.u0)
-    s.adjoint_forward(4, 3)
+    s.adjoint_forward(steps, ckpt)
     hN, _ = s.get_state()
     ghN = np.zeros(om.N)
     ghN[gauges] = 2.0 * (hN[gauges] - om.H[gauges])
-    gh, gu, gc = s.adjoint_backward(ghN, np.zeros(om.E))
+    return s.adjoint_backward(ghN, np.zeros(om.E))
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_fullsize_matches_oracle_complex_step(c5):
+    """20 coarse steps of the benchmark adjoint (checkpoints every 7, so the
+    last segment is short): for two random directions in (h0, C_D) the
+    gradient's directional derivative equals the oracle's complex-step
+    derivative of the same run to 1e-10 relative."""
+    w, om, lab, gauges, fm = c5
+    steps = 20
+    gh, gu, gc = _c5_gradient(c5, steps, 7)
     r = np.random.default_rng(5)
     eps = 1e-30
     for k in range(2):
         vh, vc = r.normal(size=om.N), 1e-4 * r.normal(size=om.N)
-        Lc = _loss_oracle(om, lab, w, w.h0 + 1j * eps * vh, w.u0.astype(complex), w.cd + 1j * eps * vc, 4,
+        Lc = _loss_oracle(om, lab, w, w.h0 + 1j * eps * vh, w.u0.astype(complex), w.cd + 1j * eps * vc, steps,
                           gauges, w.M)
         dL = Lc.imag / eps
         dA = gh @ vh + gc @ vc
         assert abs(dA - dL) <= 1e-10 * abs(dL), (k, dA, dL)
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_fullsize_200_steps_central_differences(c5):
+    """The benchmark adjoint at full length: 200 coarse steps, checkpoints
+    every 20, loss = sum of squared SSH over the 50 gauges.  For 20 random
+    unit directions in (h0, C_D) (seed 10; the C_D part scaled to C_D's size)
+    the gradient's directional derivative equals central differences of the
+    GPU forward to 1e-6 relative: Richardson extrapolation of the central
+    differences at eps = 1 and 1/2 (fixed in advance; the unit direction
+    spreads eps over 100k parameters, a few mm per cell)."""
+    from paper_2405_10505_amd import autotune
+    w, om, lab, gauges, fm = c5
+    steps = 200
+    gh, gu, gc = _c5_gradient(c5, steps, 20)
+    q = _solver(fm, w, w.cd)
+    autotune.apply(q, dict(fuse_vertex=1, block=64, edge_cells=0))
+
+    def loss(h0, cd):
+        q.set_drag(cd)
+        q.set_state(h0, w.u0)
+        q.step(steps)
+        h, _ = q.get_state()
+        return float(np.sum((h[gauges] - om.H[gauges]) ** 2))
+
+    rd = workloads.rng_for(10)
+    errs = []
+    for k in range(20):
+        vh = rd.normal(size=om.N)
+        vc = rd.normal(size=om.N)
+        nrm = np.sqrt(vh @ vh + vc @ vc)
+        vh, vc = vh / nrm, vc / nrm
+        ref = gh @ vh + 1e-3 * (gc @ vc)
+
+        def fd(e):
+            return (loss(w.h0 + e * vh, w.cd + e * 1e-3 * vc) - loss(w.h0 - e * vh, w.cd - e * 1e-3 * vc)) / (2 * e)
+        d1, d2 = fd(1.0), fd(0.5)
+        rich = (4 * d2 - d1) / 3
+        errs.append(abs(rich - ref) / abs(ref))
+    print("central differences, 20 directions: max rel err %.2e, median %.2e" % (max(errs), np.median(errs)))
+    assert max(errs) <= 1e-6, errs

@@ -209,3 +209,40 @@ def test_wide_members_share_slots_and_equal_single_solver_bitwise(two_meshes, nm
             hs, us = s.get_state()
             he, ue = ens.get_member(k, m)
             assert np.array_equal(he, hs) and np.array_equal(ue, us), (k, m)
+
+
+@pytest.fixture(scope="module")
+def four_meshes(two_meshes):
+    return two_meshes + [workloads.small_cvt(n=1000, seed=14), workloads.small_cvt(n=1800, seed=15)]
+
+
+@pytest.mark.parametrize("nms,graph", [([16, 4, 8, 16], True), ([1, 2, 4, 8], False), ([16, 16, 32, 16], True)])
+def test_four_meshes_every_segment_equals_single_solver_bitwise(four_meshes, nms, graph):
+    """Four meshes in one launch per pass (every slot of the launch's segment
+    table, uneven member counts, with and without the shared-slot momentum
+    pass): sampled members of every mesh equal the single-member solver."""
+    ws = four_meshes
+    dt = min(w.dt for w in ws)
+    fms = [F.Mesh(w.mesh) for w in ws]
+    ens = F.Ensemble(fms, [np.where(w.fine_mask, 0, 1) for w in ws], nms, dt, M=4, linear=False)
+    inputs = [_members(w, nm, k) for k, (w, nm) in enumerate(zip(ws, nms))]
+    for k, mem in enumerate(inputs):
+        for m, (h, u, cd) in enumerate(mem):
+            ens.set_member(k, m, h, u, cd)
+    ens.set_graph(graph)
+    d0 = ens.diagnostics()
+    ens.step(5)
+    d1 = ens.diagnostics()
+    for a, b in zip(d0, d1):
+        assert abs(b["mass"] - a["mass"]) <= 1e-13 * abs(a["mass"])
+    for k, (w, mem) in enumerate(zip(ws, inputs)):
+        for m in sorted({0, nms[k] // 2, nms[k] - 1}):
+            h, u, cd = mem[m]
+            s = F.Solver(fms[k], dt, M=4, linear=False)
+            s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+            s.set_drag(cd)
+            s.set_state(h, u)
+            s.step(5)
+            hs, us = s.get_state()
+            he, ue = ens.get_member(k, m)
+            assert np.array_equal(he, hs) and np.array_equal(ue, us), (k, m)

@@ -1,6 +1,7 @@
 """GPU parity at the benchmark's full size and launch configuration: the
 50k-cell variable-resolution CVT (nonlinear, drag, M = 4, hipGraph replay)
-against the oracle for 10 coarse steps, and Theorems 1 and 2 over 200 steps."""
+against the oracle for 100 coarse steps (relative L2 of h - H and u within
+1e-10, compared every 25 steps), and Theorems 1 and 2 over 200 steps."""
 import numpy as np
 import pytest
 
@@ -27,19 +28,23 @@ def c2():
     return w, s
 
 
-def test_fullsize_trajectory_matches_oracle(c2):
+@pytest.mark.timeout(900)
+def test_fullsize_trajectory_matches_oracle_100_steps(c2):
     w, s = c2
     om = trisk.OMesh(w.mesh)
     lab, _ = regions.layer(om, w.fine_mask, 2)
     ph = trisk.Physics(linear=False, cd=w.cd)
     u, h = w.u0.copy(), w.h0.copy()
-    for _ in range(10):
-        u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
     s.set_state(w.h0, w.u0)
-    s.step(10)
-    hg, ug = s.get_state()
-    assert np.linalg.norm(hg - h) / np.linalg.norm(h - om.H) <= 1e-10
-    assert np.linalg.norm(ug - u) / np.linalg.norm(u) <= 1e-10
+    for k in range(4):
+        for _ in range(25):
+            u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
+        s.step(25)
+        hg, ug = s.get_state()
+        eh = np.linalg.norm(hg - h) / np.linalg.norm(h - om.H)
+        eu = np.linalg.norm(ug - u) / np.linalg.norm(u)
+        print("after %d steps: rel L2 h %.2e, u %.2e" % (25 * (k + 1), eh, eu), flush=True)
+        assert eh <= 1e-10 and eu <= 1e-10, (25 * (k + 1), eh, eu)
 
 
 def test_fullsize_conservation_200_steps(c2):

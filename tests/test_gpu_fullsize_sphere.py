@@ -1,8 +1,9 @@
 """GPU parity at full size for the spherical workload: the 400k-cell
 coastline-refined CVT with bathymetry, drag, the moving cyclone and M = 8, in
 the launch configuration bench.py times (separate vertex pass, 256-thread
-blocks, hipGraph replay).  Two coarse steps are compared with the oracle on
-every cell and edge; Theorems 1 and 2 are checked over 100 steps.
+blocks, hipGraph replay).  Ten coarse steps (the storm evaluated at each
+step's time) are compared with the oracle on every cell and edge, relative L2
+within 1e-10 after every step; Theorems 1 and 2 are checked over 100 steps.
 
 Building the mesh takes about a minute (the FBLTS_MESH_CACHE directory, when
 set, keeps it between processes)."""
@@ -35,20 +36,23 @@ def c3():
     return w, storm, solver
 
 
-def test_sphere400k_two_steps_match_oracle(c3):
+@pytest.mark.timeout(900)
+def test_sphere400k_ten_steps_match_oracle(c3):
     w, storm, solver = c3
     om = trisk.OMesh(w.mesh)
     lab, _ = regions.layer(om, w.fine_mask, 2)
     u, h = w.u0.copy(), w.h0.copy()
-    for k in range(2):
+    s = solver()
+    for k in range(10):
         ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_components(w.mesh, k * w.dt))
         u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
-    s = solver()
-    s.step(2)
-    hg, ug = s.get_state()
-    assert np.linalg.norm(u) > 0
-    assert np.linalg.norm(hg - h) / np.linalg.norm(h - om.H) <= 1e-10
-    assert np.linalg.norm(ug - u) / np.linalg.norm(u) <= 1e-10
+        s.step(1)
+        hg, ug = s.get_state()
+        assert np.linalg.norm(u) > 0
+        eh = np.linalg.norm(hg - h) / np.linalg.norm(h - om.H)
+        eu = np.linalg.norm(ug - u) / np.linalg.norm(u)
+        print("step %d: rel L2 h %.2e, u %.2e" % (k + 1, eh, eu), flush=True)
+        assert eh <= 1e-10 and eu <= 1e-10, (k + 1, eh, eu)
 
 
 def test_sphere400k_conservation_100_steps(c3):
