@@ -290,6 +290,22 @@ typedef struct {
  * Returns FBLTS_ENONFINITE (and fills *out) if any h,u is non-finite or h <= 0. */
 int fblts_diagnostics(fblts_solver* s, fblts_diag* out);
 
+/* fblts_diagnostics without device allocation, for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, launch shape and results, bit for bit, but
+ * the per-block partial sums and the results live in a fixed device array of
+ * the library (8 quantities x 1024 blocks + 8 doubles, about 64 KiB, one per
+ * GPU, taken when a solver is created, held until the process ends) instead
+ * of buffers the solver allocates on first use.  Every
+ * solver fits (its reduction uses at most 1024 blocks); a reduction that
+ * would not fit is refused with FBLTS_EINVAL.  All calls on one GPU share
+ * that array: calls that overlap on one GPU (other host threads, other
+ * streams) race and must be serialised by the caller.  Copies 64 bytes to
+ * the host and synchronises the solver's stream.  Errors: FBLTS_EINVAL,
+ * FBLTS_ESTATE (no state), FBLTS_EDEVICE, FBLTS_ENONFINITE as
+ * fblts_diagnostics. */
+int fblts_diagnostics_noalloc(fblts_solver* s, fblts_diag* out);
+
 typedef struct {
   int32_t n_cells, n_edges, n_vertices;
   int32_t n_fine, n_if1, n_if2, n_int;            /* cells per region */

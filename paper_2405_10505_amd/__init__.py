@@ -113,6 +113,7 @@ _SIGS = {
     "fblts_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
+    "fblts_diagnostics_noalloc": (C.c_int, [C.c_void_p, C.POINTER(fblts_diag)]),
     "fblts_get_info": (C.c_int, [C.c_void_p, C.POINTER(fblts_info)]),
     "fblts_debug_tendency": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -379,6 +380,15 @@ class Solver:
     def diagnostics(self, allow_nonfinite=False):
         d = fblts_diag()
         rc = lib().fblts_diagnostics(self.handle, C.byref(d))
+        if rc == FBLTS_ENONFINITE and allow_nonfinite:
+            return d.as_dict()
+        _check(rc)
+        return d.as_dict()
+
+    def diagnostics_noalloc(self, allow_nonfinite=False):
+        """fblts_diagnostics_noalloc: the same results without device allocation."""
+        d = fblts_diag()
+        rc = lib().fblts_diagnostics_noalloc(self.handle, C.byref(d))
         if rc == FBLTS_ENONFINITE and allow_nonfinite:
             return d.as_dict()
         _check(rc)

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <tuple>
 #include <stdexcept>
 #include <string>
@@ -1206,6 +1207,32 @@ static void diag_of(MeshUnit& u, const Params& P, DevBuf& part, DevBuf& out, hip
   hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
 }
 
+// ------------------------------------------- allocation-free diagnostics
+// fblts_diagnostics_noalloc keeps the reduction's per-block partial sums and
+// its results in this file-scope device array instead of buffers the solver
+// allocates.  Every GPU the library runs on holds its own copy until the
+// process ends.  The diagnostics of a one-member solver launch at most
+// kDiagMaxBlocks blocks (diag_blocks), so every solver fits.
+constexpr int kDiagMaxBlocks = 1024;
+constexpr size_t kScratchDoubles = (size_t)kDiagQ * kDiagMaxBlocks + kDiagQ;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Device address of `scratch` on each device, taken once per device with that
+// device current (the array's name in host code is only a stand-in).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices] = {};
+
+static void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw Err(FBLTS_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev]) return;
+  void* p = nullptr;
+  hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (!p) throw Err(FBLTS_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch_dev[dev] = static_cast<double*>(p);
+}
+
 static int fill_diag(const double* q, double time, int64_t step, fblts_diag* o) {
   o->mass = q[0];
   o->abs_vorticity = q[1];
@@ -1501,6 +1528,7 @@ int fblts_solver_create(const fblts_mesh* mesh, const fblts_params* params, void
     s->P.p = *params;
     hip_check(hipGetDevice(&s->device), "hipGetDevice");
     s->stream = make_stream(hip_stream, s->own_stream);
+    scratch_setup(s->device);   // the solver's device is current here
     *out = s.release();
     return FBLTS_OK;
   });
@@ -1822,6 +1850,32 @@ int fblts_diagnostics(fblts_solver* s, fblts_diag* out) {
     std::vector<double> q;
     diag_of(*s->unit, s->P, s->diag_partial, s->diag_out, s->stream, q);
     const int rc = fill_diag(q.data(), s->time, s->step, out);
+    if (rc != FBLTS_OK) g_err = "state holds non-finite values or h <= 0";
+    return rc;
+  });
+}
+
+int fblts_diagnostics_noalloc(fblts_solver* s, fblts_diag* out) {
+  return guarded([&] {
+    if (!s || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    if (!s->have_state) throw Err(FBLTS_ESTATE, "no state");
+    if (s->device < 0 || s->device >= kMaxDevices || !g_scratch_dev[s->device])
+      throw Err(FBLTS_EDEVICE, "the scratch array is not set up on the solver's device");
+    MeshUnit& u = *s->unit;
+    const int nb = diag_blocks(u.dm.md);
+    const size_t part = (size_t)kDiagQ * nb * u.st.nm;
+    if (part + (size_t)kDiagQ * u.st.nm > kScratchDoubles)
+      throw Err(FBLTS_EINVAL, "the diagnostics need more than the " + std::to_string(kScratchDoubles) +
+                                  " doubles of the allocation-free scratch");
+    double* sp = g_scratch_dev[s->device];
+    // every partial and result is written before it is read: nothing to clear
+    launch_diag(u.dm.md, u.st.nm_log2, s->P.wide() ? 0 : 1, u.st.H[0].as<double>(), u.st.U[0].as<double>(),
+                s->P.p.g, sp, sp + part, s->stream);
+    hip_check(hipGetLastError(), "diagnostics launch");
+    double q[kDiagQ];
+    hip_check(hipMemcpyAsync(q, sp + part, sizeof(q), hipMemcpyDeviceToHost, s->stream), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    const int rc = fill_diag(q, s->time, s->step, out);
     if (rc != FBLTS_OK) g_err = "state holds non-finite values or h <= 0";
     return rc;
   });
