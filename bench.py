@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="cvt50k: skip the sphere400k and ensemble blocks of the JSON line")
     ap.add_argument("--schedule", default=None,
-                    help="fixed launch schedule 'fuse_vertex,block[,edge_cells]' instead of autotuning (e.g. 1,64,0)")
+                    help="fixed launch schedule 'fuse_vertex,block[,edge_cells[,persistent]]' instead of autotuning "
+                         "(e.g. 1,64,0)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many graph-replayed steps (for rocprofv3), no JSON")
     return ap.parse_args()
@@ -322,7 +323,9 @@ def sphere_block(F, torch, w, steps, reps, split=0):
                 ms_per_step=ms, samples_ms=[t / steps * 1e3 for t in samples],
                 cell_substeps_per_s=info["cell_substeps_per_step"] / ms * 1e3,
                 launch_schedule=dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"],
-                                     edge_cells=tune.get("edge_cells", 0)),
+                                     edge_cells=tune.get("edge_cells", 0),
+                                     persistent=tune.get("persistent", 0)),
+                autotune_candidates=[dict(fuse_vertex=c["fuse_vertex"], block=c["block"], edge_cells=c["edge_cells"], persistent=c["persistent"], ms_per_step=c["ms_per_step"]) for c in tune.get("candidates", [])],
                 roofline=roof)
 
 
@@ -395,8 +398,10 @@ def ensemble_block(F, torch, ws, steps, reps, schedule=None, check_all_meshes=Tr
                 cell_substeps_per_s=info["cell_substeps_per_step"] / ms * 1e3,
                 model_GBs=info["model_bytes_per_step"] / ms * 1e3 / 1e9,
                 launch_schedule=dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"],
-                                     edge_cells=tune.get("edge_cells", 0)),
+                                     edge_cells=tune.get("edge_cells", 0),
+                                     persistent=tune.get("persistent", 0)),
                 loop_of_single_member_solvers_ms_per_step=loop_ms, speedup_vs_member_loop=loop_ms / ms,
+                autotune_candidates=[dict(fuse_vertex=c["fuse_vertex"], block=c["block"], edge_cells=c["edge_cells"], persistent=c["persistent"], ms_per_step=c["ms_per_step"]) for c in tune.get("candidates", [])],
                 per_mesh=per_mesh, checked_member_per_mesh_equals_single_solver_bitwise=same)
 
 
@@ -498,12 +503,17 @@ def main():
     if args.schedule:
         vals = [int(v) for v in args.schedule.split(",")]
         tune = dict(fuse_vertex=vals[0], block=vals[1], edge_cells=vals[2] if len(vals) > 2 else 0,
+                    persistent=vals[3] if len(vals) > 3 else 0,
                     ms_per_step=float("nan"))
         autotune.apply(s, tune)
     else:
         tune = autotune.autotune(s, steps=20, repeats=3, cache_path=cache)
-    log("launch schedule: fuse_vertex=%d block=%d edge_cells=%d (%.4f ms/step when tuned)" % (
-        tune["fuse_vertex"], tune["block"], tune.get("edge_cells", 0), tune["ms_per_step"]))
+    log("launch schedule: fuse_vertex=%d block=%d edge_cells=%d persistent=%d (%.4f ms/step when tuned)" % (
+        tune["fuse_vertex"], tune["block"], tune.get("edge_cells", 0), tune.get("persistent", 0),
+        tune["ms_per_step"]))
+    for c in tune.get("candidates", []):
+        log("  candidate fuse_vertex=%d block=%d edge_cells=%d persistent=%d: %.4f ms/step" % (
+            c["fuse_vertex"], c["block"], c["edge_cells"], c["persistent"], c["ms_per_step"]))
     info = s.info()
     if args.profile_steps:
         s.step(args.profile_steps)
@@ -575,7 +585,7 @@ def main():
         sweep = paper = fastest = None
         if args.split == 0 and args.workload == "cvt50k":
             w._schedule = dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"],
-                               edge_cells=tune.get("edge_cells", 0))
+                               edge_cells=tune.get("edge_cells", 0), persistent=tune.get("persistent", 0))
             sweep, paper, fastest = lts_sweep(F, torch, w, rate_fb, rate_rk4, dt_fb, ks, args.reps, args.split)
             w._schedule = None
         chosen = paper or recipe
@@ -631,9 +641,13 @@ def main():
                            cell_substeps_per_step=info["cell_substeps_per_step"],
                            launches_per_step=info["launches_per_step"], hipgraph=True,
                            launch_schedule=dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"],
-                                                edge_cells=tune.get("edge_cells", 0))),
+                                                edge_cells=tune.get("edge_cells", 0),
+                                     persistent=tune.get("persistent", 0))),
                timing=dict(samples_ms=[x / args.steps * 1e3 for x in samples], reps=args.reps,
                            statistic="median"),
+               autotune_candidates=[dict(fuse_vertex=c["fuse_vertex"], block=c["block"], edge_cells=c["edge_cells"],
+                                         persistent=c["persistent"], ms_per_step=c["ms_per_step"])
+                                    for c in tune.get("candidates", [])],
                roofline=roof, cpu_baseline=cpu, comparison=comp, sphere400k=sphere, ensemble=ensemble,
                whole_step_compulsory_GBs=whole, compulsory_bytes_per_step=info["compulsory_bytes_per_step"],
                model_bytes_per_step=info["model_bytes_per_step"],
@@ -656,7 +670,8 @@ def bench_ensemble(args):
     sched = None
     if args.schedule:
         vals = [int(v) for v in args.schedule.split(",")]
-        sched = dict(fuse_vertex=vals[0], block=vals[1], edge_cells=vals[2] if len(vals) > 2 else 0)
+        sched = dict(fuse_vertex=vals[0], block=vals[1], edge_cells=vals[2] if len(vals) > 2 else 0,
+                    persistent=vals[3] if len(vals) > 3 else 0)
     if args.profile_steps:
         # stepping dispatches only: the members are set before the profiled steps
         from paper_2405_10505_amd import autotune
@@ -711,7 +726,8 @@ def bench_adjoint(args):
     s.set_state(w.h0, w.u0)
     if args.schedule:
         vals = [int(v) for v in args.schedule.split(",")]
-        tune = dict(fuse_vertex=vals[0], block=vals[1], edge_cells=vals[2] if len(vals) > 2 else 0)
+        tune = dict(fuse_vertex=vals[0], block=vals[1], edge_cells=vals[2] if len(vals) > 2 else 0,
+                    persistent=vals[3] if len(vals) > 3 else 0)
         autotune.apply(s, tune)
     else:
         tune = autotune.autotune(s, steps=10, repeats=2)

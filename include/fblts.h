@@ -270,9 +270,24 @@ int fblts_set_graph(fblts_solver* s, int32_t enable);
  *   FBLTS_OPT_GRAPH_STEPS: coarse steps captured per hipGraph (1..64, default
  *     8); fblts_step(n) replays the multi-step graph n / G times and a one-step
  *     graph for the remainder (each graph launch costs a fixed boundary).
+ *   FBLTS_OPT_PERSISTENT: k > 0 runs each coarse step's consecutive stencil,
+ *     prediction and assembly passes (Sec. 2.2 steps 1-4) in one cooperative
+ *     launch (hipLaunchCooperativeKernel; k blocks of 256 threads per compute
+ *     unit, at most as many as stay resident, whatever FBLTS_OPT_BLOCK says;
+ *     a grid-wide barrier between passes); forcing and RK4-combination passes, and the
+ *     EDGE_CELLS momentum pass, launch on their own between such runs.  Steps
+ *     then launch directly (no graph).  A barrier that gives up waiting (only
+ *     if the device cannot keep the grid resident) makes the next state read
+ *     or diagnostics fail with FBLTS_EDEVICE.  Default 0.
  * Errors: FBLTS_EINVAL for an unknown option or value, or EDGE_CELLS on a
  * mesh whose weights are not the kite-fraction walks. */
-enum { FBLTS_OPT_FUSE_VERTEX = 1, FBLTS_OPT_BLOCK = 2, FBLTS_OPT_EDGE_CELLS = 3, FBLTS_OPT_GRAPH_STEPS = 4 };
+enum {
+  FBLTS_OPT_FUSE_VERTEX = 1,
+  FBLTS_OPT_BLOCK = 2,
+  FBLTS_OPT_EDGE_CELLS = 3,
+  FBLTS_OPT_GRAPH_STEPS = 4,
+  FBLTS_OPT_PERSISTENT = 5
+};
 int fblts_set_option(fblts_solver* s, int32_t option, int32_t value);
 
 typedef struct {
@@ -439,11 +454,15 @@ int fblts_ensemble_info(fblts_ensemble* e, int64_t* member_cells, int64_t* cell_
 /* -------------------------------------------------------- autotuning --- */
 
 /* Launch-schedule search for a solver or an ensemble.  Times every candidate
- * schedule -- q_v fused into the prep pass or not (FBLTS_OPT_FUSE_VERTEX),
- * blocks of 256, 128 or 64 threads (FBLTS_OPT_BLOCK), and, where every mesh
- * allows it, the momentum pass through the cells' edge lists
- * (FBLTS_OPT_EDGE_CELLS) -- on graph-replayed coarse steps, and leaves the
- * fastest set.  Every candidate computes the same bits, so tuning never
+ * schedule, in this order -- q_v fused into the prep pass or not
+ * (FBLTS_OPT_FUSE_VERTEX) with blocks of 256, 128 or 64 threads
+ * (FBLTS_OPT_BLOCK) on graph-replayed coarse steps; the persistent launch
+ * (FBLTS_OPT_PERSISTENT) with q_v fused or not and 1 or 4 blocks per compute
+ * unit, where the device supports cooperative launches; and, where every
+ * mesh allows it, the momentum pass
+ * through the cells' edge lists (FBLTS_OPT_EDGE_CELLS) with each fusion and
+ * block size -- and leaves the fastest set.  Every candidate computes the
+ * same bits, so tuning never
  * changes results.  Before the search the state, the model time and step
  * count, and with a moving storm its step clock and wind, are saved; they
  * are restored afterwards, as are the graph and timing settings.
@@ -474,6 +493,7 @@ typedef struct fblts_schedule {
   int32_t edge_cells;    /* FBLTS_OPT_EDGE_CELLS value */
   int32_t from_cache;    /* 1: read from the cache file, not timed */
   double ms_per_step;    /* best time per coarse step (ms), measured or cached */
+  int32_t persistent;    /* FBLTS_OPT_PERSISTENT value */
 } fblts_schedule;
 int fblts_autotune(void* handle, int32_t handle_kind, int32_t steps, int32_t repeats, const char* cache_json_path,
                    fblts_schedule* out, fblts_schedule* tried, int32_t max_tried, int32_t* n_tried);

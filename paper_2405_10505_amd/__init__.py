@@ -20,7 +20,7 @@ SCHEME_FBLTS, SCHEME_FBRK32, SCHEME_RK4 = 0, 1, 2
 PHYS_LINEAR, PHYS_NONLINEAR, PHYS_GRAVITY_WAVE = 0, 1, 2
 SPLIT_NONE, SPLIT_COARSE, SPLIT_FINE = 0, 1, 2
 BETA = (0.531, 0.531, 0.313)
-OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS, OPT_GRAPH_STEPS = 1, 2, 3, 4
+OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS, OPT_GRAPH_STEPS, OPT_PERSISTENT = 1, 2, 3, 4, 5
 HANDLE_SOLVER, HANDLE_ENSEMBLE = 0, 1
 
 _P_i32 = C.POINTER(C.c_int32)
@@ -66,7 +66,7 @@ class fblts_plan_info(C.Structure):
 
 class fblts_schedule(C.Structure):
     _fields_ = [("fuse_vertex", C.c_int32), ("block", C.c_int32), ("edge_cells", C.c_int32),
-                ("from_cache", C.c_int32), ("ms_per_step", C.c_double)]
+                ("from_cache", C.c_int32), ("ms_per_step", C.c_double), ("persistent", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -186,7 +186,7 @@ def _check(rc):
 
 
 # at most 2 x 2 x 3 candidate schedules (cells, fused q, block)
-_MAX_CANDIDATES = 12
+_MAX_CANDIDATES = 16
 
 
 def _autotune(handle, kind, steps, repeats, cache_path):

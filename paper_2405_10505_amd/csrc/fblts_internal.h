@@ -177,4 +177,36 @@ struct Launch {
   S seg[kMaxSeg];
 };
 
+// One pass of a persistent launch: a run of consecutive stencil and
+// elementwise passes executed by one cooperative kernel, with a grid-wide
+// barrier between passes.  The pass's launch table is laid out for blocks of
+// kBlock threads; nvb is its number of such (virtual) blocks.
+enum PassKind { PK_CELL = 0, PK_VERT, PK_PREP, PK_EDGE, PK_EDGE_FAST, PK_PRED, PK_ASM };
+struct PassDesc {
+  int kind;       // PassKind
+  int variant;    // CELL: MODE; PREP: 0 linear, 1 nonlinear, 2 nonlinear with q_v fused;
+                  // EDGE: drag | wind << 1 | group << 2; EDGE_FAST: slow
+  int nvb;
+  int pad;
+  union U {
+    Launch<CellSeg> cell;
+    Launch<VertSeg> vert;
+    Launch<PrepSeg> prep;
+    Launch<EdgeSeg> edge;
+    Launch<PredSeg> pred;
+    Launch<AsmSeg> asmb;
+  } u;
+};
+
+// Grid barrier state of a persistent launch (device memory, zero before the
+// first launch and zero again after every completed launch): ctr[0] counts
+// the group leaders, ctr[32 * (g + 1)] the blocks of group g (g < 8), ctr[400]
+// is the generation; abort is set when a wait gave up (the launch is then
+// abandoned and its results are invalid).
+struct GridBar {
+  unsigned* ctr;
+  int* abort;
+};
+constexpr int kBarWords = 512;
+
 }  // namespace fblts

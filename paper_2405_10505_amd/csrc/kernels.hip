@@ -77,10 +77,9 @@ __device__ __forceinline__ void sgpr_ready(const T&... v) {
 // B = K + g(h* - H)); 2: fast terms of the operator splitting, eq. fast_terms
 // (flux h_e u, B = g(h* - H), no kinetic energy).
 template <int MODE, bool ONE>
-__global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
+__device__ __forceinline__ void cell_body(const Launch<CellSeg>& L, const int b) {
   constexpr bool NONLINEAR = MODE != 0;   // thickness flux with h_e
   constexpr bool KE = MODE == 1;          // kinetic energy in B
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int s = find_seg<ONE>(L, b);
   const CellSeg& S = L.seg[s];
   if constexpr (ONE) sgpr_ready(L.block, S.m.c_edge, S.m.c_nbr, S.m.cs, S.m.c_nedge, S.Hsrc, S.Usrc, S.m.e_dv, S.m.e_dc);
@@ -165,6 +164,11 @@ __global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
   S.B[ii] = K + S.g * (hs - Hrest);
 }
 
+template <int MODE, bool ONE>
+__global__ void __launch_bounds__(kBlock) k_cell(const Launch<CellSeg> L) {
+  cell_body<MODE, ONE>(L, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // -------------------------------------------------------------- vertex pass
 // q_v = (zeta_v + f_v) / h_v with zeta_v = (1/A_v) sum s_{e,v} d_e u_e and
 // h_v = (1/A_v) sum kite_{i,v} h*_i.  Shared by the vertex pass and the fused
@@ -190,8 +194,7 @@ __device__ __forceinline__ double vertex_q(const MeshDev& m, int v, const double
 }
 
 template <bool ONE>
-__global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void vertex_body(const Launch<VertSeg>& L, const int b) {
   const int s = find_seg<ONE>(L, b);
   const VertSeg& S = L.seg[s];
   if constexpr (ONE) sgpr_ready(L.block, S.m.v_edge, S.m.v_cell, S.m.vs, S.Usrc, S.hs, S.m.e_dc, S.q);
@@ -202,6 +205,11 @@ __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
   const int mem = (int)(item & ((1 << nm_log2) - 1));
   const int nm = 1 << nm_log2;
   S.q[(long)v * nm + mem] = vertex_q(S.m, v, S.Usrc, S.hs, nm, mem);
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
+  vertex_body<ONE>(L, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // q at an edge's two vertices v0, v1 from the per-edge copies of their lists:
@@ -240,8 +248,7 @@ __device__ __forceinline__ void edge_vertices_q(const MeshDev& m, int e, int v0,
 // vertex pass's output (one launch fewer per stage, each vertex evaluated by
 // its three edges).
 template <bool LINEAR, bool FUSE_Q, bool ONE>
-__global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void prep_body(const Launch<PrepSeg>& L, const int b) {
   const int s = find_seg<ONE>(L, b);
   const PrepSeg& S = L.seg[s];
   if constexpr (ONE) {
@@ -277,6 +284,11 @@ __global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
   reinterpret_cast<double2*>(S.P)[k] = make_double2(dv * (he * u), qe);
   S.P[2 * np + k] = dv * u;
   S.P[3 * np + k] = he;
+}
+
+template <bool LINEAR, bool FUSE_Q, bool ONE>
+__global__ void __launch_bounds__(kBlock) k_prep(const Launch<PrepSeg> L) {
+  prep_body<LINEAR, FUSE_Q, ONE>(L, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------- edge pass
@@ -350,8 +362,7 @@ __device__ __forceinline__ void walk_cell(const MeshDev& m, const double* __rest
 // slot; all maxEOE slots are taken (the padding slots are exact no-ops), so
 // every lane of the group takes part in every permute.
 template <bool DRAG, bool WIND, bool CELLS, bool ONE, bool GROUP>
-__global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void edge_body(const Launch<EdgeSeg>& L, const int b) {
   const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
   if constexpr (ONE) {
@@ -440,13 +451,17 @@ __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
   }
 }
 
+template <bool DRAG, bool WIND, bool CELLS, bool ONE, bool GROUP>
+__global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
+  edge_body<DRAG, WIND, CELLS, ONE, GROUP>(L, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // ----------------------------------------------------- fast momentum pass
 // Fast momentum tendency of the operator splitting (eq. fast_terms):
 // Phi = -(B_c1 - B_c0) / d_e with B = g(h* - H), plus (SLOW) the slow tendency
 // frozen at the start of the step or substep (eq. splitting).
 template <bool SLOW, bool ONE>
-__global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
-  const int b = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void edge_fast_body(const Launch<EdgeSeg>& L, const int b) {
   const int s = find_seg<ONE>(L, b);
   const EdgeSeg& S = L.seg[s];
   if constexpr (ONE) sgpr_ready(L.block, S.B, S.m.es, S.m.e_cell, S.m.e_invdc, S.Udst, S.U0);
@@ -468,10 +483,14 @@ __global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
   }
 }
 
+template <bool SLOW, bool ONE>
+__global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
+  edge_fast_body<SLOW, ONE>(L, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------- prediction pass
 template <bool ONE>
-__global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void predict_body(const Launch<PredSeg>& L, const int b) {
   const int s = find_seg<ONE>(L, b);
   const PredSeg& S = L.seg[s];
   if constexpr (ONE) sgpr_ready(L.block, S.save, S.c_begin, S.c_end, S.e_begin, S.e_end, S.a, S.invM);
@@ -509,10 +528,14 @@ __global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
   }
 }
 
+template <bool ONE>
+__global__ void __launch_bounds__(kBlock) k_predict(const Launch<PredSeg> L) {
+  predict_body<ONE>(L, blockIdx.x);
+}
+
 // ------------------------------------------------------------ assembly pass
 template <bool ONE>
-__global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void assemble_body(const Launch<AsmSeg>& L, const int b) {
   const int s = find_seg<ONE>(L, b);
   const AsmSeg& S = L.seg[s];
   if constexpr (ONE) sgpr_ready(L.block, S.if1_c_begin, S.if1_c_end, S.if2_c_end, S.N, S.if1_e_begin, S.if1_e_end,
@@ -542,6 +565,126 @@ __global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
     } else {
       S.U0[i] = S.U3[i];
     }
+  }
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(kBlock) k_assemble(const Launch<AsmSeg> L) {
+  assemble_body<ONE>(L, blockIdx.x);
+}
+
+// -------------------------------------------------------- persistent launch
+// A run of passes in one cooperative launch: every block walks the passes in
+// order, takes its share of each pass's blocks (each XCD a contiguous slice,
+// as xcd_tile does for a separate launch), and waits at a grid barrier before
+// the next pass.  Each pass evaluates exactly what its own launch would
+// (the same body, item by item), so the results are bitwise those of the
+// separate launches.
+
+// Two-level grid barrier: the blocks of group g = blockIdx.x % 8 arrive at
+// their group's counter, the last of each group at the top counter, and the
+// last group leader advances the generation, which everyone polls.  Device-
+// scope atomics are relaxed; fences order the data: a release fence before
+// arriving, an acquire-release fence on each leader's path, an acquire fence
+// after the wait.  A wait gives up after kSpinLimit polls (seconds) and sets
+// the abort flag, which also releases every other waiting block; the launch's
+// results are then invalid and the host reports it.
+constexpr long kSpinLimit = 1L << 22;
+
+__device__ bool grid_barrier(const GridBar& B) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    const unsigned X = 8, G = gridDim.x, g = blockIdx.x % X;
+    const unsigned members = G / X + (g < G % X ? 1u : 0u);
+    const unsigned groups = G < X ? G : X;
+    unsigned* gen = B.ctr + 400;
+    unsigned* grp = B.ctr + 32 * (g + 1);
+    const unsigned cur = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    bool last = false;
+    if (__hip_atomic_fetch_add(grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+      __hip_atomic_store(grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      if (__hip_atomic_fetch_add(B.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == groups - 1) {
+        __hip_atomic_store(B.ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(gen, cur + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
+      long spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == cur) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit || __hip_atomic_load(B.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(B.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+__device__ __forceinline__ void run_pass(const PassDesc& D, int b) {
+  switch (D.kind) {
+    case PK_CELL:
+      if (D.variant == 1) cell_body<1, false>(D.u.cell, b);
+      else if (D.variant == 2) cell_body<2, false>(D.u.cell, b);
+      else cell_body<0, false>(D.u.cell, b);
+      break;
+    case PK_VERT: vertex_body<false>(D.u.vert, b); break;
+    case PK_PREP:
+      if (D.variant == 0) prep_body<true, false, false>(D.u.prep, b);
+      else if (D.variant == 1) prep_body<false, false, false>(D.u.prep, b);
+      else prep_body<false, true, false>(D.u.prep, b);
+      break;
+    case PK_EDGE:
+      switch (D.variant) {
+        case 0: edge_body<false, false, false, false, false>(D.u.edge, b); break;
+        case 1: edge_body<true, false, false, false, false>(D.u.edge, b); break;
+        case 2: edge_body<false, true, false, false, false>(D.u.edge, b); break;
+        case 3: edge_body<true, true, false, false, false>(D.u.edge, b); break;
+        case 4: edge_body<false, false, false, false, true>(D.u.edge, b); break;
+        case 5: edge_body<true, false, false, false, true>(D.u.edge, b); break;
+        case 6: edge_body<false, true, false, false, true>(D.u.edge, b); break;
+        default: edge_body<true, true, false, false, true>(D.u.edge, b); break;
+      }
+      break;
+    case PK_EDGE_FAST:
+      if (D.variant) edge_fast_body<true, false>(D.u.edge, b);
+      else edge_fast_body<false, false>(D.u.edge, b);
+      break;
+    case PK_PRED: predict_body<false>(D.u.pred, b); break;
+    case PK_ASM: assemble_body<false>(D.u.asmb, b); break;
+    default: break;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_persistent(const PassDesc* __restrict__ D, int n, GridBar B) {
+  __shared__ PassDesc sd;
+  const int G = (int)gridDim.x;
+  for (int p = 0; p < n; ++p) {
+    // the pass's descriptor, staged in LDS for the whole block
+    {
+      const unsigned long long* src = reinterpret_cast<const unsigned long long*>(D + p);
+      unsigned long long* dst = reinterpret_cast<unsigned long long*>(&sd);
+      for (int k = threadIdx.x; k < (int)(sizeof(PassDesc) / 8); k += kBlock) dst[k] = src[k];
+    }
+    __syncthreads();
+    const int nvb = sd.nvb;
+    if (nvb > 0) {
+      const int X = 8, x = blockIdx.x % X, k = blockIdx.x / X, per = G / X;
+      const int lo = (int)((long)nvb * x / X), hi = (int)((long)nvb * (x + 1) / X);
+      for (int vb = lo + k; vb < hi; vb += per) run_pass(sd, vb);
+    }
+    __syncthreads();
+    if (nvb > 0 && p + 1 < n && !grid_barrier(B)) return;
   }
 }
 
@@ -828,6 +971,80 @@ int launch_assemble(Launch<AsmSeg> L, hipStream_t st) {
   if (L.nseg == 1) hipLaunchKernelGGL(k_assemble<true>, dim3(nb), dim3(kBlock), 0, st, L);
   else hipLaunchKernelGGL(k_assemble<false>, dim3(nb), dim3(kBlock), 0, st, L);
   return nb;
+}
+
+// Descriptors of the passes a persistent launch can run (laid out for
+// kBlock-thread blocks); false for a pass kind it cannot run.
+bool desc_cell(PassDesc& d, Launch<CellSeg> L, int mode) {
+  d.kind = PK_CELL;
+  d.variant = mode;
+  d.nvb = blocks_for(L, cell_items, kBlock);
+  d.u.cell = L;
+  return true;
+}
+
+bool desc_vert(PassDesc& d, Launch<VertSeg> L) {
+  d.kind = PK_VERT;
+  d.variant = 0;
+  d.nvb = blocks_for(L, vert_items, kBlock);
+  d.u.vert = L;
+  return true;
+}
+
+bool desc_prep(PassDesc& d, Launch<PrepSeg> L, bool fuse_q) {
+  d.kind = PK_PREP;
+  d.variant = L.seg[0].linear ? 0 : (fuse_q ? 2 : 1);
+  d.nvb = blocks_for(L, prep_items, kBlock);
+  d.u.prep = L;
+  return true;
+}
+
+bool desc_edge(PassDesc& d, Launch<EdgeSeg> L, bool drag, bool wind, bool fast, bool cells) {
+  if (cells) return false;
+  d.nvb = blocks_for(L, edge_items, kBlock);
+  if (fast) {
+    d.kind = PK_EDGE_FAST;
+    d.variant = L.seg[0].slow != nullptr ? 1 : 0;
+  } else {
+    d.kind = PK_EDGE;
+    d.variant = (drag ? 1 : 0) | (wind ? 2 : 0) | (group_slots(L) ? 4 : 0);
+  }
+  d.u.edge = L;
+  return true;
+}
+
+bool desc_pred(PassDesc& d, Launch<PredSeg> L) {
+  d.kind = PK_PRED;
+  d.variant = 0;
+  d.nvb = blocks_for(L, pred_items, kBlock);
+  d.u.pred = L;
+  return true;
+}
+
+bool desc_asm(PassDesc& d, Launch<AsmSeg> L) {
+  d.kind = PK_ASM;
+  d.variant = 0;
+  d.nvb = blocks_for(L, asm_items, kBlock);
+  d.u.asmb = L;
+  return true;
+}
+
+// Blocks of one cooperative launch of k_persistent: per_cu blocks per
+// compute unit, at most as many as stay resident (a multiple of 8, the XCD
+// count).
+int persistent_grid(int per_cu, hipError_t* err) {
+  int dev = 0, cus = 0, occ = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_persistent, kBlock, 0);
+  *err = e;
+  if (e != hipSuccess) return 0;
+  return ((per_cu < occ ? per_cu : occ) * cus) / 8 * 8;
+}
+
+hipError_t launch_persistent(const PassDesc* dev_desc, int n, int grid, GridBar B, hipStream_t st) {
+  void* args[] = {(void*)&dev_desc, (void*)&n, (void*)&B};
+  return hipLaunchCooperativeKernel((const void*)k_persistent, dim3(grid), dim3(kBlock), args, 0, st);
 }
 
 void launch_axpy_final(double* y, const double* acc, double c, long n, hipStream_t st) {

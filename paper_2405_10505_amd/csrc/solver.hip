@@ -51,6 +51,14 @@ int diag_blocks(const MeshDev& m);
 void launch_diag(const MeshDev& m, int nm_log2, int linear, const double* h, const double* u, double g,
                  double* partial, double* out, hipStream_t st);
 constexpr int kDiagQ = 8;
+bool desc_cell(PassDesc& d, Launch<CellSeg> L, int mode);
+bool desc_vert(PassDesc& d, Launch<VertSeg> L);
+bool desc_prep(PassDesc& d, Launch<PrepSeg> L, bool fuse_q);
+bool desc_edge(PassDesc& d, Launch<EdgeSeg> L, bool drag, bool wind, bool fast, bool cells);
+bool desc_pred(PassDesc& d, Launch<PredSeg> L);
+bool desc_asm(PassDesc& d, Launch<AsmSeg> L);
+int persistent_grid(int per_cu, hipError_t* err);
+hipError_t launch_persistent(const PassDesc* dev_desc, int n, int grid, GridBar B, hipStream_t st);
 }  // namespace fblts
 
 using namespace fblts;
@@ -290,6 +298,7 @@ struct MeshUnit {
   DevMesh dm;
   DevState st;
   std::vector<Pass> passes;
+  uint64_t version = 0;   // advanced whenever the pass list is rebuilt
   int64_t cell_substeps = 0;
   double bytes_edge = 0.0, bytes_cell = 0.0;   // per-pass model of the momentum / thickness passes
   double comp_edge = 0.0, comp_cell = 0.0;     // compulsory model of the same passes
@@ -329,6 +338,8 @@ struct LaunchOpts {
   int block = kBlock;        // threads per block of the stencil passes
   bool edge_cells = false;   // momentum pass through the cells' edge lists
   int graph_steps = 8;       // coarse steps per replayed hipGraph
+  int persistent = 0;        // > 0: runs of passes in one cooperative launch each, with
+                             // this many blocks per compute unit
 };
 
 void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, const Plan* plan = nullptr,
@@ -658,6 +669,7 @@ void build_passes(MeshUnit& u, const Params& P, bool drag_on, const LaunchOpts& 
   build_passes_impl(u, P, drag_on, o.fuse_q, nullptr, o.edge_cells);
   add_forcing_passes(u);
   for (Pass& p : u.passes) p.bs = bs;
+  ++u.version;
 }
 
 // Merge per-mesh pass lists into multi-segment launches.
@@ -720,9 +732,10 @@ struct Timing {
   void reset() { std::fill(used, used + 4, 0); }
 };
 
-// Launch a pass list on a stream.
-void run_passes(const std::vector<Pass>& passes, bool drag, bool wind, hipStream_t st, Timing* tm) {
-  for (const Pass& ps : passes) {
+// Launch the passes [first, last) on a stream.
+void run_pass_range(const Pass* first, const Pass* last, bool drag, bool wind, hipStream_t st, Timing* tm) {
+  for (const Pass* pp = first; pp != last; ++pp) {
+    const Pass& ps = *pp;
     int cls = -1;
     switch (ps.kind) {
       case Pass::EDGE: cls = 0; break;
@@ -765,6 +778,110 @@ void run_passes(const std::vector<Pass>& passes, bool drag, bool wind, hipStream
     }
   }
   hip_check(hipGetLastError(), "kernel launch");
+}
+
+void run_passes(const std::vector<Pass>& passes, bool drag, bool wind, hipStream_t st, Timing* tm) {
+  run_pass_range(passes.data(), passes.data() + passes.size(), drag, wind, st, tm);
+}
+
+// The step program in persistent form: maximal runs of consecutive passes
+// that the persistent kernel can run, each one cooperative launch (grid-wide
+// barriers between its passes), and the other passes (forcing, the RK4
+// combination) launched on their own in between.
+struct PersistProg {
+  struct Item {
+    int first = 0, count = 0;   // passes [first, first + count)
+    bool coop = false;
+    int desc = 0, grid = 0;     // first descriptor and grid of a cooperative run
+  };
+  std::vector<Item> items;
+  DevBuf desc, bar;             // descriptors; barrier counters + abort flag
+  uint64_t version = ~0ull;     // the pass list it was built from
+  int per_cu = 0;               // and the blocks per compute unit
+  void reset() { version = ~0ull; }
+};
+
+void build_persist(const std::vector<Pass>& passes, bool drag, bool wind, int per_cu, PersistProg& pp,
+                   hipStream_t st) {
+  hipError_t err = hipSuccess;
+  const int gmax = persistent_grid(per_cu, &err);
+  hip_check(err, "cooperative launch occupancy");
+  if (gmax < 8) throw Err(FBLTS_EDEVICE, "the persistent kernel cannot keep 8 blocks resident");
+  std::vector<PassDesc> host;
+  pp.items.clear();
+  for (size_t i = 0; i < passes.size(); ++i) {
+    const Pass& p = passes[i];
+    PassDesc d;
+    bool ok = false;
+    switch (p.kind) {
+      case Pass::CELL: ok = desc_cell(d, p.cell, p.cell_mode); break;
+      case Pass::VERT: ok = desc_vert(d, p.vert); break;
+      case Pass::PREP: ok = desc_prep(d, p.prep, p.fuse_q); break;
+      case Pass::EDGE: ok = desc_edge(d, p.edge, drag, wind, p.edge_fast, p.edge_cells); break;
+      case Pass::PRED: ok = desc_pred(d, p.pred); break;
+      case Pass::ASM: ok = desc_asm(d, p.asmb); break;
+      default: break;
+    }
+    if (!ok) {
+      PersistProg::Item it;
+      it.first = (int)i;
+      it.count = 1;
+      pp.items.push_back(it);
+      continue;
+    }
+    if (pp.items.empty() || !pp.items.back().coop) {
+      PersistProg::Item it;
+      it.first = (int)i;
+      it.coop = true;
+      it.desc = (int)host.size();
+      it.grid = 8;
+      pp.items.push_back(it);
+    }
+    PersistProg::Item& it = pp.items.back();
+    ++it.count;
+    it.grid = std::min(gmax, std::max(it.grid, (d.nvb + 7) / 8 * 8));
+    host.push_back(d);
+  }
+  if (!host.empty()) {
+    pp.desc.alloc(host.size() * sizeof(PassDesc));
+    hip_check(hipMemcpyAsync(pp.desc.p, host.data(), host.size() * sizeof(PassDesc), hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync");
+  }
+  if (!pp.bar.p) {
+    pp.bar.alloc(kBarWords * sizeof(unsigned) + 64);
+    hip_check(hipMemsetAsync(pp.bar.p, 0, kBarWords * sizeof(unsigned) + 64, st), "hipMemsetAsync");
+  }
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+void run_persist(const std::vector<Pass>& passes, const PersistProg& pp, bool drag, bool wind, hipStream_t st) {
+  GridBar B;
+  B.ctr = static_cast<unsigned*>(pp.bar.p);
+  B.abort = reinterpret_cast<int*>(static_cast<char*>(pp.bar.p) + kBarWords * sizeof(unsigned));
+  for (const PersistProg::Item& it : pp.items) {
+    if (it.coop)
+      hip_check(launch_persistent(pp.desc.as<PassDesc>() + it.desc, it.count, it.grid, B, st),
+                "hipLaunchCooperativeKernel");
+    else
+      run_pass_range(passes.data() + it.first, passes.data() + it.first + it.count, drag, wind, st, nullptr);
+  }
+}
+
+// A grid barrier that gave up (the launch could not keep its blocks
+// resident) leaves results that are invalid: report it, and clear the
+// counters for the next launch.
+void check_persist(PersistProg& pp, hipStream_t st) {
+  if (!pp.bar.p) return;
+  int abort_flag = 0;
+  hip_check(hipMemcpyAsync(&abort_flag, static_cast<char*>(pp.bar.p) + kBarWords * sizeof(unsigned), sizeof(int),
+                           hipMemcpyDeviceToHost, st),
+            "hipMemcpyAsync");
+  hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (abort_flag) {
+    hip_check(hipMemsetAsync(pp.bar.p, 0, kBarWords * sizeof(unsigned) + 64, st), "hipMemsetAsync");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    throw Err(FBLTS_EDEVICE, "a grid barrier of the persistent launch gave up waiting: the state is invalid");
+  }
 }
 
 }  // namespace
@@ -1078,6 +1195,7 @@ struct fblts_solver {
   LaunchOpts opt;
   bool graph_on = false;
   StepGraphs graphs;
+  PersistProg persist;
   Timing timing;
   DevBuf diag_partial, diag_out;
   DevBuf stage_h, stage_u;   // caller-order staging
@@ -1103,8 +1221,10 @@ struct fblts_ensemble {
   bool own_stream = false;
   std::vector<std::unique_ptr<MeshUnit>> units;
   std::vector<Pass> passes;
+  uint64_t version = 0;   // advanced whenever the merged pass list is rebuilt
   bool graph_on = false;
   StepGraphs graphs;
+  PersistProg persist;
   DevBuf diag_partial, diag_out, stage_h, stage_u;
   int64_t step = 0;
   ~fblts_ensemble() {
@@ -1249,7 +1369,16 @@ static int fill_diag(const double* q, double time, int64_t step, fblts_diag* o) 
 
 static void solver_run(fblts_solver* s, int n) {
   MeshUnit& u = *s->unit;
-  if (s->graph_on && !s->timing.on) {
+  if (s->opt.persistent && !s->timing.on) {
+    // one cooperative launch per run of passes; no graph (timing launches
+    // every pass on its own)
+    if (s->persist.version != u.version || s->persist.per_cu != s->opt.persistent) {
+      build_persist(u.passes, s->drag_on, u.st.has_wind, s->opt.persistent, s->persist, s->stream);
+      s->persist.version = u.version;
+      s->persist.per_cu = s->opt.persistent;
+    }
+    for (int k = 0; k < n; ++k) run_persist(u.passes, s->persist, s->drag_on, u.st.has_wind, s->stream);
+  } else if (s->graph_on && !s->timing.on) {
     s->graphs.run(s->stream, n, s->opt.graph_steps,
                   [&] { run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, nullptr); });
   } else {
@@ -1263,7 +1392,14 @@ static void solver_run(fblts_solver* s, int n) {
 
 static void ensemble_run(fblts_ensemble* e, int n) {
   const bool nl = e->P.nonlinear();
-  if (e->graph_on) {
+  if (e->opt.persistent) {
+    if (e->persist.version != e->version || e->persist.per_cu != e->opt.persistent) {
+      build_persist(e->passes, nl, e->units[0]->st.has_wind, e->opt.persistent, e->persist, e->stream);
+      e->persist.version = e->version;
+      e->persist.per_cu = e->opt.persistent;
+    }
+    for (int k = 0; k < n; ++k) run_persist(e->passes, e->persist, nl, e->units[0]->st.has_wind, e->stream);
+  } else if (e->graph_on) {
     e->graphs.run(e->stream, n, e->opt.graph_steps,
                   [&] { run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr); });
   } else {
@@ -1285,6 +1421,7 @@ static void ensemble_rebuild(fblts_ensemble* e) {
     units.push_back(u.get());
   }
   e->passes = merge_passes(units);
+  ++e->version;
   e->graphs.reset();
 }
 
@@ -1341,6 +1478,7 @@ static void snapshot_restore(const std::vector<MeshUnit*>& units, const std::vec
 struct Schedule {
   int fuse = 1, block = kBlock, cells = 0;
   double ms = 0.0;
+  int persistent = 0;
 };
 using ScheduleCache = std::vector<std::pair<std::string, Schedule>>;
 
@@ -1370,11 +1508,12 @@ static ScheduleCache cache_read(const char* path) {
     int end = 0;
     ok = q != std::string::npos &&
          std::sscanf(s.c_str() + q + 1,
-                     " : {\"fuse_vertex\": %d, \"block\": %d, \"edge_cells\": %d, \"ms_per_step\": %lf }%n", &t.fuse,
-                     &t.block, &t.cells, &t.ms, &end) == 4 &&
+                     " : {\"fuse_vertex\": %d, \"block\": %d, \"edge_cells\": %d, \"persistent\": %d, "
+                     "\"ms_per_step\": %lf }%n",
+                     &t.fuse, &t.block, &t.cells, &t.persistent, &t.ms, &end) == 5 &&
          end > 0 && s.c_str()[q + 1 + end] == '\0' && (t.fuse == 0 || t.fuse == 1) &&
          (t.block == 64 || t.block == 128 || t.block == 256) && (t.cells == 0 || t.cells == 1) &&
-         std::isfinite(t.ms) && t.ms >= 0.0;
+         t.persistent >= 0 && t.persistent <= 16 && std::isfinite(t.ms) && t.ms >= 0.0;
     if (ok) v.emplace_back(s.substr(1, q - 1), t);
   }
   std::fclose(f);
@@ -1389,8 +1528,10 @@ static void cache_write(const char* path, const ScheduleCache& v) {
   std::fprintf(f, "{\n");
   for (size_t k = 0; k < v.size(); ++k) {
     const Schedule& t = v[k].second;
-    std::fprintf(f, "\"%s\": {\"fuse_vertex\": %d, \"block\": %d, \"edge_cells\": %d, \"ms_per_step\": %.6f}%s\n",
-                 v[k].first.c_str(), t.fuse, t.block, t.cells, t.ms, k + 1 < v.size() ? "," : "");
+    std::fprintf(f,
+                 "\"%s\": {\"fuse_vertex\": %d, \"block\": %d, \"edge_cells\": %d, \"persistent\": %d, "
+                 "\"ms_per_step\": %.6f}%s\n",
+                 v[k].first.c_str(), t.fuse, t.block, t.cells, t.persistent, t.ms, k + 1 < v.size() ? "," : "");
   }
   std::fprintf(f, "}\n");
   const bool closed = std::fclose(f) == 0;
@@ -1584,6 +1725,7 @@ int fblts_get_state(fblts_solver* s, double* h, double* u, int32_t on_device) {
   return guarded([&] {
     if (!s || (!h && !u)) throw Err(FBLTS_EINVAL, "NULL argument");
     if (!s->have_state) throw Err(FBLTS_ESTATE, "no state");
+    check_persist(s->persist, s->stream);
     state_out(*s->unit, s->stage_h, s->stage_u, h, u, 0, on_device != 0, s->stream);
     return FBLTS_OK;
   });
@@ -1815,6 +1957,9 @@ int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
       if (value && (!s->have_regions || s->unit->pm.kite_weights == 0))
         throw Err(FBLTS_EINVAL, "edge-via-cells needs set_regions first and kite-derived TRiSK weights");
       s->opt.edge_cells = value != 0;
+    } else if (option == FBLTS_OPT_PERSISTENT) {
+      if (value < 0 || value > 16) throw Err(FBLTS_EINVAL, "persistent: 0 (off) or blocks per compute unit, 1..16");
+      s->opt.persistent = value;
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
@@ -1847,6 +1992,7 @@ int fblts_diagnostics(fblts_solver* s, fblts_diag* out) {
   return guarded([&] {
     if (!s || !out) throw Err(FBLTS_EINVAL, "NULL argument");
     if (!s->have_state) throw Err(FBLTS_ESTATE, "no state");
+    check_persist(s->persist, s->stream);
     std::vector<double> q;
     diag_of(*s->unit, s->P, s->diag_partial, s->diag_out, s->stream, q);
     const int rc = fill_diag(q.data(), s->time, s->step, out);
@@ -1861,6 +2007,7 @@ int fblts_diagnostics_noalloc(fblts_solver* s, fblts_diag* out) {
     if (!s->have_state) throw Err(FBLTS_ESTATE, "no state");
     if (s->device < 0 || s->device >= kMaxDevices || !g_scratch_dev[s->device])
       throw Err(FBLTS_EDEVICE, "the scratch array is not set up on the solver's device");
+    check_persist(s->persist, s->stream);
     MeshUnit& u = *s->unit;
     const int nb = diag_blocks(u.dm.md);
     const size_t part = (size_t)kDiagQ * nb * u.st.nm;
@@ -2142,6 +2289,7 @@ int fblts_ensemble_create(const fblts_mesh* const* meshes, const int8_t* const* 
       e->units.push_back(std::move(u));
     }
     e->passes = merge_passes(units);
+    ++e->version;
     // zero drag until set
     for (auto& u : e->units) launch_fill(u->st.cd.as<double>(), 0.0, (long)u->pm.N * u->st.nm, e->stream);
     hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
@@ -2187,6 +2335,7 @@ int fblts_ensemble_get_member(fblts_ensemble* e, int32_t mesh, int32_t member, d
     if (!e || mesh < 0 || mesh >= (int)e->units.size()) throw Err(FBLTS_EINVAL, "bad mesh index");
     MeshUnit& U = *e->units[mesh];
     if (member < 0 || member >= U.st.nm) throw Err(FBLTS_EINVAL, "bad member index");
+    check_persist(e->persist, e->stream);
     state_out(U, e->stage_h, e->stage_u, h, u, member, on_device != 0, e->stream);
     return FBLTS_OK;
   });
@@ -2214,6 +2363,7 @@ int fblts_ensemble_set_cyclone(fblts_ensemble* e, int32_t mesh, int32_t member, 
       units.push_back(u.get());
     }
     e->passes = merge_passes(units);
+    ++e->version;
     e->graphs.reset();
     launch_cyclone(U.st.cyc, e->stream);
     hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
@@ -2248,6 +2398,9 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
         if (value && u->pm.kite_weights == 0)
           throw Err(FBLTS_EINVAL, "edge-via-cells needs kite-derived TRiSK weights on every mesh");
       e->opt.edge_cells = value != 0;
+    } else if (option == FBLTS_OPT_PERSISTENT) {
+      if (value < 0 || value > 16) throw Err(FBLTS_EINVAL, "persistent: 0 (off) or blocks per compute unit, 1..16");
+      e->opt.persistent = value;
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
@@ -2268,6 +2421,7 @@ int fblts_ensemble_step(fblts_ensemble* e, int32_t n) {
 int fblts_ensemble_diagnostics(fblts_ensemble* e, fblts_diag* out) {
   return guarded([&] {
     if (!e || !out) throw Err(FBLTS_EINVAL, "NULL argument");
+    check_persist(e->persist, e->stream);
     int rc = FBLTS_OK;
     size_t k = 0;
     for (auto& u : e->units) {
@@ -2359,21 +2513,39 @@ int fblts_autotune(void* handle, int32_t handle_kind, int32_t steps, int32_t rep
       };
       if (s) s->timing.on = false;
       best.ms = std::numeric_limits<double>::infinity();
+      // search order: the graph-replayed per-pass schedules, then the
+      // persistent launch (fused q_v or not; its blocks are kBlock threads),
+      // then the momentum pass through the cells' edge lists
+      struct Cand {
+        int fuse, bs, cells, persistent;
+      };
+      std::vector<Cand> cands;
+      for (int fuse = 1; fuse >= 0; --fuse)
+        for (int bs : {256, 128, 64}) cands.push_back({fuse, bs, 0, 0});
+      int coop = 0;
+      hip_check(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s ? s->device : 0),
+                "hipDeviceGetAttribute");
+      if (coop)
+        for (int fuse = 1; fuse >= 0; --fuse)
+          for (int per_cu : {1, 4}) cands.push_back({fuse, kBlock, 0, per_cu});
+      if (cells_ok)
+        for (int fuse = 1; fuse >= 0; --fuse)
+          for (int bs : {256, 128, 64}) cands.push_back({fuse, bs, 1, 0});
       try {
-        for (int cells = 0; cells <= 1; ++cells)
-          for (int fuse = 1; fuse >= 0; --fuse)
-            for (int bs : {256, 128, 64}) {
-              if (cells && !cells_ok) continue;
-              opt.fuse_q = fuse != 0;
-              opt.block = bs;
-              opt.edge_cells = cells != 0;
-              graph_on = true;
-              rebuild();
-              const double ms = time_schedule(st, steps, repeats, run);
-              if (ntried < max_tried) tried[ntried] = fblts_schedule{fuse, bs, cells, 0, ms};
-              ++ntried;
-              if (ms < best.ms) best = Schedule{fuse, bs, cells, ms};
-            }
+        for (const Cand& c : cands) {
+          opt.fuse_q = c.fuse != 0;
+          opt.block = c.bs;
+          opt.edge_cells = c.cells != 0;
+          opt.persistent = c.persistent;
+          graph_on = true;
+          rebuild();
+          const double ms = time_schedule(st, steps, repeats, run);
+          if (s) check_persist(s->persist, st);
+          else check_persist(e->persist, st);
+          if (ntried < max_tried) tried[ntried] = fblts_schedule{c.fuse, c.bs, c.cells, 0, ms, c.persistent};
+          ++ntried;
+          if (ms < best.ms) best = Schedule{c.fuse, c.bs, c.cells, ms, c.persistent};
+        }
       } catch (...) {
         try {
           hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -2387,6 +2559,7 @@ int fblts_autotune(void* handle, int32_t handle_kind, int32_t steps, int32_t rep
     opt.fuse_q = best.fuse != 0;
     opt.block = best.block;
     opt.edge_cells = best.cells != 0;
+    opt.persistent = best.persistent;
     rebuild();
     if (!hit && cache_json_path) {
       bool replaced = false;
@@ -2398,7 +2571,7 @@ int fblts_autotune(void* handle, int32_t handle_kind, int32_t steps, int32_t rep
       if (!replaced) cache.emplace_back(key, best);
       cache_write(cache_json_path, cache);
     }
-    if (out) *out = fblts_schedule{best.fuse, best.block, best.cells, hit ? 1 : 0, best.ms};
+    if (out) *out = fblts_schedule{best.fuse, best.block, best.cells, hit ? 1 : 0, best.ms, best.persistent};
     if (n_tried) *n_tried = ntried;
     return FBLTS_OK;
   });

@@ -220,11 +220,13 @@ def test_autotuner_restores_state_and_picks_a_candidate(cvt, tmp_path):
     d0 = s.diagnostics()
     path = str(tmp_path / "tune.json")
     choice = autotune.autotune(s, steps=5, repeats=1, cache_path=path)
-    assert (choice["fuse_vertex"], choice["block"], choice["edge_cells"]) in autotune.CANDIDATES
+    key = lambda c: (c["fuse_vertex"], c["block"], c["edge_cells"], c["persistent"])   # noqa: E731
+    assert key(choice) in autotune.CANDIDATES
     assert choice["from_cache"] == 0 and choice["ms_per_step"] > 0
-    timed = [(c["fuse_vertex"], c["block"], c["edge_cells"]) for c in choice["candidates"]]
-    # every schedule without the cells variant, then (where the mesh allows it) every one with it
-    assert len(timed) in (6, 12) and timed == autotune.CANDIDATES[:len(timed)]
+    timed = [key(c) for c in choice["candidates"]]
+    # every per-pass schedule, the persistent launch, then (where the mesh
+    # allows it) every schedule of the cells variant
+    assert len(timed) in (10, 16) and timed == autotune.CANDIDATES[:len(timed)]
     assert choice["ms_per_step"] == min(c["ms_per_step"] for c in choice["candidates"])
     h1, u1 = s.get_state()
     assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
@@ -235,8 +237,7 @@ def test_autotuner_restores_state_and_picks_a_candidate(cvt, tmp_path):
     assert len(entries) == 1 and list(entries.values())[0]["block"] == choice["block"]
     again = autotune.autotune(s, cache_path=path)
     assert again["from_cache"] == 1 and again["candidates"] == []
-    assert (again["fuse_vertex"], again["block"], again["edge_cells"]) == (
-        choice["fuse_vertex"], choice["block"], choice["edge_cells"])
+    assert key(again) == key(choice)
     # stepping after tuning continues the trajectory bit for bit
     ref = _solver(fm, w)
     ref.step(5)

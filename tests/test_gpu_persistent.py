@@ -1,0 +1,125 @@
+"""The persistent launch (FBLTS_OPT_PERSISTENT): each coarse step's runs of
+stencil, prediction and assembly passes execute in one cooperative launch with
+grid-wide barriers between passes.  Every pass evaluates the same items with
+the same code as its own launch, so the trajectories must equal the
+graph-replayed per-pass launches bit for bit -- for FB-LTS, the global
+schemes (RK4's combination passes launch on their own between cooperative
+runs), the operator splittings, the moving storm (its wind and clock passes
+launch on their own), and multi-mesh ensembles (segment tables, shared-slot
+momentum pass)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import paper_2405_10505_amd as F
+from paper_2405_10505_amd import autotune
+from paper_2405_10505_amd.inputs import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cvt():
+    w = workloads.small_cvt()
+    return w, F.Mesh(w.mesh)
+
+
+def _run(fm, w, steps, persistent, fuse=1, scheme=F.SCHEME_FBLTS, split=0, physics=None, storm=None,
+         cells=0):
+    kw = dict(physics=physics) if physics is not None else dict(linear=w.linear)
+    # global schemes at the fine step (the coarse step exceeds their stability limit)
+    dt = w.dt if scheme == F.SCHEME_FBLTS else w.dt / w.M
+    s = F.Solver(fm, dt, M=w.M if scheme == F.SCHEME_FBLTS else 1, scheme=scheme, split=split, **kw)
+    if scheme == F.SCHEME_FBLTS:
+        s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+    else:
+        s.set_regions(np.full(w.mesh.n_cells, 3, np.int8), binary=False)
+    if w.cd is not None and not w.linear and physics != F.PHYS_GRAVITY_WAVE:
+        s.set_drag(w.cd)
+    s.set_state(w.h0, w.u0)
+    if storm is not None:
+        s.set_cyclone(w.mesh.x_edge, w.mesh.normal_edge, **storm.cyclone_kwargs())
+    autotune.apply(s, dict(fuse_vertex=fuse, block=64 if not persistent else 256, edge_cells=cells,
+                           persistent=persistent))
+    s.step(steps)
+    h, u = s.get_state()
+    return h, u, s.diagnostics()
+
+
+@pytest.mark.parametrize("per_cu", [1, 4])
+@pytest.mark.parametrize("fuse", [1, 0])
+@pytest.mark.parametrize("scheme", [F.SCHEME_FBLTS, F.SCHEME_FBRK32, F.SCHEME_RK4])
+def test_persistent_equals_per_pass_launches(cvt, fuse, scheme, per_cu):
+    """per_cu: blocks of the cooperative launch per compute unit."""
+    w, fm = cvt
+    h0, u0, d0 = _run(fm, w, 7, 0, fuse, scheme)
+    h1, u1, d1 = _run(fm, w, 7, per_cu, fuse, scheme)
+    assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
+    assert d0["mass"] == d1["mass"] and d1["n_nonfinite"] == 0
+
+
+def test_persistent_linear_inertia_gravity_wave():
+    w = workloads.config1()
+    fm = F.Mesh(w.mesh)
+    h0, u0, _ = _run(fm, w, 9, 0)
+    h1, u1, _ = _run(fm, w, 9, 1)
+    assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
+
+
+@pytest.mark.parametrize("split", [1, 2])
+def test_persistent_operator_splitting(cvt, split):
+    w, fm = cvt
+    h0, u0, _ = _run(fm, w, 5, 0, split=split)
+    h1, u1, _ = _run(fm, w, 5, 1, split=split)
+    assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
+
+
+def test_persistent_gravity_wave_system(cvt):
+    w, fm = cvt
+    h0, u0, _ = _run(fm, w, 5, 0, physics=F.PHYS_GRAVITY_WAVE)
+    h1, u1, _ = _run(fm, w, 5, 1, physics=F.PHYS_GRAVITY_WAVE)
+    assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
+
+
+@pytest.mark.parametrize("cells", [0, 1])
+def test_persistent_sphere_with_moving_storm(cells):
+    """Wind and clock passes (and, with cells = 1, the momentum pass through
+    the cells' edge lists) launch on their own between cooperative runs."""
+    w = workloads.small_sphere()
+    fm = F.Mesh(w.mesh)
+    storm = dataclasses.replace(w.meta["storm"], rm=400e3)
+    h0, u0, _ = _run(fm, w, 6, 0, storm=storm, cells=cells)
+    h1, u1, _ = _run(fm, w, 6, 1, storm=storm, cells=cells)
+    assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
+
+
+@pytest.mark.parametrize("nms", [[4, 2], [16, 32]])
+def test_persistent_ensemble_equals_per_pass_launches(nms):
+    ws = [workloads.small_cvt(n=2000, seed=12), workloads.small_cvt(n=1500, seed=13)]
+    dt = min(w.dt for w in ws)
+    fms = [F.Mesh(w.mesh) for w in ws]
+    out = []
+    for persistent in (0, 1):
+        ens = F.Ensemble(fms, [np.where(w.fine_mask, 0, 1) for w in ws], nms, dt, M=4, linear=False)
+        for k, (w, nm) in enumerate(zip(ws, nms)):
+            fields, cds = workloads.ensemble_members(w.mesh, nm, seed_ssh0=700 + 50 * k)
+            for m in range(nm):
+                ens.set_member(k, m, w.h0 + fields[m], w.u0, np.full(w.mesh.n_cells, cds[m]))
+        autotune.apply(ens, dict(fuse_vertex=0, block=256, edge_cells=0, persistent=persistent))
+        ens.step(5)
+        out.append([ens.get_member(k, m) for k, nm in enumerate(nms) for m in (0, nm - 1)])
+    for (ha, ua), (hb, ub) in zip(*out):
+        assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
+
+
+def test_autotuner_times_the_persistent_launch(cvt):
+    w, fm = cvt
+    s = F.Solver(fm, w.dt, M=w.M, linear=False)
+    s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+    s.set_drag(w.cd)
+    s.set_state(w.h0, w.u0)
+    choice = autotune.autotune(s, steps=4, repeats=1)
+    timed = [(c["fuse_vertex"], c["block"], c["edge_cells"], c["persistent"]) for c in choice["candidates"]]
+    assert {(1, 256, 0, 1), (0, 256, 0, 1), (1, 256, 0, 4), (0, 256, 0, 4)} <= set(timed)
+    assert all(c["ms_per_step"] > 0 for c in choice["candidates"])
