@@ -573,6 +573,9 @@ def main():
                              samples_ms=[x / ks * 1e3 for x in smp])
         rate_fb = res["fbrk32_own_limit"]["sim_seconds_per_wall_second"]
         rate_rk4 = res["rk4_own_limit"]["sim_seconds_per_wall_second"]
+        # every FB-LTS leg runs the launch schedule tuned for this workload
+        w._schedule = dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"],
+                           edge_cells=tune.get("edge_cells", 0), persistent=tune.get("persistent", 0))
         # the recipe's fine set and M with its own largest stable coarse step
         dt_lts = largest_stable_dt(F, w, F.SCHEME_FBLTS, w.dt, split=args.split)
         g = make_solver(F, w, F.SCHEME_FBLTS, dt_lts, w.M, split=args.split)
@@ -584,10 +587,8 @@ def main():
             w.M, dt_lts, dt_lts / w.M, recipe["speedup_vs_fbrk32"], recipe["speedup_vs_rk4"]))
         sweep = paper = fastest = None
         if args.split == 0 and args.workload == "cvt50k":
-            w._schedule = dict(fuse_vertex=tune["fuse_vertex"], block=tune["block"],
-                               edge_cells=tune.get("edge_cells", 0), persistent=tune.get("persistent", 0))
             sweep, paper, fastest = lts_sweep(F, torch, w, rate_fb, rate_rk4, dt_fb, ks, args.reps, args.split)
-            w._schedule = None
+        w._schedule = None
         chosen = paper or recipe
         comp = dict(fblts=chosen, fblts_recipe=recipe, lts_sweep=sweep, fastest_of_sweep=fastest,
                     **res,

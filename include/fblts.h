@@ -275,8 +275,9 @@ int fblts_set_graph(fblts_solver* s, int32_t enable);
  *     launch (hipLaunchCooperativeKernel; k blocks of 256 threads per compute
  *     unit, at most as many as stay resident, whatever FBLTS_OPT_BLOCK says;
  *     a grid-wide barrier between passes); forcing and RK4-combination passes, and the
- *     EDGE_CELLS momentum pass, launch on their own between such runs.  Steps
- *     then launch directly (no graph).  A barrier that gives up waiting (only
+ *     EDGE_CELLS momentum pass, launch on their own between such runs; with
+ *     graphs enabled the cooperative launches are captured and replayed like
+ *     the per-pass ones.  A barrier that gives up waiting (only
  *     if the device cannot keep the grid resident) makes the next state read
  *     or diagnostics fail with FBLTS_EDEVICE.  Default 0.
  * Errors: FBLTS_EINVAL for an unknown option or value, or EDGE_CELLS on a

@@ -1370,14 +1370,18 @@ static int fill_diag(const double* q, double time, int64_t step, fblts_diag* o) 
 static void solver_run(fblts_solver* s, int n) {
   MeshUnit& u = *s->unit;
   if (s->opt.persistent && !s->timing.on) {
-    // one cooperative launch per run of passes; no graph (timing launches
-    // every pass on its own)
+    // one cooperative launch per run of passes (timing launches every pass on
+    // its own); the program is built before any capture
     if (s->persist.version != u.version || s->persist.per_cu != s->opt.persistent) {
       build_persist(u.passes, s->drag_on, u.st.has_wind, s->opt.persistent, s->persist, s->stream);
       s->persist.version = u.version;
       s->persist.per_cu = s->opt.persistent;
+      s->drop_graph();
     }
-    for (int k = 0; k < n; ++k) run_persist(u.passes, s->persist, s->drag_on, u.st.has_wind, s->stream);
+    auto one = [&] { run_persist(u.passes, s->persist, s->drag_on, u.st.has_wind, s->stream); };
+    if (s->graph_on) s->graphs.run(s->stream, n, s->opt.graph_steps, one);
+    else
+      for (int k = 0; k < n; ++k) one();
   } else if (s->graph_on && !s->timing.on) {
     s->graphs.run(s->stream, n, s->opt.graph_steps,
                   [&] { run_passes(u.passes, s->drag_on, u.st.has_wind, s->stream, nullptr); });
@@ -1397,8 +1401,12 @@ static void ensemble_run(fblts_ensemble* e, int n) {
       build_persist(e->passes, nl, e->units[0]->st.has_wind, e->opt.persistent, e->persist, e->stream);
       e->persist.version = e->version;
       e->persist.per_cu = e->opt.persistent;
+      e->graphs.reset();
     }
-    for (int k = 0; k < n; ++k) run_persist(e->passes, e->persist, nl, e->units[0]->st.has_wind, e->stream);
+    auto one = [&] { run_persist(e->passes, e->persist, nl, e->units[0]->st.has_wind, e->stream); };
+    if (e->graph_on) e->graphs.run(e->stream, n, e->opt.graph_steps, one);
+    else
+      for (int k = 0; k < n; ++k) one();
   } else if (e->graph_on) {
     e->graphs.run(e->stream, n, e->opt.graph_steps,
                   [&] { run_passes(e->passes, nl, e->units[0]->st.has_wind, e->stream, nullptr); });

@@ -123,3 +123,22 @@ def test_autotuner_times_the_persistent_launch(cvt):
     timed = [(c["fuse_vertex"], c["block"], c["edge_cells"], c["persistent"]) for c in choice["candidates"]]
     assert {(1, 256, 0, 1), (0, 256, 0, 1), (1, 256, 0, 4), (0, 256, 0, 4)} <= set(timed)
     assert all(c["ms_per_step"] > 0 for c in choice["candidates"])
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_persistent_launch_direct_and_graph_replayed(cvt, graph):
+    """The cooperative launches replay from captured hipGraphs (G-step and
+    one-step graphs) with the same bits as direct launches and as the
+    per-pass launches."""
+    w, fm = cvt
+    h0, u0, _ = _run(fm, w, 11, 0)
+    s = F.Solver(fm, w.dt, M=w.M, linear=False)
+    s.set_regions(np.where(w.fine_mask, 0, 1), binary=True)
+    s.set_drag(w.cd)
+    s.set_state(w.h0, w.u0)
+    s.set_option(F.OPT_PERSISTENT, 1)
+    s.set_option(F.OPT_GRAPH_STEPS, 4)
+    s.set_graph(graph)
+    s.step(11)
+    h1, u1 = s.get_state()
+    assert np.array_equal(h0, h1) and np.array_equal(u0, u1)
