@@ -296,11 +296,20 @@ def lts_sweep(F, torch, w, rate_fb, rate_rk4, dt_fb, steps, reps, split=0):
         log("LTS M=%d margin=%.2f: fine %d, dt %.2f/%.2f s, %.4f ms/step, %.2fx FB-RK(3,2), %.2fx RK4 (%.1fs)" % (
             M, margin, rows[-1]["n_fine"], dtc, dtc / M, rows[-1]["ms_per_step"], rows[-1]["speedup_vs_fbrk32"],
             rows[-1]["speedup_vs_rk4"], time.perf_counter() - t0))
+    paper, fastest = paper_choice(rows)
+    return rows, paper, fastest
+
+
+def paper_choice(rows, tol=0.02):
+    """The paper's order (Sec. 4.1) applied to searched (M, margin) rows: the
+    largest stable fine step first (rows within tol of it count as equal), then
+    the largest M among them (the larger margin on a tie); and the row with the
+    fastest time to solution."""
     best_f = max(r["dt_fine"] for r in rows)
-    near = [r for r in rows if r["dt_fine"] >= 0.98 * best_f]
+    near = [r for r in rows if r["dt_fine"] >= (1.0 - tol) * best_f]
     paper = max(near, key=lambda r: (r["M"], r["margin"]))
     fastest = max(rows, key=lambda r: r["sim_seconds_per_wall_second"])
-    return rows, paper, fastest
+    return paper, fastest
 
 
 # ------------------------------------------------------------ extra blocks

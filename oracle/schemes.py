@@ -17,7 +17,7 @@ Test infrastructure only (see the package header).
   (step 4, eq. ``if_correction``) as h^n + (dt/M) * (sum over k of the
   stage-2 tendencies, accumulated in increasing k).
 
-Readings (listed in the design doc): the prediction coefficients are FP64
+Readings where the paper leaves a choice: the prediction coefficients are FP64
 quotients of integers (k/M, (M-k)/M, 1/M, (M-k-1)/M); velocity stage 3 of the
 coarse advancement is also evaluated on interface two, where it is unused.
 

@@ -37,3 +37,21 @@ def test_cpu_baseline_reports_one_thread_and_all_cores():
         assert a["cores"] == ncpu and a["value"] > 0
     else:
         pytest.skip("one host core")
+
+
+def test_paper_time_step_order():
+    """Largest fine step first (within 2%), then the largest M; the fastest
+    row is reported separately."""
+    b = _bench()
+    rows = [dict(M=4, margin=1.0, dt_fine=10.4, sim_seconds_per_wall_second=194.0),
+            dict(M=3, margin=0.8, dt_fine=13.2, sim_seconds_per_wall_second=265.0),
+            dict(M=2, margin=0.65, dt_fine=14.55, sim_seconds_per_wall_second=258.0),
+            dict(M=4, margin=0.65, dt_fine=14.49, sim_seconds_per_wall_second=230.0),
+            dict(M=6, margin=0.65, dt_fine=14.43, sim_seconds_per_wall_second=241.0),
+            dict(M=8, margin=0.8, dt_fine=12.7, sim_seconds_per_wall_second=200.0)]
+    paper, fastest = b.paper_choice(rows)
+    assert (paper["M"], paper["margin"]) == (6, 0.65)
+    assert (fastest["M"], fastest["margin"]) == (3, 0.8)
+    # a fine step 3% below the best is not "equal": M = 8 at 12.7 s never wins
+    paper, _ = b.paper_choice(rows[:3] + [dict(M=8, margin=1.0, dt_fine=14.1, sim_seconds_per_wall_second=1.0)])
+    assert (paper["M"], paper["margin"]) == (2, 0.65)

@@ -288,7 +288,7 @@ def _bloch(m, om, kvec, ph):
 def test_discrete_inertia_gravity_frequency_and_geostrophic_modes():
     """Configuration 1's mesh and wavenumber (2, 1): the Bloch eigenvalues of the
     linear TRiSK operator are {0, 0, +-i omega_d} with omega_d = 4.46348e-3 1/s
-    (the survey's independent computation; the continuous f-plane value is
+    (an independent Bloch computation done before this test; the continuous f-plane value is
     4.49233e-3), and the two zero-frequency (geostrophically balanced) modes are
     steady states of FB-RK(3,2)."""
     from oracle import schemes
