@@ -426,7 +426,7 @@ def _oracle_run(w, steps, split, limit_s=20.0):
     t0 = time.perf_counter()
     n = 0
     while n < steps:
-        wind = storm.edge_components(w.mesh, n * w.dt) if storm is not None else None
+        wind = storm.edge_forcing(w.mesh, n * w.dt) if storm is not None else None
         ph = trisk.Physics(linear=w.linear, cd=w.cd if not w.linear else None, wind=wind)
         u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab, split=split)
         n += 1

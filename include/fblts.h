@@ -198,11 +198,16 @@ int fblts_set_state(fblts_solver* s, const double* h, const double* u, int32_t o
 int fblts_get_state(fblts_solver* s, double* h, double* u, int32_t on_device);
 /* Per-cell quadratic bottom drag coefficient C_D[n_cells] (nonlinear physics). */
 int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device);
-/* Wind at edge points, normal and tangential components (m/s), held fixed
- * until the next call; enables the wind-stress term of eq. hurricane_model.
- * Pass NULL to disable. */
+/* Wind forcing at edge points, held fixed until the next call; enables the
+ * wind-stress term C_W |u_W - u| (u_W - u) / h of eq. hurricane_model:
+ *   wind_normal[n_edges], wind_tangential[n_edges]: the components of u_W
+ *     (m/s) along n_e and t_e;
+ *   wind_coef[n_edges]: the wind-stress coefficient C_W at each edge
+ *     (dimensionless, kinematic: air stress over water density); the paper
+ *     takes it from Garratt's drag law, which the caller applies.
+ * Caller order, host or device (on_device).  Pass NULL arrays to disable. */
 int fblts_set_wind(fblts_solver* s, const double* wind_normal, const double* wind_tangential,
-                   int32_t on_device);
+                   const double* wind_coef, int32_t on_device);
 
 /* Moving analytic cyclone as the wind of the wind-stress term of eq.
  * hurricane_model (the paper forces it with observed hurricane winds; this is
@@ -219,7 +224,10 @@ int fblts_set_wind(fblts_solver* s, const double* wind_normal, const double* win
  * held for the whole step (coarse advancement and every fine substep); the
  * step counter lives on the device, so captured graphs replay correctly.
  * Components at edges: W.n_e and W.(x_e cross n_e) (the tangent convention of
- * the mesh, t_e = k x n_e).
+ * the mesh, t_e = k x n_e).  With the wind the device also forms the
+ * coefficient C_W = (rho_air / rho_water)(0.75 + 0.067 |W|) 1e-3 at each edge
+ * (the kinematic form of Garratt's 10 m drag law; rho_air and rho_water from
+ * the solver's parameters), part of the same forcing evaluation.
  *   x_edge[3*n_edges]: edge positions (any length; normalised), host, caller order;
  *   n_edge[3*n_edges]: unit edge normals n_e, host, caller order.
  * Both are copied.  c = NULL disables the wind (as does fblts_set_wind).
@@ -239,10 +247,11 @@ typedef struct fblts_cyclone {
   double t0;          /* time of the first step's wind (s) */
 } fblts_cyclone;
 int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_edge, const double* n_edge);
-/* Copy the wind components the last step used (or the first step will use,
- * right after fblts_set_cyclone) to host arrays in caller order.
+/* Copy the wind forcing the last step used (or the first step will use,
+ * right after fblts_set_cyclone) to host arrays in caller order: the two
+ * components and C_W (wind_coef may be NULL).
  * Errors: FBLTS_ESTATE when no wind is set. */
-int fblts_get_wind(fblts_solver* s, double* wind_normal, double* wind_tangential);
+int fblts_get_wind(fblts_solver* s, double* wind_normal, double* wind_tangential, double* wind_coef);
 
 /* Advance n coarse steps (async).  Errors: FBLTS_ESTATE before set_state. */
 int fblts_step(fblts_solver* s, int32_t n_coarse_steps);
@@ -278,8 +287,10 @@ int fblts_set_graph(fblts_solver* s, int32_t enable);
  *     EDGE_CELLS momentum pass, launch on their own between such runs; with
  *     graphs enabled the cooperative launches are captured and replayed like
  *     the per-pass ones.  A barrier that gives up waiting (only
- *     if the device cannot keep the grid resident) makes the next state read
- *     or diagnostics fail with FBLTS_EDEVICE.  Default 0.
+ *     if the device cannot keep the grid resident, e.g. while another
+ *     solver's persistent launch or other work occupies the GPU on another
+ *     stream) makes the next state read or diagnostics fail with
+ *     FBLTS_EDEVICE.  Default 0.
  * Errors: FBLTS_EINVAL for an unknown option or value, or EDGE_CELLS on a
  * mesh whose weights are not the kite-fraction walks. */
 enum {

@@ -25,7 +25,8 @@ cited by section / equation label:
 Parity pins: see the module headers.  The quadratic drag and wind-stress terms
 (eq. ``hurricane_model``) follow a reading of the paper.  Their vector laws are
 pinned by closed forms for uniform flow (tendencies on the regular hexagon, and
-an inertial oscillation with quadratic drag).  Parity unpinned: the wind drag
-coefficient C_W(|u_W|) and the edge value of a varying C_D.
+an inertial oscillation with quadratic drag), the edge value of a varying C_D
+by a linear field on the hexagon.  The coefficients C_D (per cell) and C_W (per
+edge, from the wind through Garratt's law) are inputs, like the wind itself.
 """
 from . import trisk, schemes, regions  # noqa: F401

@@ -28,8 +28,10 @@ regular hexagonal mesh; curl(grad) = 0; the energy identity
 sum l d F Phi + sum A B Psi = 0; B and F as the gradients of the discrete
 energy; constant-PV compatibility of the vorticity flux; the linear operator's
 energy skew-symmetry; the drag and wind-stress vector laws for uniform flow
-and wind on the regular hexagon, and drag's energy sign.  Parity unpinned: the
-wind drag coefficient C_W(|u_W|) and the edge mean of a varying C_D.
+and wind on the regular hexagon, and drag's energy sign; the edge value of a
+drag coefficient that varies linearly in space (exact at the edge midpoints of
+the hexagon).  The wind-stress coefficient C_W arrives with the wind as forcing
+data per edge (the paper takes it from Garratt's law), like C_D per cell.
 """
 from __future__ import annotations
 
@@ -137,15 +139,14 @@ class Physics:
     z_b = -H; the system of eq. ``grav_wave_model`` (Section 2.3).
     """
 
-    def __init__(self, linear=False, g=9.81, cd=None, wind=None, rho_air=1.15, rho_w=1000.0,
-                 gravity_wave=False):
+    def __init__(self, linear=False, g=9.81, cd=None, wind=None, gravity_wave=False):
         self.linear = linear
         self.gravity_wave = gravity_wave
         self.g = g
         self.cd = cd            # per-cell quadratic drag coefficient C_D (nonlinear only)
-        self.wind = wind        # (uW_normal[E], uW_tangential[E]) at edges (nonlinear only)
-        self.rho_air = rho_air
-        self.rho_w = rho_w
+        # wind forcing at edges (nonlinear only): (uW_normal[E], uW_tangential[E],
+        # C_W[E]), the wind and the wind-stress coefficient of eq. hurricane_model
+        self.wind = wind
 
 
 def psi(om, u, h, ph):
@@ -184,8 +185,7 @@ def forcing_terms(om, u, he, ph):
         speed = np.sqrt(u * u + up * up)
         out = out - cde * speed * u / he
     if ph.wind is not None:
-        wn, wt = ph.wind
-        cw = wind_drag_coefficient(np.sqrt(wn * wn + wt * wt), ph)
+        wn, wt, cw = ph.wind
         rel = np.sqrt((wn - u) ** 2 + (wt - up) ** 2)
         out = out + cw * rel * (wn - u) / he
     return out
@@ -214,16 +214,10 @@ def phi(om, u, h, ph):
             speed = np.sqrt(u * u + up * up)
             out = out - cde * speed * u / he
         if ph.wind is not None:
-            wn, wt = ph.wind
-            cw = wind_drag_coefficient(np.sqrt(wn * wn + wt * wt), ph)
+            wn, wt, cw = ph.wind
             rel = np.sqrt((wn - u) ** 2 + (wt - up) ** 2)
             out = out + cw * rel * (wn - u) / he
     return out
-
-
-def wind_drag_coefficient(speed, ph):
-    """C_W = (rho_air/rho_w)(0.75 + 0.067 |u_W|) 1e-3 (a Garratt-type law)."""
-    return (ph.rho_air / ph.rho_w) * (0.75 + 0.067 * speed) * 1e-3
 
 
 # ----------------------------------------------------------------------------

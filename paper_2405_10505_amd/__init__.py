@@ -106,9 +106,9 @@ _SIGS = {
     "fblts_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_set_drag": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
-    "fblts_set_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "fblts_set_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "fblts_set_cyclone": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
-    "fblts_get_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fblts_get_wind": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fblts_ensemble_set_cyclone": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fblts_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "fblts_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -348,10 +348,14 @@ class Solver:
         p, d, k = _ptr(cd, np.float64, self.mesh.n_cells, "cd")
         _check(lib().fblts_set_drag(self.handle, p, d))
 
-    def set_wind(self, wn, wt):
+    def set_wind(self, wn, wt, cw):
+        """Fixed wind forcing at edges: components (m/s) and the wind-stress coefficient C_W."""
         pn, dn, kn = _ptr(wn, np.float64, self.mesh.n_edges, "wind_normal")
         pt, dt, kt = _ptr(wt, np.float64, self.mesh.n_edges, "wind_tangential")
-        _check(lib().fblts_set_wind(self.handle, pn, pt, dn))
+        pc, dc, kc = _ptr(cw, np.float64, self.mesh.n_edges, "wind_coef")
+        if not (dn == dt == dc):
+            raise ValueError("wind arrays must all be on the host or all on the device")
+        _check(lib().fblts_set_wind(self.handle, pn, pt, pc, dn))
 
     def set_cyclone(self, x_edge, n_edge, **storm):
         """Moving Holland cyclone as the wind-stress forcing (device-evaluated per coarse step)."""
@@ -363,10 +367,12 @@ class Solver:
         _check(lib().fblts_set_cyclone(self.handle, None, None, None))
 
     def get_wind(self):
+        """The wind forcing of the current step: (normal, tangential, C_W) at edges."""
         wn = np.empty(self.mesh.n_edges)
         wt = np.empty(self.mesh.n_edges)
-        _check(lib().fblts_get_wind(self.handle, wn.ctypes.data, wt.ctypes.data))
-        return wn, wt
+        wc = np.empty(self.mesh.n_edges)
+        _check(lib().fblts_get_wind(self.handle, wn.ctypes.data, wt.ctypes.data, wc.ctypes.data))
+        return wn, wt, wc
 
     def step(self, n=1):
         _check(lib().fblts_step(self.handle, int(n)))

@@ -121,8 +121,9 @@ struct EdgeSeg {
   const double* cd;        // per cell and member, or nullptr
   const double* wind_n;    // per edge and member, or nullptr
   const double* wind_t;
+  const double* wind_c;    // wind-stress coefficient C_W per edge and member
   const double* slow;      // fast pass: frozen slow tendency per edge and member, or nullptr
-  double c_dt, acc_w, rho_ratio;
+  double c_dt, acc_w;
 };
 
 // Interface-one prediction (eq. preds) over cells [c_begin,c_end) and edges
@@ -163,10 +164,12 @@ struct CycloneArgs {
   const double* n;          // [3][E] unit edge normals
   double* wn;               // [E*nm] W . n_e, members innermost
   double* wt;               // [E*nm] W . (x cross n_e)
+  double* wc;               // [E*nm] wind-stress coefficient C_W(|W|)
   const long long* clock;   // coarse steps since the storms were set
   const CycloneParams* p;   // [nm]
   int E, nm_log2;
   double dt;
+  double rho_ratio;         // rho_air / rho_water of the C_W law
 };
 
 template <class S>

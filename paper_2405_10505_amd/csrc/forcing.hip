@@ -14,12 +14,15 @@
 // f = 2 Omega z, swirl sign(f_c) V (x cross r_hat) (counter-clockwise about the
 // centre in the northern hemisphere; r_hat points away from the centre) plus a
 // translation part v_trans (V / V(Rm, f_c)) along the track direction projected
-// onto the tangent plane.  Outputs W.n_e and W.t_e with t_e = x cross n_e.
+// onto the tangent plane.  Outputs W.n_e and W.t_e with t_e = x cross n_e,
+// and the wind-stress coefficient of the forcing at the edge,
+// C_W = (rho_air / rho_water)(0.75 + 0.067 |W|) 1e-3 (Garratt's 10 m drag law
+// in kinematic form; |W| from the two tangent-plane components).
 //
 // Members are innermost (item = edge * nm + member), each member with its
 // own storm parameters, or calm air (zero wind) without a storm.
 //
-// Bytes per edge: 6 doubles read (unit position, unit normal), 2 per member written.
+// Bytes per edge: 6 doubles read (unit position, unit normal), 3 per member written.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -50,6 +53,10 @@ __device__ __forceinline__ double holland_speed(const CycloneParams& a, double r
   return sqrt(a.b / a.rho_air * s * a.dp * exp(-s) + rf2 * rf2) - 0.5 * r * fabs(f);
 }
 
+__device__ __forceinline__ double wind_coefficient(double rho_ratio, double wn, double wt) {
+  return rho_ratio * (0.75 + 0.067 * sqrt(wn * wn + wt * wt)) * 1e-3;
+}
+
 __global__ void __launch_bounds__(kBlock) k_cyclone(CycloneArgs a) {
   const long item = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= ((long)a.E << a.nm_log2)) return;
@@ -58,6 +65,7 @@ __global__ void __launch_bounds__(kBlock) k_cyclone(CycloneArgs a) {
   if (!P.enabled) {
     a.wn[item] = 0.0;
     a.wt[item] = 0.0;
+    a.wc[item] = wind_coefficient(a.rho_ratio, 0.0, 0.0);
     return;
   }
   // storm centre at this step: c0 rotated about the track axis
@@ -90,8 +98,10 @@ __global__ void __launch_bounds__(kBlock) k_cyclone(CycloneArgs a) {
   const V3 th = scale(1.0 / fmax(norm(tx), 1e-300), tx);
   const V3 W = axpy(vmax > 0.0 ? P.v_trans * V / vmax : 0.0, th, sw);
 
-  a.wn[item] = dot(W, n);
-  a.wt[item] = dot(W, cross(x, n));
+  const double wn = dot(W, n), wt = dot(W, cross(x, n));
+  a.wn[item] = wn;
+  a.wt[item] = wt;
+  a.wc[item] = wind_coefficient(a.rho_ratio, wn, wt);
 }
 
 __global__ void k_clock_tick(long long* clock) {

@@ -390,6 +390,7 @@ __device__ __forceinline__ void edge_body(const Launch<EdgeSeg>& L, const int b)
   const double u = (DRAG || WIND) ? S.Usrc[ee] : 0.0;
   const double cde = DRAG ? 0.5 * (S.cd[(long)c0 * nm + mem] + S.cd[(long)c1 * nm + mem]) : 0.0;
   const double wn = WIND ? S.wind_n[ee] : 0.0, wt = WIND ? S.wind_t[ee] : 0.0;
+  const double cw = WIND ? S.wind_c[ee] : 0.0;
   const bool upd = e >= S.upd_begin && e < S.upd_end, acc = e >= S.acc_begin && e < S.acc_end;
   const double u0 = upd ? S.U0[ee] : 0.0;
   const double acc0 = (acc && !S.acc_first) ? S.acc[ee] : 0.0;
@@ -439,7 +440,6 @@ __device__ __forceinline__ void edge_body(const Launch<EdgeSeg>& L, const int b)
     const double up = su * idc;
     if (DRAG) phi -= cde * sqrt(u * u + up * up) * u / he;
     if (WIND) {
-      const double cw = S.rho_ratio * (0.75 + 0.067 * sqrt(wn * wn + wt * wt)) * 1e-3;
       const double rn = wn - u, rt = wt - up;
       phi += cw * sqrt(rn * rn + rt * rt) * rn / he;
     }

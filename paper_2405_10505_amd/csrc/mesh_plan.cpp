@@ -893,7 +893,7 @@ double bytes_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag, bool
     if (upd) b += 2 * S;                     // U0, Udst
     if (acc) b += 2 * S;
     if (drag || wind) b += S;                // u of the edge
-    if (wind) b += 16;
+    if (wind) b += 3 * S;                    // wind components and C_W (per member)
     b += rs.own(e, drag || wind, S);
     for (int j = 0; j < n; ++j) b += rs.nbr(pm.e_eoe[(size_t)j * pm.es + e], drag || wind, S);
     for (int j = 0; j < 2; ++j)
@@ -915,7 +915,7 @@ double bytes_edge_cells_pass(const PermMesh& pm, const StageRanges& r, bool drag
     if (upd) b += 2 * S;                     // U0, Udst
     if (acc) b += 2 * S;
     if (drag || wind) b += S;                // u of the edge
-    if (wind) b += 16;
+    if (wind) b += 3 * S;                    // wind components and C_W (per member)
     b += rs.own(e, drag || wind, S);
     for (int j = 0; j < 2; ++j) {
       const int c = pm.e_cell[(size_t)j * pm.es + e];
@@ -1018,7 +1018,7 @@ double compulsory_edge_pass(const PermMesh& pm, const StageRanges& r, bool drag,
     const bool acc = e >= r.edge_acc.b && e < r.edge_acc.e;
     if (upd) b += 2 * S;                     // u^n, the new u
     if (acc) b += 2 * S;
-    if (wind) b += 16;
+    if (wind) b += 3 * S;                    // wind components and C_W (per member)
     if (tang) {
       if (se.mark(e)) b += S;                // u of the edge
       for (int j = 0; j < n; ++j)

@@ -232,7 +232,7 @@ struct DevState {
   int nm = 1, nm_log2 = 0;
   DevBuf H[4], hs, B, acc_h, sv_h, cd;
   DevBuf U[4], acc_u, sv_u, P, q;
-  DevBuf wind_n, wind_t;
+  DevBuf wind_n, wind_t, wind_c;   // wind forcing: components and C_W per edge and member
   bool has_wind = false;
   DevBuf slow;   // operator splitting: frozen slow momentum tendency [E*nm]
   // moving cyclone: wind evaluated on the device once per coarse step
@@ -468,9 +468,9 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     e.cd = drag_on ? s.cd.as<double>() : nullptr;
     e.wind_n = s.has_wind ? s.wind_n.as<double>() : nullptr;
     e.wind_t = s.has_wind ? s.wind_t.as<double>() : nullptr;
+    e.wind_c = s.has_wind ? s.wind_c.as<double>() : nullptr;
     e.c_dt = c_dt;
     e.acc_w = acc_w;
-    e.rho_ratio = p.rho_air / p.rho_water;
     e.slow = fast_pass ? slow : nullptr;
     ps.model_bytes = fast_pass ? bytes_edge_fast_pass(u.pm, r, slow != nullptr, nm)
                      : ps.edge_cells ? bytes_edge_cells_pass(u.pm, r, drag_on, s.has_wind, nm)
@@ -1437,7 +1437,7 @@ static void ensemble_rebuild(fblts_ensemble* e) {
 // Everything a coarse step changes besides the counters, per mesh unit: the
 // state, and with a moving storm its step clock and the wind it evaluated.
 struct SnapUnit {
-  DevBuf h, u, wn, wt;
+  DevBuf h, u, wn, wt, wc;
   long long clock = 0;
   bool cyclone = false;
 };
@@ -1455,8 +1455,10 @@ static std::vector<std::unique_ptr<SnapUnit>> snapshot_take(const std::vector<Me
       q->cyclone = true;
       q->wn.alloc((size_t)Ne * 8);
       q->wt.alloc((size_t)Ne * 8);
+      q->wc.alloc((size_t)Ne * 8);
       launch_copy(q->wn.as<double>(), u->st.wind_n.as<double>(), Ne, st);
       launch_copy(q->wt.as<double>(), u->st.wind_t.as<double>(), Ne, st);
+      launch_copy(q->wc.as<double>(), u->st.wind_c.as<double>(), Ne, st);
       hip_check(hipMemcpyAsync(&q->clock, u->st.cyc_clock.p, 8, hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
     }
     snap.push_back(std::move(q));
@@ -1477,6 +1479,7 @@ static void snapshot_restore(const std::vector<MeshUnit*>& units, const std::vec
     if (q.cyclone) {
       launch_copy(u.st.wind_n.as<double>(), q.wn.as<double>(), Ne, st);
       launch_copy(u.st.wind_t.as<double>(), q.wt.as<double>(), Ne, st);
+      launch_copy(u.st.wind_c.as<double>(), q.wc.as<double>(), Ne, st);
       hip_check(hipMemcpyAsync(u.st.cyc_clock.p, &q.clock, 8, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
     }
   }
@@ -1767,7 +1770,7 @@ int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device) {
   });
 }
 
-int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t on_device) {
+int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, const double* wc, int32_t on_device) {
   return guarded([&] {
     if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
     if (!s->have_regions) throw Err(FBLTS_ESTATE, "set_regions must come first");
@@ -1776,7 +1779,8 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
     s->drop_graph();
     ++s->gen;
     u.st.cyclone = false;
-    if (!wn || !wt) {
+    if (!wn || !wt || !wc) {
+      if (wn || wt || wc) throw Err(FBLTS_EINVAL, "set_wind takes all three arrays or none");
       u.st.has_wind = false;
     } else {
       if (!s->P.nonlinear()) throw Err(FBLTS_EINVAL, "wind stress needs nonlinear physics");
@@ -1785,20 +1789,26 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, int32_t 
       if (u.st.wind_n.bytes < (size_t)E * 8) {
         u.st.wind_n.alloc((size_t)E * 8);
         u.st.wind_t.alloc((size_t)E * 8);
+        u.st.wind_c.alloc((size_t)E * 8);
       }
       const double* a = wn;
       const double* b = wt;
-      DevBuf ta, tb;
+      const double* c = wc;
+      DevBuf ta, tb, tc;
       if (!on_device) {
         ta.alloc((size_t)E * 8);
         tb.alloc((size_t)E * 8);
+        tc.alloc((size_t)E * 8);
         hip_check(hipMemcpy(ta.p, wn, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
         hip_check(hipMemcpy(tb.p, wt, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
+        hip_check(hipMemcpy(tc.p, wc, (size_t)E * 8, hipMemcpyHostToDevice), "memcpy");
         a = ta.as<double>();
         b = tb.as<double>();
+        c = tc.as<double>();
       }
       launch_permute(u.st.wind_n.as<double>(), a, u.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
       launch_permute(u.st.wind_t.as<double>(), b, u.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
+      launch_permute(u.st.wind_c.as<double>(), c, u.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
       u.st.has_wind = true;
     }
@@ -1840,11 +1850,12 @@ static CycloneParams cyclone_params(const fblts_cyclone* c) {
 }
 
 // Wind arrays [E*nm], per-member parameters (calm air) and a zero step clock.
-static void cyclone_install(MeshUnit& u, double dt) {
+static void cyclone_install(MeshUnit& u, double dt, double rho_ratio) {
   const int E = u.pm.E, nm = u.st.nm;
   if (u.st.wind_n.bytes < (size_t)E * nm * 8) {
     u.st.wind_n.alloc((size_t)E * nm * 8);
     u.st.wind_t.alloc((size_t)E * nm * 8);
+    u.st.wind_c.alloc((size_t)E * nm * 8);
   }
   std::vector<CycloneParams> calm(nm);
   u.st.cyc_p.alloc(calm.size() * sizeof(CycloneParams));
@@ -1858,6 +1869,8 @@ static void cyclone_install(MeshUnit& u, double dt) {
   a.n = u.st.cyc_n.bytes ? u.st.cyc_n.as<double>() : nullptr;
   a.wn = u.st.wind_n.as<double>();
   a.wt = u.st.wind_t.as<double>();
+  a.wc = u.st.wind_c.as<double>();
+  a.rho_ratio = rho_ratio;
   a.clock = u.st.cyc_clock.as<long long>();
   a.p = static_cast<const CycloneParams*>(u.st.cyc_p.p);
   a.E = E;
@@ -1918,7 +1931,7 @@ int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_e
       if (!s->P.nonlinear()) throw Err(FBLTS_EINVAL, "wind stress needs nonlinear physics");
       const CycloneParams q = cyclone_params(c);
       cyclone_positions(u, x_edge, n_edge);
-      cyclone_install(u, s->P.p.dt);
+      cyclone_install(u, s->P.p.dt, s->P.p.rho_air / s->P.p.rho_water);
       cyclone_member(u, 0, q);
       // wind of the first step, so that the state is complete before any step
       launch_cyclone(u.st.cyc, s->stream);
@@ -1929,20 +1942,22 @@ int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_e
   });
 }
 
-int fblts_get_wind(fblts_solver* s, double* wn, double* wt) {
+int fblts_get_wind(fblts_solver* s, double* wn, double* wt, double* wc) {
   return guarded([&] {
     if (!s || !wn || !wt) throw Err(FBLTS_EINVAL, "NULL argument");
     if (!s->have_regions || !s->unit->st.has_wind) throw Err(FBLTS_ESTATE, "no wind is set");
     MeshUnit& u = *s->unit;
     const int E = u.pm.E;
-    std::vector<double> a(E), b(E);
+    std::vector<double> a(E), b(E), c(E);
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     hip_check(hipMemcpy(a.data(), u.st.wind_n.p, (size_t)E * 8, hipMemcpyDeviceToHost), "memcpy");
     hip_check(hipMemcpy(b.data(), u.st.wind_t.p, (size_t)E * 8, hipMemcpyDeviceToHost), "memcpy");
+    hip_check(hipMemcpy(c.data(), u.st.wind_c.p, (size_t)E * 8, hipMemcpyDeviceToHost), "memcpy");
     for (int i = 0; i < E; ++i) {
       const int o = u.plan.edge_new2old[i];
       wn[o] = a[i];
       wt[o] = b[i];
+      if (wc) wc[o] = c[i];
     }
     return FBLTS_OK;
   });
@@ -2248,9 +2263,9 @@ int fblts_debug_tendency(fblts_solver* s, int32_t which, const double* h, const 
       es.cd = s->drag_on ? U.st.cd.as<double>() : nullptr;
       es.wind_n = U.st.has_wind ? U.st.wind_n.as<double>() : nullptr;
       es.wind_t = U.st.has_wind ? U.st.wind_t.as<double>() : nullptr;
+      es.wind_c = U.st.has_wind ? U.st.wind_c.as<double>() : nullptr;
       es.c_dt = 0;
       es.acc_w = 1;
-      es.rho_ratio = s->P.p.rho_air / s->P.p.rho_water;
       launch_edge(ee, s->drag_on, U.st.has_wind, kBlock, s->stream, false);
     }
     const int n = which == 0 ? N : E;
@@ -2362,7 +2377,7 @@ int fblts_ensemble_set_cyclone(fblts_ensemble* e, int32_t mesh, int32_t member, 
     // first storm: every member of every mesh gets the atmosphere (calm air
     // until given a storm), so that all meshes share one pass sequence
     if (!e->units[0]->st.cyclone)
-      for (auto& u : e->units) cyclone_install(*u, e->P.p.dt);
+      for (auto& u : e->units) cyclone_install(*u, e->P.p.dt, e->P.p.rho_air / e->P.p.rho_water);
     if (q.enabled && !U.st.cyc.x) throw Err(FBLTS_EINVAL, "edge positions and normals are required");
     cyclone_member(U, member, q);
     std::vector<MeshUnit*> units;

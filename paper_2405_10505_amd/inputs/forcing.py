@@ -14,9 +14,13 @@ x (unit vector, sphere radius R) at time t:
           direction at c projected onto x's tangent plane)
 
 and its edge components wind_normal = W.n_e, wind_tangential = W.t_e.  The
-library evaluates the same vortex on the device at the start of each coarse
-step (time t0 + k dt for the k-th step after the storm is set); this numpy
-version feeds the oracle and checks the device evaluation.
+wind-stress coefficient of eq. hurricane_model comes with the wind: the paper
+takes it from Garratt (1977), C_W = (rho_air / rho_water)(0.75 + 0.067 |W|)
+1e-3 (his 10 m drag law in kinematic form), evaluated from the wind speed at
+the edge.  The library evaluates the same vortex and coefficient on the device
+at the start of each coarse step (time t0 + k dt for the k-th step after the
+storm is set); this numpy version feeds the oracle and checks the device
+evaluation.
 """
 from __future__ import annotations
 
@@ -26,6 +30,12 @@ from dataclasses import dataclass
 import numpy as np
 
 OMEGA = 7.292e-5
+RHO_WATER = 1000.0
+
+
+def wind_stress_coefficient(wn, wt, rho_air=1.15, rho_water=RHO_WATER):
+    """C_W at edges from the wind components there (Garratt's law, kinematic form)."""
+    return (rho_air / rho_water) * (0.75 + 0.067 * np.sqrt(wn * wn + wt * wt)) * 1e-3
 
 
 @dataclass
@@ -87,6 +97,11 @@ class Holland:
         x = mesh.x_edge / np.linalg.norm(mesh.x_edge, axis=1, keepdims=True)
         W = self.wind(x, t)
         return np.einsum("ij,ij->i", W, mesh.normal_edge), np.einsum("ij,ij->i", W, mesh.tangent_edge)
+
+    def edge_forcing(self, mesh, t, rho_water=RHO_WATER):
+        """(wind_normal, wind_tangential, C_W) at the edges at time t."""
+        wn, wt = self.edge_components(mesh, t)
+        return wn, wt, wind_stress_coefficient(wn, wt, self.rho_air, rho_water)
 
 
 def seeded_track(seed, target=None, start_distance=None, radius=6.371229e6):

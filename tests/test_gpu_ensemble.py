@@ -7,7 +7,7 @@ import pytest
 
 import paper_2405_10505_amd as F
 from oracle import regions, schemes, trisk
-from paper_2405_10505_amd.inputs import workloads
+from paper_2405_10505_amd.inputs import forcing, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -108,7 +108,9 @@ def test_per_member_cyclones_equal_single_solver_bitwise(graph):
         s.set_drag(np.full(w.mesh.n_cells, cds[m]))
         s.set_state(w.h0, w.u0)
         if st is None:
-            s.set_wind(np.zeros(w.mesh.n_edges), np.zeros(w.mesh.n_edges))
+            # calm air: zero wind, the coefficient of zero wind speed
+            z = np.zeros(w.mesh.n_edges)
+            s.set_wind(z, z, forcing.wind_stress_coefficient(z, z))
         else:
             s.set_cyclone(w.mesh.x_edge, w.mesh.normal_edge, **st)
         s.step(8)

@@ -44,7 +44,7 @@ def test_sphere400k_ten_steps_match_oracle(c3):
     u, h = w.u0.copy(), w.h0.copy()
     s = solver()
     for k in range(10):
-        ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_components(w.mesh, k * w.dt))
+        ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_forcing(w.mesh, k * w.dt))
         u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
         s.step(1)
         hg, ug = s.get_state()

@@ -57,22 +57,24 @@ def test_cyclone_wind_matches_numpy_vortex(sph, t0):
     s = _solver(fm, w, storm)
     for k_after, k_used in ((0, 0), (4, 3), (3, 6)):
         s.step(k_after)
-        wn, wt = s.get_wind()
-        rn, rt = storm.edge_components(w.mesh, k_used * w.dt)
+        wn, wt, wc = s.get_wind()
+        rn, rt, rc = storm.edge_forcing(w.mesh, k_used * w.dt)
         scale = max(np.abs(rn).max(), np.abs(rt).max())
         assert scale > 5.0
         assert max(np.abs(wn - rn).max(), np.abs(wt - rt).max()) <= 1e-12 * scale
+        # the wind-stress coefficient the device forms from its wind
+        assert np.abs(wc - rc).max() <= 1e-12 * np.abs(rc).max()
 
 
 def test_tendency_with_fixed_wind_matches_oracle(sph):
     w, om, lab, fm, storm = sph
     s = _solver(fm, w, scheme=F.SCHEME_FBRK32, M=1)
-    wn, wt = storm.edge_components(w.mesh, 0.0)
-    s.set_wind(wn, wt)
+    wn, wt, wc = storm.edge_forcing(w.mesh, 0.0)
+    s.set_wind(wn, wt, wc)
     r = np.random.default_rng(5)
     u = 0.3 * r.normal(size=om.E)
     h = om.H * (1 + 0.01 * r.normal(size=om.N))
-    ph = trisk.Physics(linear=False, cd=w.cd, wind=(wn, wt))
+    ph = trisk.Physics(linear=False, cd=w.cd, wind=(wn, wt, wc))
     ref = trisk.phi(om, u, h, ph)
     assert np.max(np.abs(s.tendency(1, h, u) - ref)) <= 1e-13 * np.max(np.abs(ref))
     ref0 = trisk.phi(om, u, h, trisk.Physics(linear=False, cd=w.cd))
@@ -89,7 +91,7 @@ def test_fblts_with_moving_cyclone_matches_oracle(sph):
     d1 = s.diagnostics()
     u, h = w.u0.copy(), w.h0.copy()
     for k in range(steps):
-        ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_components(w.mesh, k * w.dt))
+        ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_forcing(w.mesh, k * w.dt))
         u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab)
     assert np.linalg.norm(u) > 1e-3
     assert rel_l2(hg - om.H, h - om.H) <= 1e-10
@@ -108,7 +110,7 @@ def test_cyclone_graph_replay_bitwise(sph):
         hb, ub = b.get_state()
         assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
         wa, wb = a.get_wind(), b.get_wind()
-        assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
+        assert all(np.array_equal(x, y) for x, y in zip(wa, wb))
 
 
 def test_cyclone_argument_errors(sph):
@@ -143,7 +145,7 @@ def test_cyclone_clock_advances_inside_multi_step_graphs(sph):
     hb, ub = b.get_state()
     assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
     wa, wb = a.get_wind(), b.get_wind()
-    assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
+    assert all(np.array_equal(x, y) for x, y in zip(wa, wb))
 
 
 def test_set_state_restarts_the_storm(sph):
@@ -158,7 +160,7 @@ def test_set_state_restarts_the_storm(sph):
     hb, ub = b.get_state()
     assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
     wa, wb = a.get_wind(), b.get_wind()
-    assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
+    assert all(np.array_equal(x, y) for x, y in zip(wa, wb))
 
 
 def test_autotune_leaves_the_storm_where_it_was(sph):
@@ -169,7 +171,7 @@ def test_autotune_leaves_the_storm_where_it_was(sph):
     choice = a.autotune(steps=2, repeats=1)
     assert choice["candidates"]
     w1 = a.get_wind()
-    assert np.array_equal(wind0[0], w1[0]) and np.array_equal(wind0[1], w1[1])
+    assert all(np.array_equal(x, y) for x, y in zip(wind0, w1))
     a.step(2)
     b = _solver(fm, w, storm, graph=True)
     b.step(5)
@@ -177,4 +179,4 @@ def test_autotune_leaves_the_storm_where_it_was(sph):
     hb, ub = b.get_state()
     assert np.array_equal(ha, hb) and np.array_equal(ua, ub)
     wa, wb = a.get_wind(), b.get_wind()
-    assert np.array_equal(wa[0], wb[0]) and np.array_equal(wa[1], wb[1])
+    assert all(np.array_equal(x, y) for x, y in zip(wa, wb))

@@ -288,7 +288,7 @@ def test_theorems_on_the_sphere_with_a_moving_storm():
     def run(correct):
         u, h = w.u0.copy(), w.h0.copy()
         for n in range(10):
-            ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_components(w.mesh, n * w.dt))
+            ph = trisk.Physics(linear=False, cd=w.cd, wind=storm.edge_forcing(w.mesh, n * w.dt))
             u, h = schemes.fblts_step(om, u, h, w.dt, w.M, ph, lab, correct_interface=correct)
         return u, h
 

@@ -41,7 +41,7 @@ def test_fast_plus_slow_is_the_full_tendency(cvt_small):
     w, om, lab = cvt_small
     u, h = _state(om, 1)
     r = np.random.default_rng(2)
-    wind = (10 * r.normal(size=om.E), 10 * r.normal(size=om.E))
+    wind = (10 * r.normal(size=om.E), 10 * r.normal(size=om.E), 1e-3 * (1.0 + r.uniform(size=om.E)))
     for ph in (trisk.Physics(cd=w.cd), trisk.Physics(cd=w.cd, wind=wind), trisk.Physics()):
         full = trisk.phi(om, u, h, ph)
         parts = trisk.phi_fast(om, u, h, ph) + trisk.phi_slow(om, u, h, ph)

@@ -111,7 +111,7 @@ def test_hex_uniform_flow_drag_and_wind_stress(hexm):
     quadratic drag adds n_e . (-C_D |U| U / h) to Phi and the wind stress adds
     n_e . (C_W |W - U| (W - U) / h), the vector laws with the full speeds (the
     tangential components come from the TRiSK reconstruction, exact for uniform
-    flow here).  C_W(|W|) is the oracle's coefficient law, a reading."""
+    flow here); C_W is forcing data, like the wind."""
     m = hexm
     om = trisk.OMesh(m)
     U = np.array([1.3, -0.6])
@@ -123,11 +123,41 @@ def test_hex_uniform_flow_drag_and_wind_stress(hexm):
     drag = trisk.phi(om, u, h, trisk.Physics(linear=False, cd=np.full(om.N, cd))) - base
     expect = m.normal_edge @ (-cd * np.hypot(*U) * U / 37.0)
     np.testing.assert_allclose(drag, expect, rtol=1e-10, atol=1e-13 * np.abs(expect).max())
-    ph = trisk.Physics(linear=False, wind=(m.normal_edge @ W, m.tangent_edge @ W))
+    cw = 1.7e-3
+    ph = trisk.Physics(linear=False, wind=(m.normal_edge @ W, m.tangent_edge @ W, np.full(om.E, cw)))
     wind = trisk.phi(om, u, h, ph) - base
-    cw = trisk.wind_drag_coefficient(np.hypot(*W), ph)
     expect = m.normal_edge @ (cw * np.hypot(*(W - U)) * (W - U) / 37.0)
     np.testing.assert_allclose(wind, expect, rtol=1e-10, atol=1e-13 * np.abs(expect).max())
+
+
+def test_hex_linear_drag_coefficient_field(hexm):
+    """A drag coefficient varying linearly in space, uniform flow U over
+    uniform depth h on the regular hexagon: on every edge away from the
+    periodic seam the drag term equals the vector law n_e . (-C_D(x_e) |U| U / h)
+    with C_D evaluated at the edge's own midpoint x_e.  Each hexagon edge
+    bisects the segment between its two cell centres, so the edge value of a
+    linear field is exactly the mean of the two cell values, and any other
+    reconstruction from the cells (one side, a geometric mean) misses it."""
+    m = hexm
+    om = trisk.OMesh(m)
+    U = np.array([0.9, 1.7])
+    u = m.normal_edge @ U
+    h = np.full(om.N, 52.0)
+    a, bx, by = 1.0e-3, 2.0e-3 / m.lx, 1.0e-3 / m.ly
+    xc = m.x_cell
+    cd = a + bx * xc[:, 0] + by * xc[:, 1]
+    base = trisk.phi(om, u, h, trisk.Physics(linear=False))
+    drag = trisk.phi(om, u, h, trisk.Physics(linear=False, cd=cd)) - base
+    c0, c1 = m.cells_on_edge[:, 0], m.cells_on_edge[:, 1]
+    d = xc[c1] - xc[c0]
+    inner = np.all(np.abs(d) < 2.0 * m.dc_edge[:, None], axis=1)   # no periodic wrap between the cells
+    assert inner.sum() > 0.9 * om.E
+    xe = m.x_edge[inner]
+    # the mesh property the reading relies on: the edge point is the midpoint of the cell centres
+    np.testing.assert_allclose(xe, 0.5 * (xc[c0] + xc[c1])[inner], rtol=0, atol=1e-9 * m.lx)
+    cde = a + bx * xe[:, 0] + by * xe[:, 1]
+    expect = -cde * np.hypot(*U) * (m.normal_edge[inner] @ U) / 52.0
+    np.testing.assert_allclose(drag[inner], expect, rtol=1e-10, atol=1e-13 * np.abs(expect).max())
 
 
 def test_hex_uniform_state_diagnostics(hexm):
