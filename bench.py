@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--schedule", default=None,
                     help="fixed launch schedule 'fuse_vertex,block[,edge_cells[,persistent]]' instead of autotuning "
                          "(e.g. 1,64,0)")
+    ap.add_argument("--pipeline", type=int, default=None, choices=[0, 1],
+                    help="FB-LTS step arrangement (FBLTS_OPT_PIPELINE) of the main solver; default: the library's")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many graph-replayed steps (for rocprofv3), no JSON")
     return ap.parse_args()
@@ -504,6 +506,8 @@ def main():
         w.name, w.mesh.n_cells, w.mesh.n_edges, int(w.fine_mask.sum()), w.dt, w.M, time.perf_counter() - t))
     w._fm = F.Mesh(w.mesh)
     s = make_solver(F, w, F.SCHEME_FBLTS, w.dt, w.M, split=args.split)
+    if args.pipeline is not None:
+        s.set_option(F.OPT_PIPELINE, args.pipeline)
     from paper_2405_10505_amd import autotune
     # later runs on the same workload (a profiled run after the timed one) replay
     # the schedule it chose: the cache is keyed by the workload's shape

@@ -291,6 +291,15 @@ int fblts_set_graph(fblts_solver* s, int32_t enable);
  *     solver's persistent launch or other work occupies the GPU on another
  *     stream) makes the next state read or diagnostics fail with
  *     FBLTS_EDEVICE.  Default 0.
+ *   FBLTS_OPT_PIPELINE: 1 (default) arranges an FB-LTS coarse step into fewer
+ *     dependent launches (Sec. 2.2 steps 1-4, same arithmetic): the first fine
+ *     substep, which needs each coarse stage only through its interface-one
+ *     prediction, runs beside the coarse stages 2 and 3 on arrays of its own
+ *     (segments of the same launches), and the prediction for the next
+ *     substep, or the correction and assembly after the last one, is done by
+ *     the substep's last momentum pass.  9M + 3 stencil launches per coarse
+ *     step instead of 10M + 10 (q_v fused; a separate vertex pass adds 3M + 1).
+ *     0 runs the steps one pass after another.  Ensembles take 0 only.
  * Errors: FBLTS_EINVAL for an unknown option or value, or EDGE_CELLS on a
  * mesh whose weights are not the kite-fraction walks. */
 enum {
@@ -298,7 +307,8 @@ enum {
   FBLTS_OPT_BLOCK = 2,
   FBLTS_OPT_EDGE_CELLS = 3,
   FBLTS_OPT_GRAPH_STEPS = 4,
-  FBLTS_OPT_PERSISTENT = 5
+  FBLTS_OPT_PERSISTENT = 5,
+  FBLTS_OPT_PIPELINE = 6
 };
 int fblts_set_option(fblts_solver* s, int32_t option, int32_t value);
 

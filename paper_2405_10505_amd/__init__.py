@@ -20,7 +20,7 @@ SCHEME_FBLTS, SCHEME_FBRK32, SCHEME_RK4 = 0, 1, 2
 PHYS_LINEAR, PHYS_NONLINEAR, PHYS_GRAVITY_WAVE = 0, 1, 2
 SPLIT_NONE, SPLIT_COARSE, SPLIT_FINE = 0, 1, 2
 BETA = (0.531, 0.531, 0.313)
-OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS, OPT_GRAPH_STEPS, OPT_PERSISTENT = 1, 2, 3, 4, 5
+OPT_FUSE_VERTEX, OPT_BLOCK, OPT_EDGE_CELLS, OPT_GRAPH_STEPS, OPT_PERSISTENT, OPT_PIPELINE = 1, 2, 3, 4, 5, 6
 HANDLE_SOLVER, HANDLE_ENSEMBLE = 0, 1
 
 _P_i32 = C.POINTER(C.c_int32)

@@ -62,6 +62,19 @@ struct MeshDev {
   const int* e_vq_cell;    // [6][es]  v0's three cells, then v1's
 };
 
+// Coarse stages of the pipelined FB-LTS step (fine substep 0 overlapping the
+// coarse advancement) hand their stage values to the fine substeps' own
+// arrays as they are formed: on [b, p) (interface one) the k = 0 prediction
+// a * y + c * y0, on [p, e) the value itself, where y is the updated value
+// and y0 the FB base value of the item; with sv, y0 is also saved on [b, p)
+// (compact, members innermost).  dst == nullptr: nothing.
+struct Mirror {
+  double* dst;
+  double* sv;
+  int b, p, e;
+  double a, c;
+};
+
 // Thickness pass: Psi, FB stage update, FB-averaged thickness and Bernoulli
 // function over cells [begin,end).  Psi is evaluated on [upd_begin,upd_end)
 // (written as H0 + c_dt*Psi to Hdst) and on [acc_begin,acc_end) (added to acc
@@ -81,6 +94,7 @@ struct CellSeg {
   double* B;
   double* acc;
   double c_dt, wn, ws, wb, acc_w, g;
+  Mirror mir;
 };
 
 // Vertex pass: q_v = (zeta_v(Usrc) + f_v) / h_v(hs) over vertices [begin,end).
@@ -105,6 +119,29 @@ struct PrepSeg {
   double* P;               // 4 doubles per edge and member, split by use (prep_record.h)
 };
 
+// Work folded into the last momentum pass of a fine substep (pipelined
+// FB-LTS step), in place of a separate launch after it:
+//  kind 1, the interface-one prediction for the next substep (eq. preds):
+//    edges [e_b, e_p) by the edge's own thread after its own work, cells
+//    [c_b, c_p) by extra items after the edges;
+//  kind 2, the correction and assembly of t^{n+1}: edges [e_b, e_q)
+//    (interface one and two, whose accumulated tendency the thread has just
+//    formed) by their own thread, cells [c_b, c_e) and interior edges
+//    [e_q, e_e) by extra items.
+// H* / U* are the fine substeps' arrays (H0, U0 the state), C* / D* the coarse
+// stage values, sv_* the saved h^n, u^n on interface one.
+struct StepTail {
+  int kind;
+  int c_b, c_p, c_q, c_e;
+  int e_b, e_p, e_q, e_e;
+  double* H0; double* H1; double* H2; double* H3;
+  const double* C1; const double* C2; const double* C3;
+  double* U0; double* U1; double* U2;
+  const double* D1; const double* D2; const double* D3;
+  const double* sv_h; const double* sv_u; const double* acc_h;
+  double a, one_minus_a, invM, c, ap, delta;
+};
+
 // Momentum pass: Phi_e from P, B, drag and wind over edges; update
 // [upd_begin,upd_end) as U0 + c_dt*Phi into Udst, accumulate on
 // [acc_begin,acc_end).
@@ -124,6 +161,8 @@ struct EdgeSeg {
   const double* wind_c;    // wind-stress coefficient C_W per edge and member
   const double* slow;      // fast pass: frozen slow tendency per edge and member, or nullptr
   double c_dt, acc_w;
+  Mirror mir;
+  StepTail tail;
 };
 
 // Interface-one prediction (eq. preds) over cells [c_begin,c_end) and edges
@@ -177,6 +216,10 @@ struct Launch {
   int nseg;
   int block;                 // threads per block of the launch
   int blk_start[kMaxSeg + 1];
+  // > 0: only the first xcd_n blocks are laid out XCD by XCD; the blocks
+  // after them (work folded into a momentum pass) go round-robin over the
+  // XCDs, so that every XCD gets its share of both kinds of block
+  int xcd_n;
   S seg[kMaxSeg];
 };
 

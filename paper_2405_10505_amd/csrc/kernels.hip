@@ -72,6 +72,78 @@ __device__ __forceinline__ void sgpr_ready(const T&... v) {
   (sgpr_ready1(v), ...);
 }
 
+// ------------------------------------------------- prediction arithmetic
+// Interface-one prediction (eq. preds) at fine substep k from the values at
+// t^n (yn) and the coarse stage values (y_s, y3): each product rounded, then
+// summed left to right (the library is built without contraction).  At k = 0
+// the y3 term is a zero product, and adding it changes nothing, so the k = 0
+// values are formed without it while y3 does not exist yet.
+__device__ __forceinline__ double pred_n(double a, double y3, double one_minus_a, double yn) {
+  return a * y3 + one_minus_a * yn;
+}
+__device__ __forceinline__ double pred_s(double a, double y3, double invM, double ys, double c, double yn) {
+  return a * y3 + invM * ys + c * yn;
+}
+__device__ __forceinline__ double pred_3(double ap, double y3, double c, double yn) { return ap * y3 + c * yn; }
+
+// A coarse stage's hand-over of item i (flat index ii) to the fine arrays.
+__device__ __forceinline__ void mirror_store(const Mirror& M, int i, long ii, double y, double y0, int nm_log2) {
+  if (M.dst == nullptr || i < M.b || i >= M.e) return;
+  if (i < M.p) {
+    M.dst[ii] = M.a * y + M.c * y0;
+    if (M.sv != nullptr) M.sv[ii - ((long)M.b << nm_log2)] = y0;
+  } else {
+    M.dst[ii] = y;
+  }
+}
+
+// The folded prediction / assembly of an edge by its own thread (after its
+// own update and accumulation; afin = the accumulated tendency).
+__device__ __forceinline__ void tail_own_edge(const StepTail& T, int e, long ee, int nm_log2, double afin) {
+  if (e < T.e_b) return;
+  const long t = ee - ((long)T.e_b << nm_log2);
+  if (T.kind == 1) {
+    if (e >= T.e_p) return;
+    const double un = T.sv_u[t], u3 = T.D3[ee];
+    const double u1 = T.D1[ee], u2 = T.D2[ee];
+    T.U0[ee] = pred_n(T.a, u3, T.one_minus_a, un);
+    T.U1[ee] = pred_s(T.a, u3, T.invM, u1, T.c, un);
+    T.U2[ee] = pred_s(T.a, u3, T.invM, u2, T.c, un);
+  } else {
+    if (e >= T.e_q) return;
+    double base;
+    if (e < T.e_p) base = T.sv_u[t];
+    else base = T.U0[ee];
+    T.U0[ee] = fma(T.delta, afin, base);
+  }
+}
+
+// The folded work's extra items: t counts from 0 after the pass's edges.
+__device__ __forceinline__ void tail_item(const StepTail& T, long t, int nm_log2) {
+  if (T.kind == 1) {
+    if (t >= ((long)(T.c_p - T.c_b) << nm_log2)) return;
+    const long i = ((long)T.c_b << nm_log2) + t;
+    const double hn = T.sv_h[t], h3 = T.C3[i];
+    const double h1 = T.C1[i], h2 = T.C2[i];
+    T.H0[i] = pred_n(T.a, h3, T.one_minus_a, hn);
+    T.H1[i] = pred_s(T.a, h3, T.invM, h1, T.c, hn);
+    T.H2[i] = pred_s(T.a, h3, T.invM, h2, T.c, hn);
+    T.H3[i] = pred_3(T.ap, h3, T.c, hn);
+  } else {
+    const long nc = (long)(T.c_e - T.c_b) << nm_log2;
+    if (t < nc) {
+      const long i = ((long)T.c_b << nm_log2) + t;
+      const int c = (int)(i >> nm_log2);
+      if (c < T.c_p) T.H0[i] = fma(T.delta, T.acc_h[i], T.sv_h[t]);
+      else if (c < T.c_q) T.H0[i] = fma(T.delta, T.acc_h[i], T.H0[i]);
+      else T.H0[i] = T.C3[i];
+    } else if (t - nc < ((long)(T.e_e - T.e_q) << nm_log2)) {
+      const long i = ((long)T.e_q << nm_log2) + (t - nc);
+      T.U0[i] = T.D3[i];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- cell pass
 // MODE 0: linear TRiSK (flux H_e u, B = g(h* - H)); 1: nonlinear (flux h_e u,
 // B = K + g(h* - H)); 2: fast terms of the operator splitting, eq. fast_terms
@@ -151,6 +223,7 @@ __device__ __forceinline__ void cell_body(const Launch<CellSeg>& L, const int b)
   if (in_upd) {
     hnew = fma(S.c_dt, psi, h0);
     S.Hdst[ii] = hnew;
+    mirror_store(S.mir, i, ii, hnew, h0, nm_log2);
   } else {
     hnew = hnew_src;
   }
@@ -373,7 +446,10 @@ __device__ __forceinline__ void edge_body(const Launch<EdgeSeg>& L, const int b)
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   const int e = (int)(item >> nm_log2);
-  if (e >= S.end) return;
+  if (e >= S.end) {
+    if (S.tail.kind != 0) tail_item(S.tail, item - ((long)S.end << nm_log2), nm_log2);
+    return;
+  }
   const int mem = (int)(item & ((1 << nm_log2) - 1));
   const int nm = 1 << nm_log2;
   const MeshDev& m = S.m;
@@ -444,16 +520,31 @@ __device__ __forceinline__ void edge_body(const Launch<EdgeSeg>& L, const int b)
       phi += cw * sqrt(rn * rn + rt * rt) * rn / he;
     }
   }
-  if (upd) S.Udst[ee] = fma(S.c_dt, phi, u0);
+  if (upd) {
+    const double unew = fma(S.c_dt, phi, u0);
+    S.Udst[ee] = unew;
+    mirror_store(S.mir, e, ee, unew, u0, nm_log2);
+  }
+  double afin = 0.0;
   if (acc) {
     const double a = S.acc_w * phi;
-    S.acc[ee] = S.acc_first ? a : acc0 + a;
+    afin = S.acc_first ? a : acc0 + a;
+    S.acc[ee] = afin;
   }
+  if (S.tail.kind != 0) tail_own_edge(S.tail, e, ee, nm_log2, afin);
+}
+
+// Block index of a momentum-pass launch: the edge blocks XCD by XCD, the
+// blocks of folded work (if any) after them in dispatch order.
+__device__ __forceinline__ int edge_tile(const Launch<EdgeSeg>& L) {
+  const int n = L.xcd_n;
+  if (n > 0 && (int)blockIdx.x >= n) return blockIdx.x;
+  return xcd_tile(blockIdx.x, n > 0 ? n : gridDim.x);
 }
 
 template <bool DRAG, bool WIND, bool CELLS, bool ONE, bool GROUP>
 __global__ void __launch_bounds__(kBlock) k_edge(const Launch<EdgeSeg> L) {
-  edge_body<DRAG, WIND, CELLS, ONE, GROUP>(L, xcd_tile(blockIdx.x, gridDim.x));
+  edge_body<DRAG, WIND, CELLS, ONE, GROUP>(L, edge_tile(L));
 }
 
 // ----------------------------------------------------- fast momentum pass
@@ -468,7 +559,10 @@ __device__ __forceinline__ void edge_fast_body(const Launch<EdgeSeg>& L, const i
   const int nm_log2 = S.nm_log2;
   const long item = (long)S.begin * (1L << nm_log2) + (long)(b - seg_block<ONE>(L, s)) * L.block + threadIdx.x;
   const int e = (int)(item >> nm_log2);
-  if (e >= S.end) return;
+  if (e >= S.end) {
+    if (S.tail.kind != 0) tail_item(S.tail, item - ((long)S.end << nm_log2), nm_log2);
+    return;
+  }
   const int mem = (int)(item & ((1 << nm_log2) - 1));
   const int nm = 1 << nm_log2;
   const MeshDev& m = S.m;
@@ -476,16 +570,24 @@ __device__ __forceinline__ void edge_fast_body(const Launch<EdgeSeg>& L, const i
   const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
   double phi = -(S.B[(long)c1 * nm + mem] - S.B[(long)c0 * nm + mem]) * m.e_invdc[e];
   if (SLOW) phi += S.slow[ee];
-  if (e >= S.upd_begin && e < S.upd_end) S.Udst[ee] = fma(S.c_dt, phi, S.U0[ee]);
+  if (e >= S.upd_begin && e < S.upd_end) {
+    const double u0 = S.U0[ee];
+    const double unew = fma(S.c_dt, phi, u0);
+    S.Udst[ee] = unew;
+    mirror_store(S.mir, e, ee, unew, u0, nm_log2);
+  }
+  double afin = 0.0;
   if (e >= S.acc_begin && e < S.acc_end) {
     const double a = S.acc_w * phi;
-    S.acc[ee] = S.acc_first ? a : S.acc[ee] + a;
+    afin = S.acc_first ? a : S.acc[ee] + a;
+    S.acc[ee] = afin;
   }
+  if (S.tail.kind != 0) tail_own_edge(S.tail, e, ee, nm_log2, afin);
 }
 
 template <bool SLOW, bool ONE>
 __global__ void __launch_bounds__(kBlock) k_edge_fast(const Launch<EdgeSeg> L) {
-  edge_fast_body<SLOW, ONE>(L, xcd_tile(blockIdx.x, gridDim.x));
+  edge_fast_body<SLOW, ONE>(L, edge_tile(L));
 }
 
 // ---------------------------------------------------------- prediction pass
@@ -508,10 +610,10 @@ __device__ __forceinline__ void predict_body(const Launch<PredSeg>& L, const int
     } else {
       hn = S.sv_h[t]; h1 = S.sv_h[nc + t]; h2 = S.sv_h[2 * nc + t]; h3 = S.sv_h[3 * nc + t];
     }
-    S.H0[i] = S.a * h3 + S.one_minus_a * hn;
-    S.H1[i] = S.a * h3 + S.invM * h1 + S.c * hn;
-    S.H2[i] = S.a * h3 + S.invM * h2 + S.c * hn;
-    S.H3[i] = S.ap * h3 + S.c * hn;
+    S.H0[i] = pred_n(S.a, h3, S.one_minus_a, hn);
+    S.H1[i] = pred_s(S.a, h3, S.invM, h1, S.c, hn);
+    S.H2[i] = pred_s(S.a, h3, S.invM, h2, S.c, hn);
+    S.H3[i] = pred_3(S.ap, h3, S.c, hn);
   } else if (t < nc + ne) {
     const long tt = t - nc;
     const long i = (long)S.e_begin * nm + tt;
@@ -522,9 +624,9 @@ __device__ __forceinline__ void predict_body(const Launch<PredSeg>& L, const int
     } else {
       un = S.sv_u[tt]; u1 = S.sv_u[ne + tt]; u2 = S.sv_u[2 * ne + tt]; u3 = S.sv_u[3 * ne + tt];
     }
-    S.U0[i] = S.a * u3 + S.one_minus_a * un;
-    S.U1[i] = S.a * u3 + S.invM * u1 + S.c * un;
-    S.U2[i] = S.a * u3 + S.invM * u2 + S.c * un;
+    S.U0[i] = pred_n(S.a, u3, S.one_minus_a, un);
+    S.U1[i] = pred_s(S.a, u3, S.invM, u1, S.c, un);
+    S.U2[i] = pred_s(S.a, u3, S.invM, u2, S.c, un);
   }
 }
 
@@ -857,7 +959,14 @@ static int blocks_for(Launch<S>& L, long (*items)(const S&), int bs) {
 static long cell_items(const CellSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
 static long vert_items(const VertSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
 static long prep_items(const PrepSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
-static long edge_items(const EdgeSeg& s) { return s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0; }
+static long tail_items(const StepTail& t, int nm_log2) {
+  if (t.kind == 1) return (long)(t.c_p - t.c_b) << nm_log2;
+  if (t.kind == 2) return ((long)(t.c_e - t.c_b) + (long)(t.e_e - t.e_q)) << nm_log2;
+  return 0;
+}
+static long edge_items(const EdgeSeg& s) {
+  return (s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0) + tail_items(s.tail, s.nm_log2);
+}
 static long pred_items(const PredSeg& s) {
   return ((long)(s.c_end - s.c_begin) + (long)(s.e_end - s.e_begin)) << s.nm_log2;
 }
@@ -940,9 +1049,20 @@ static bool group_slots(const Launch<EdgeSeg>& L) {
   return true;
 }
 
+// A one-segment momentum pass with folded work: its edge blocks keep the
+// XCD layout, the folded work's blocks follow round-robin.
+static void tail_layout(Launch<EdgeSeg>& L, int bs) {
+  L.xcd_n = 0;
+  const EdgeSeg& s = L.seg[0];
+  if (L.nseg != 1 || s.tail.kind == 0) return;
+  const long ne = s.end > s.begin ? (long)(s.end - s.begin) << s.nm_log2 : 0;
+  L.xcd_n = (int)((ne + bs - 1) / bs);
+}
+
 int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st, bool cells) {
   const int nb = blocks_for(L, edge_items, bs);
   if (nb == 0) return 0;
+  tail_layout(L, bs);
   if (cells) launch_edge_t<true, false>(L, drag, wind, nb, bs, st);
   else if (group_slots(L)) launch_edge_t<false, true>(L, drag, wind, nb, bs, st);
   else launch_edge_t<false, false>(L, drag, wind, nb, bs, st);
@@ -952,6 +1072,7 @@ int launch_edge(Launch<EdgeSeg> L, bool drag, bool wind, int bs, hipStream_t st,
 int launch_edge_fast(Launch<EdgeSeg> L, bool slow, int bs, hipStream_t st) {
   const int nb = blocks_for(L, edge_items, bs);
   if (nb == 0) return 0;
+  tail_layout(L, bs);
   if (slow) launch_segs(k_edge_fast<true, true>, k_edge_fast<true, false>, nb, bs, st, L);
   else launch_segs(k_edge_fast<false, true>, k_edge_fast<false, false>, nb, bs, st, L);
   return nb;

@@ -530,6 +530,11 @@ void build_plan(const HostMesh& m, const std::vector<int8_t>& lab4, const std::v
     R.cell_upd = {0, p.nF};
     R.cell_acc = (s == 2) ? Range{p.nF, nIF} : Range{0, 0};
   }
+  {
+    const Reads rd = stage_input_reads(a, p.fine[2], nonlinear);
+    p.fine3_cell_end = std::max(rd.max_cell + 1, p.fine[2].cell.e);
+    p.fine3_edge_end = std::max(rd.max_edge + 1, p.fine[2].edge.e);
+  }
 
   // ---- coarse advancement: suffix ranges by backward closure.  Every coarse
   // stage value is kept on the whole coarse region (the fine substeps read the

@@ -51,6 +51,10 @@ struct Plan {
   StageRanges coarse[3];   // coarse advancement (suffix ranges)
   StageRanges fine[3];     // fine substep (prefix ranges)
   int fine_depth_max = 0;  // deepest fine layer touched by the coarse sweep (hops)
+  // one past the largest cell / edge whose stage-input value (h, u) the third
+  // fine stage reads: interface two and the interior cells within its
+  // stencils hold the coarse stage values there (Sec. 2.2, step 4)
+  int fine3_cell_end = 0, fine3_edge_end = 0;
 };
 
 // Build the plan for FB-LTS (4-level labels) or for a global scheme (all

@@ -258,6 +258,23 @@ struct DevState {
     sv_h.alloc((size_t)4 * std::max(1, p.nIF1) * nm * 8);
     sv_u.alloc((size_t)4 * std::max(1, p.nIF1E) * nm * 8);
   }
+  // The fine substeps' own stage arrays and scratch (pipelined FB-LTS step:
+  // fine substep 0 runs beside the coarse stages 2 and 3, so neither may
+  // overwrite what the other reads); allocated on first use, zeroed once.
+  DevBuf Hf[4], Uf[3], hs_f, B_f, P_f, q_f;
+  void alloc_fine(const PermMesh& pm, hipStream_t st) {
+    const size_t Nc = (size_t)pm.N * nm, Ne = (size_t)pm.E * nm, Nv = (size_t)pm.V * nm;
+    if (hs_f.bytes >= Nc * 8 && P_f.bytes >= Ne * 32 && q_f.bytes >= Nv * 8) return;
+    DevBuf* cells[] = {&Hf[1], &Hf[2], &Hf[3], &hs_f, &B_f};
+    DevBuf* edges[] = {&Uf[1], &Uf[2]};
+    for (DevBuf* b : cells) b->alloc(Nc * 8);
+    for (DevBuf* b : edges) b->alloc(Ne * 8);
+    P_f.alloc(Ne * 32);
+    q_f.alloc(Nv * 8);
+    for (DevBuf* b : {&Hf[1], &Hf[2], &Hf[3], &hs_f, &B_f, &Uf[1], &Uf[2], &P_f, &q_f})
+      hip_check(hipMemsetAsync(b->p, 0, b->bytes, st), "hipMemsetAsync");
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+  }
 };
 
 struct Pass {
@@ -268,12 +285,12 @@ struct Pass {
   double* cdst = nullptr;          // COPY
   const double* csrc = nullptr;
   long cn = 0;
-  Launch<CellSeg> cell;
-  Launch<VertSeg> vert;
-  Launch<PrepSeg> prep;
-  Launch<EdgeSeg> edge;
-  Launch<PredSeg> pred;
-  Launch<AsmSeg> asmb;
+  Launch<CellSeg> cell{};
+  Launch<VertSeg> vert{};
+  Launch<PrepSeg> prep{};
+  Launch<EdgeSeg> edge{};
+  Launch<PredSeg> pred{};
+  Launch<AsmSeg> asmb{};
   std::vector<CycloneArgs> cycs;   // WIND (one per mesh)
   std::vector<long long*> clocks;  // TICK (one per mesh)
   // RK4 final: per segment (y, acc, n)
@@ -340,17 +357,221 @@ struct LaunchOpts {
   int graph_steps = 8;       // coarse steps per replayed hipGraph
   int persistent = 0;        // > 0: runs of passes in one cooperative launch each, with
                              // this many blocks per compute unit
+  bool pipeline = true;      // FB-LTS: fine substep 0 beside the coarse stages, prediction
+                             // and assembly folded into momentum passes
 };
 
+// Pipelined FB-LTS step: the same passes and arithmetic as the sequential
+// list (Sec. 2.2 steps 1-4), arranged into fewer dependent launches.
+//  * Fine substep 0 depends on the coarse advancement only through the
+//    interface-one predictions, and its stage j needs the coarse stage j
+//    values only: it runs on its own arrays (Hf, Uf) and scratch, as a second
+//    segment of the launches of coarse stage j + 1.  The coarse stages hand
+//    their values over as they form them (Mirror): the k = 0 prediction on
+//    interface one, and on stage 2 and 3 the values themselves where the
+//    third fine stage reads interface two and the interior.
+//  * The prediction for substep k + 1, and after the last substep the
+//    correction and assembly, are folded into the last momentum pass of
+//    substep k (StepTail) instead of launching on their own.
+// A coarse step is then 9M + 3 stencil launches instead of 10M + 10 (q_v
+// fused).  emit(which, k) appends one stage's passes: which 0..2 the coarse
+// stages, 3..5 the fine stages of substep k, 6 the per-substep slow terms.
+template <class Emit>
+void build_pipelined(MeshUnit& u, const Params& P, const Plan& pl, Emit emit, hipStream_t st) {
+  const fblts_params& p = P.p;
+  DevState& s = u.st;
+  s.alloc_fine(u.pm, st);
+  const int M = p.M, N = u.pm.N, E = u.pm.E, nm = s.nm;
+  auto take = [&](int which, int k) {
+    std::vector<Pass> keep;
+    keep.swap(u.passes);
+    emit(which, k);
+    std::vector<Pass> got;
+    got.swap(u.passes);
+    u.passes.swap(keep);
+    return got;
+  };
+  const int if1b = pl.nF, if1e = pl.nF + pl.nIF1, if2e = if1e + pl.nIF2;
+  const int if1eb = pl.nFE, if1ee = pl.nFE + pl.nIF1E, if2ee = if1ee + pl.nIF2E;
+  const int cend = std::max(pl.fine3_cell_end, if1e), eend = std::max(pl.fine3_edge_end, if1ee);
+  // the k = 0 prediction coefficients, formed as the prediction pass forms them
+  const double invM = 1.0 / M, c0 = (double)(M - 1) / (double)M, ap0 = (double)1 / (double)M;
+  auto internal = [](const char* what) { throw Err(FBLTS_EINVAL, std::string("internal: pipelined step: ") + what); };
+  auto add_bytes = [&](Pass& ps, double b) {
+    ps.model_bytes += b;
+    ps.comp_bytes += b;
+    if (ps.kind == Pass::EDGE) {
+      u.bytes_edge += b;
+      u.comp_edge += b;
+    } else if (ps.kind == Pass::CELL) {
+      u.bytes_cell += b;
+      u.comp_cell += b;
+    }
+  };
+  auto set_mirror = [&](std::vector<Pass>& v, Pass::Kind kind, Mirror m) {
+    if (m.e <= m.b) return;
+    for (Pass& ps : v) {
+      if (ps.kind != kind) continue;
+      int ub, ue, b, e;
+      if (kind == Pass::CELL) {
+        const CellSeg& c = ps.cell.seg[0];
+        ub = c.upd_begin, ue = c.upd_end, b = c.begin, e = c.end;
+      } else {
+        const EdgeSeg& c = ps.edge.seg[0];
+        ub = c.upd_begin, ue = c.upd_end, b = c.begin, e = c.end;
+      }
+      if (m.b < std::max(ub, b) || m.e > std::min(ue, e)) internal("hand-over range outside the coarse update");
+      if (kind == Pass::CELL) ps.cell.seg[0].mir = m;
+      else ps.edge.seg[0].mir = m;
+      add_bytes(ps, 8.0 * nm * ((double)(m.e - m.b) + (m.sv ? (double)(m.p - m.b) : 0.0)));
+      return;
+    }
+    internal("no pass to hand over from");
+  };
+  auto set_tail = [&](std::vector<Pass>& v, int k) {
+    for (Pass& ps : v) {
+      if (ps.kind != Pass::EDGE) continue;
+      EdgeSeg& e = ps.edge.seg[0];
+      StepTail t{};
+      t.c_b = if1b, t.c_p = if1e, t.c_q = if2e, t.c_e = N;
+      t.e_b = if1eb, t.e_p = if1ee, t.e_q = if2ee, t.e_e = E;
+      t.H0 = s.H[0].as<double>();
+      t.H1 = s.Hf[1].as<double>();
+      t.H2 = s.Hf[2].as<double>();
+      t.H3 = s.Hf[3].as<double>();
+      t.C1 = s.H[1].as<double>();
+      t.C2 = s.H[2].as<double>();
+      t.C3 = s.H[3].as<double>();
+      t.U0 = s.U[0].as<double>();
+      t.U1 = s.Uf[1].as<double>();
+      t.U2 = s.Uf[2].as<double>();
+      t.D1 = s.U[1].as<double>();
+      t.D2 = s.U[2].as<double>();
+      t.D3 = s.U[3].as<double>();
+      t.sv_h = s.sv_h.as<double>();
+      t.sv_u = s.sv_u.as<double>();
+      t.acc_h = s.acc_h.as<double>();
+      double b;
+      if (k + 1 < M) {
+        const int kk = k + 1;
+        t.kind = 1;
+        t.a = (double)kk / (double)M;
+        t.one_minus_a = (double)(M - kk) / (double)M;
+        t.invM = 1.0 / M;
+        t.c = (double)(M - kk - 1) / (double)M;
+        t.ap = (double)(kk + 1) / (double)M;
+        if (if1ee > if1eb && (e.begin > if1eb || e.end < if1ee)) internal("interface-one edges outside the pass");
+        b = 64.0 * (if1e - if1b) + 56.0 * (if1ee - if1eb);
+      } else {
+        t.kind = 2;
+        t.delta = p.dt / M;
+        if (if2ee > if1eb && (e.acc_begin > if1eb || e.acc_end < if2ee))
+          internal("interface edges outside the accumulation");
+        b = 24.0 * (if1e - if1b) + 24.0 * (if2e - if1e) + 16.0 * (N - if2e) + 16.0 * (if2ee - if1eb) +
+            16.0 * (E - if2ee);
+      }
+      if (e.end < e.begin) e.end = e.begin;
+      e.tail = t;
+      add_bytes(ps, b * nm);
+      return;
+    }
+    internal("no momentum pass to fold into");
+  };
+  // one launch for two stages' passes of a kind (segments of one launch)
+  auto rank = [](const Pass& q) {
+    switch (q.kind) {
+      case Pass::CELL: return 0;
+      case Pass::VERT: return 1;
+      case Pass::PREP: return 2;
+      case Pass::EDGE: return 3;
+      default: return 4;
+    }
+  };
+  auto nonempty = [](const Pass& q) {
+    switch (q.kind) {
+      case Pass::CELL: return q.cell.seg[0].end > q.cell.seg[0].begin;
+      case Pass::VERT: return q.vert.seg[0].end > q.vert.seg[0].begin;
+      case Pass::PREP: return q.prep.seg[0].end > q.prep.seg[0].begin;
+      case Pass::EDGE: return q.edge.seg[0].end > q.edge.seg[0].begin || q.edge.seg[0].tail.kind != 0;
+      default: return true;
+    }
+  };
+  auto merge2 = [&](const std::vector<Pass>& a, const std::vector<Pass>& b) {
+    std::vector<Pass> out;
+    size_t i = 0, j = 0;
+    while (i < a.size() || j < b.size()) {
+      if (j == b.size() || (i < a.size() && rank(a[i]) < rank(b[j]))) {
+        out.push_back(a[i++]);
+        continue;
+      }
+      if (i == a.size() || rank(b[j]) < rank(a[i])) {
+        out.push_back(b[j++]);
+        continue;
+      }
+      const Pass& x = a[i++];
+      const Pass& y = b[j++];
+      if (rank(x) > 3) internal("unexpected pass kind in a stage");
+      if (!nonempty(y)) {
+        out.push_back(x);
+        continue;
+      }
+      if (!nonempty(x)) {
+        out.push_back(y);
+        continue;
+      }
+      Pass m = x;
+      switch (m.kind) {
+        case Pass::CELL: m.cell.seg[m.cell.nseg++] = y.cell.seg[0]; break;
+        case Pass::VERT: m.vert.seg[m.vert.nseg++] = y.vert.seg[0]; break;
+        case Pass::PREP: m.prep.seg[m.prep.nseg++] = y.prep.seg[0]; break;
+        default: m.edge.seg[m.edge.nseg++] = y.edge.seg[0]; break;
+      }
+      m.model_bytes += y.model_bytes;
+      m.comp_bytes += y.comp_bytes;
+      out.push_back(m);
+    }
+    return out;
+  };
+  auto append = [&](const std::vector<Pass>& v) { u.passes.insert(u.passes.end(), v.begin(), v.end()); };
+
+  std::vector<Pass> C[3];
+  for (int j = 0; j < 3; ++j) C[j] = take(j, 0);
+  set_mirror(C[0], Pass::CELL, Mirror{s.Hf[1].as<double>(), s.sv_h.as<double>(), if1b, if1e, if1e, invM, c0});
+  set_mirror(C[0], Pass::EDGE, Mirror{s.Uf[1].as<double>(), s.sv_u.as<double>(), if1eb, if1ee, if1ee, invM, c0});
+  set_mirror(C[1], Pass::CELL, Mirror{s.Hf[2].as<double>(), nullptr, if1b, if1e, cend, invM, c0});
+  set_mirror(C[1], Pass::EDGE, Mirror{s.Uf[2].as<double>(), nullptr, if1eb, if1ee, eend, invM, c0});
+  set_mirror(C[2], Pass::CELL, Mirror{s.Hf[3].as<double>(), nullptr, if1b, if1e, cend, ap0, c0});
+  for (int k = 0; k < M; ++k) {
+    if (p.split == 2 && k > 0) append(take(6, k));
+    std::vector<Pass> F[3];
+    for (int j = 0; j < 3; ++j) F[j] = take(3 + j, k);
+    set_tail(F[2], k);
+    if (k == 0) {
+      append(C[0]);
+      append(merge2(C[1], F[0]));
+      append(merge2(C[2], F[1]));
+      append(F[2]);
+    } else {
+      for (auto& f : F) append(f);
+    }
+  }
+  u.cell_substeps = ((int64_t)(N - pl.nF) + (int64_t)M * pl.nF) * nm;
+}
+
 void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, const Plan* plan = nullptr,
-                       bool edge_cells = false) {
+                       bool edge_cells = false, bool pipeline = false, hipStream_t st = nullptr) {
   const fblts_params& p = P.p;
   const bool nl = P.nonlinear();
   const MeshDev& md = u.dm.md;
   DevState& s = u.st;
   auto H = [&](int k) { return s.H[k].as<double>(); };
   auto U = [&](int k) { return s.U[k].as<double>(); };
-  const double* qsrc = nl ? s.q.as<double>() : md.v_q0;
+  // stage scratch (h*, B, edge records, q_v): the fine substeps of a
+  // pipelined step switch to their own set
+  double* sc_hs = s.hs.as<double>();
+  double* sc_B = s.B.as<double>();
+  double* sc_P = s.P.as<double>();
+  double* sc_q = s.q.as<double>();
   u.passes.clear();
   int cur_tag = 0;
   u.bytes_edge = 0;
@@ -386,8 +607,8 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     c.H0 = H0;
     c.Hnew_src = Hnew_src;
     c.Hdst = Hdst;
-    c.hs = s.hs.as<double>();
-    c.B = s.B.as<double>();
+    c.hs = sc_hs;
+    c.B = sc_B;
     c.acc = acc;
     c.c_dt = c_dt;
     c.wn = wn;
@@ -413,8 +634,8 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     v.begin = r.vert.b;
     v.end = r.vert.e;
     v.Usrc = Usrc;
-    v.hs = s.hs.as<double>();
-    v.q = s.q.as<double>();
+    v.hs = sc_hs;
+    v.q = sc_q;
     ps.model_bytes = bytes_vert_pass(u.pm, r.vert, nm);
     ps.comp_bytes = compulsory_vert_pass(u.pm, r.vert, nm);
     ps.tag = cur_tag;
@@ -431,9 +652,9 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     q.end = r.prep.e;
     q.linear = nl ? 0 : 1;
     q.Usrc = Usrc;
-    q.hs = s.hs.as<double>();
-    q.q = qsrc;
-    q.P = s.P.as<double>();
+    q.hs = sc_hs;
+    q.q = nl ? sc_q : md.v_q0;
+    q.P = sc_P;
     ps.fuse_q = nl && fuse_q;
     ps.model_bytes = bytes_prep_pass(u.pm, r.prep, nl, nm, ps.fuse_q);
     // with q_v fused the prep pass references the vertex pass's arrays too
@@ -459,8 +680,8 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
     e.acc_begin = r.edge_acc.b;
     e.acc_end = r.edge_acc.e;
     e.acc_first = acc_first;
-    e.P = s.P.as<double>();
-    e.B = s.B.as<double>();
+    e.P = sc_P;
+    e.B = sc_B;
     e.Usrc = Usrc;
     e.U0 = U0;
     e.Udst = Udst;
@@ -559,6 +780,58 @@ void build_passes_impl(MeshUnit& u, const Params& P, bool drag_on, bool fuse_q, 
   if (p.split) {
     cur_tag = 0;
     slow_eval(full, H(0), U(0));
+  }
+  if (pipeline) {
+    build_pipelined(u, P, pl, [&](int which, int k) {
+      // which: 0..2 coarse stage, 3..5 fine stage of substep k, 6 the
+      // per-substep slow terms (split 2); the fine ones on the fine arrays
+      // and scratch
+      DevState& d = u.st;
+      auto Hf = [&](int j) { return j == 0 ? H(0) : d.Hf[j].as<double>(); };
+      auto Uf = [&](int j) { return j == 0 ? U(0) : d.Uf[j].as<double>(); };
+      const bool fine = which >= 3;
+      sc_hs = fine ? d.hs_f.as<double>() : d.hs.as<double>();
+      sc_B = fine ? d.B_f.as<double>() : d.B.as<double>();
+      sc_P = fine ? d.P_f.as<double>() : d.P.as<double>();
+      sc_q = fine ? d.q_f.as<double>() : d.q.as<double>();
+      double* ahp = d.acc_h.as<double>();
+      double* aup = d.acc_u.as<double>();
+      const double dl = dt / M;
+      switch (which) {
+        case 0:
+          cur_tag = 1;
+          stage(C[0], H(0), U(0), H(0), H(1), H(1), dt / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
+          break;
+        case 1:
+          cur_tag = 2;
+          stage(C[1], H(1), U(1), H(0), H(2), H(2), dt / 2, b2, 0.0, 1 - b2, nullptr, U(0), U(2), nullptr, 1, 1);
+          break;
+        case 2:
+          cur_tag = 3;
+          stage(C[2], H(2), U(2), H(0), H(3), H(3), dt, b3, 1 - 2 * b3, b3, nullptr, U(0), U(3), nullptr, 1, 1);
+          break;
+        case 3:
+          cur_tag = 100 + 10 * k + 1;
+          stage(pl.fine[0], H(0), U(0), H(0), Hf(1), Hf(1), dl / 3, b1, 0.0, 1 - b1, nullptr, U(0), Uf(1), nullptr,
+                1, 1);
+          break;
+        case 4:
+          cur_tag = 100 + 10 * k + 2;
+          stage(pl.fine[1], Hf(1), Uf(1), H(0), Hf(2), Hf(2), dl / 2, b2, 0.0, 1 - b2, nullptr, U(0), Uf(2), nullptr,
+                1, 1);
+          break;
+        case 5:
+          cur_tag = 100 + 10 * k + 3;
+          stage(pl.fine[2], Hf(2), Uf(2), H(0), Hf(3), H(0), dl, b3, 1 - 2 * b3, b3, ahp, U(0), U(0), aup, 1.0,
+                k == 0);
+          break;
+        case 6:
+          cur_tag = 100 + 10 * k;
+          slow_eval(pl.fine[2], H(0), U(0));
+          break;
+      }
+    }, st);
+    return;
   }
   cur_tag = 1;
   stage(C[0], H(0), U(0), H(0), H(1), H(1), dt / 3, b1, 0.0, 1 - b1, nullptr, U(0), U(1), nullptr, 1, 1);
@@ -662,11 +935,11 @@ void add_forcing_passes(MeshUnit& u) {
   u.passes.push_back(t);
 }
 
-void build_passes(MeshUnit& u, const Params& P, bool drag_on, const LaunchOpts& o) {
+void build_passes(MeshUnit& u, const Params& P, bool drag_on, const LaunchOpts& o, hipStream_t st) {
   const int bs = o.block;
   if (o.edge_cells && u.pm.kite_weights == 0)
     throw Err(FBLTS_EINVAL, "the mesh's edges_on_edge weights are not the kite-fraction walks of its cells");
-  build_passes_impl(u, P, drag_on, o.fuse_q, nullptr, o.edge_cells);
+  build_passes_impl(u, P, drag_on, o.fuse_q, nullptr, o.edge_cells, o.pipeline, st);
   add_forcing_passes(u);
   for (Pass& p : u.passes) p.bs = bs;
   ++u.version;
@@ -1216,7 +1489,12 @@ struct fblts_solver {
 
 struct fblts_ensemble {
   Params P;
-  LaunchOpts opt;
+  // ensemble launches hold one segment per mesh: the sequential step
+  LaunchOpts opt = [] {
+    LaunchOpts o;
+    o.pipeline = false;
+    return o;
+  }();
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<std::unique_ptr<MeshUnit>> units;
@@ -1419,13 +1697,13 @@ static void ensemble_run(fblts_ensemble* e, int n) {
 // Rebuild the pass lists after a change of launch options (drops the graphs).
 static void solver_rebuild(fblts_solver* s) {
   s->drop_graph();
-  if (s->have_regions) build_passes(*s->unit, s->P, s->drag_on, s->opt);
+  if (s->have_regions) build_passes(*s->unit, s->P, s->drag_on, s->opt, s->stream);
 }
 
 static void ensemble_rebuild(fblts_ensemble* e) {
   std::vector<MeshUnit*> units;
   for (auto& u : e->units) {
-    build_passes(*u, e->P, e->P.nonlinear(), e->opt);
+    build_passes(*u, e->P, e->P.nonlinear(), e->opt, e->stream);
     units.push_back(u.get());
   }
   e->passes = merge_passes(units);
@@ -1703,7 +1981,7 @@ int fblts_set_regions(fblts_solver* s, const int8_t* labels, int32_t binary) {
     setup_unit(*u, s->mesh->hm, s->P, labels, binary != 0, 1);
     s->unit = std::move(u);
     s->drag_on = false;
-    build_passes(*s->unit, s->P, s->drag_on, s->opt);
+    build_passes(*s->unit, s->P, s->drag_on, s->opt, s->stream);
     s->have_regions = true;
     return FBLTS_OK;
   });
@@ -1765,7 +2043,7 @@ int fblts_set_drag(fblts_solver* s, const double* cd, int32_t on_device) {
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
       s->drag_on = true;
     }
-    build_passes(u, s->P, s->drag_on, s->opt);
+    build_passes(u, s->P, s->drag_on, s->opt, s->stream);
     return FBLTS_OK;
   });
 }
@@ -1812,7 +2090,7 @@ int fblts_set_wind(fblts_solver* s, const double* wn, const double* wt, const do
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
       u.st.has_wind = true;
     }
-    build_passes(u, s->P, s->drag_on, s->opt);
+    build_passes(u, s->P, s->drag_on, s->opt, s->stream);
     return FBLTS_OK;
   });
 }
@@ -1937,7 +2215,7 @@ int fblts_set_cyclone(fblts_solver* s, const fblts_cyclone* c, const double* x_e
       launch_cyclone(u.st.cyc, s->stream);
       hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     }
-    build_passes(u, s->P, s->drag_on, s->opt);
+    build_passes(u, s->P, s->drag_on, s->opt, s->stream);
     return FBLTS_OK;
   });
 }
@@ -1983,6 +2261,8 @@ int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
     } else if (option == FBLTS_OPT_PERSISTENT) {
       if (value < 0 || value > 16) throw Err(FBLTS_EINVAL, "persistent: 0 (off) or blocks per compute unit, 1..16");
       s->opt.persistent = value;
+    } else if (option == FBLTS_OPT_PIPELINE) {
+      s->opt.pipeline = value != 0;
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
@@ -2307,7 +2587,7 @@ int fblts_ensemble_create(const fblts_mesh* const* meshes, const int8_t* const* 
       if (!meshes[k]) throw Err(FBLTS_EINVAL, "mesh is NULL");
       auto u = std::make_unique<MeshUnit>();
       setup_unit(*u, meshes[k]->hm, e->P, cell_labels ? cell_labels[k] : nullptr, binary != 0, nm);
-      build_passes(*u, e->P, e->P.nonlinear(), e->opt);
+      build_passes(*u, e->P, e->P.nonlinear(), e->opt, e->stream);
       units.push_back(u.get());
       e->units.push_back(std::move(u));
     }
@@ -2382,7 +2662,7 @@ int fblts_ensemble_set_cyclone(fblts_ensemble* e, int32_t mesh, int32_t member, 
     cyclone_member(U, member, q);
     std::vector<MeshUnit*> units;
     for (auto& u : e->units) {
-      build_passes(*u, e->P, e->P.nonlinear(), e->opt);
+      build_passes(*u, e->P, e->P.nonlinear(), e->opt, e->stream);
       units.push_back(u.get());
     }
     e->passes = merge_passes(units);
@@ -2424,6 +2704,8 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
     } else if (option == FBLTS_OPT_PERSISTENT) {
       if (value < 0 || value > 16) throw Err(FBLTS_EINVAL, "persistent: 0 (off) or blocks per compute unit, 1..16");
       e->opt.persistent = value;
+    } else if (option == FBLTS_OPT_PIPELINE) {
+      if (value != 0) throw Err(FBLTS_EINVAL, "ensembles run the sequential step (pipeline 0)");
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }

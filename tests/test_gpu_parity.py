@@ -269,7 +269,9 @@ def test_dispatch_timing_mode_counts_launches_and_keeps_results(cvt):
     ms, launches = s.kernel_time(0)
     info = s.info()
     assert ms > 0
-    assert launches % 3 == 0 and launches // 3 == 3 * (1 + w.M)   # 3 stages x (coarse + M fine)
+    # pipelined step: 3 stages x (coarse + M fine), the first two stages of
+    # fine substep 0 sharing the coarse stages 2 and 3's launches
+    assert launches % 3 == 0 and launches // 3 == 3 * (1 + w.M) - 2
     for cls in (1, 3):
         m2, n2 = s.kernel_time(cls)
         assert m2 > 0 and n2 > 0
@@ -278,6 +280,12 @@ def test_dispatch_timing_mode_counts_launches_and_keeps_results(cvt):
     hs, us = s.get_state()
     assert np.array_equal(hr, hs) and np.array_equal(ur, us)
     assert info["launches_per_step"] > 0
+    # the sequential step: one momentum launch per stage
+    s.set_option(F.OPT_PIPELINE, 0)
+    s.set_timing(True)
+    s.step(3)
+    assert s.kernel_time(0)[1] == 3 * 3 * (1 + w.M)
+    s.set_timing(False)
 
 
 def test_edge_cells_rejected_for_foreign_weights(cvt):
