@@ -62,10 +62,10 @@ __global__ void __launch_bounds__(kBlock) k_lincomb_batch(const LinBatch B) {
 
 // ------------------------------------------------------------ Psi transpose
 // Fbar_e = l_e (-pb_c0/A_c0 + pb_c1/A_c1); ub_e += Fbar_e h_e; T_e = Fbar_e u_e.
-__global__ void __launch_bounds__(kBlock) k_psi_vjp_edge(MeshDev m, int linear, const double* u, const double* h,
-                                                         const double* pb, double* ub, double* T) {
+__global__ void __launch_bounds__(kBlock) k_psi_vjp_edge(MeshDev m, int n_e, int linear, const double* u,
+                                                         const double* h, const double* pb, double* ub, double* T) {
   const int e = tid_global();
-  if (e >= m.E) return;
+  if (e >= n_e) return;
   const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
   const double fb = m.e_dv[e] * (pb[c1] * m.c_invA[c1] - pb[c0] * m.c_invA[c0]);
   const double he = linear ? m.e_He[e] : 0.5 * (h[c0] + h[c1]);
@@ -74,9 +74,9 @@ __global__ void __launch_bounds__(kBlock) k_psi_vjp_edge(MeshDev m, int linear, 
 }
 
 // hb_i += (1/2) sum_{e in E_i} T_e.
-__global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, const double* T, double* hb) {
+__global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, int n_c, const double* T, double* hb) {
   const int i = tid_global();
-  if (i >= m.N) return;
+  if (i >= n_c) return;
   const int n = m.c_nedge[i];
   const double hb0 = hb[i];
   double t[kUnrollCell];
@@ -92,11 +92,11 @@ __global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, const double
 
 // ------------------------------------------------------------ Phi transpose
 // Pass 1 (edges): G_e = fb_e/d_e; drag terms of d/du_e, d/du_perp_e, d/dh_e, d/dC_D.
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int drag, const double* u, const double* P,
-                                                       const double* cd, const double* fb, double* G, double* R,
-                                                       double* HD, double* CDB, double* ub) {
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int n_e, int drag, const double* u,
+                                                       const double* P, const double* cd, const double* fb, double* G,
+                                                       double* R, double* HD, double* CDB, double* ub) {
   const int e = tid_global();
-  if (e >= m.E) return;
+  if (e >= n_e) return;
   const double g = fb[e] * m.e_invdc[e];
   G[e] = g;
   if (!drag) return;
@@ -130,10 +130,10 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int drag, cons
 }
 
 // Pass 2 (cells): Bbar_i = sum n_{e,i} G_e; hsb_i += g Bbar_i.
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, double g, const double* G, double* BB,
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, int n_c, double g, const double* G, double* BB,
                                                        double* hsb) {
   const int i = tid_global();
-  if (i >= m.N) return;
+  if (i >= n_c) return;
   const int n = m.c_nedge[i];
   const double hsb0 = hsb[i];
   int code[kUnrollCell];
@@ -158,12 +158,12 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, double g, cons
 
 // Pass 3 (edges, edges_on_edge gathers): PV-flux transpose, drag perp transpose,
 // kinetic-energy transpose; writes qbar_e, and h_e's cotangent HE_e.
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int linear, int drag, const double* u,
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int n_e, int linear, int drag, const double* u,
                                                        const double* P, const double* G, const double* R,
                                                        const double* HD, const double* BB, double* QB, double* HE,
                                                        double* ub) {
   const int e = tid_global();
-  if (e >= m.E) return;
+  if (e >= n_e) return;
   const double2 pe = rec_fq(P, e);
   const int n = m.e_neoe[e];
   // the edge's own operands first, then every slot's loads together
@@ -224,10 +224,10 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e2(MeshDev m, int linear, in
 // (scaled by 1/A_v): ZA_v = qbar_v / (h_v A_v), HV_v = -qbar_v q_v / (h_v A_v).
 // q_v = (zeta_v + f_v) / h_v is formed here from u and hs with the operations,
 // in the order, of the forward's vertex PV.
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_v1(MeshDev m, const double* u, const double* hs,
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_v1(MeshDev m, int n_v, const double* u, const double* hs,
                                                        const double* QB, double* ZA, double* HV) {
   const int v = tid_global();
-  if (v >= m.V) return;
+  if (v >= n_v) return;
   int code[3], cell[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -251,8 +251,8 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_v1(MeshDev m, const double* 
   HV[v] = -qb * q / hvv * ia;
 }
 
-// Passes 5 and 6, independent of each other, in one launch: threads [0, E)
-// take the edges, threads [E, E + N) the cells.
+// Passes 5 and 6, independent of each other, in one launch: threads [0, n_e)
+// take the edges [0, n_e), threads [n_e, n_e + n_c) the cells [0, n_c).
 // Edges: ub_e += d_e (ZA_{v1} - ZA_{v0})  (circulation sign +1 at v1).
 // Cells: hsb_i += (1/2) sum_{e in E_i} HE_e + sum_{v in V_i} kite_{i,v} HV_v;
 // cdb_i += (1/2) sum_{e in E_i} CDB_e.
@@ -293,14 +293,14 @@ __device__ __forceinline__ void phi_vjp_c2(const MeshDev& m, int i, int drag, co
   if (drag) cdb[i] = fma(0.5, sc, cdb0);
 }
 
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_ec(MeshDev m, int drag, const double* ZA, const double* HE,
-                                                       const double* HV, const double* CDB, double* ub, double* hsb,
-                                                       double* cdb) {
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_ec(MeshDev m, int n_e, int n_c, int drag, const double* ZA,
+                                                       const double* HE, const double* HV, const double* CDB,
+                                                       double* ub, double* hsb, double* cdb) {
   const int t = tid_global();
-  if (t < m.E)
+  if (t < n_e)
     phi_vjp_e3(m, t, ZA, ub);
-  else if (t < m.E + m.N)
-    phi_vjp_c2(m, t - m.E, drag, HE, HV, CDB, hsb, cdb);
+  else if (t < n_e + n_c)
+    phi_vjp_c2(m, t - n_e, drag, HE, HV, CDB, hsb, cdb);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -318,24 +318,33 @@ void launch_lincomb_batch(const LinBatch& B, hipStream_t st) {
 }
 
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
-                    double* hb, double* T, hipStream_t st) {
-  hipLaunchKernelGGL(k_psi_vjp_edge, grid_for(m.E), dim3(kBlock), 0, st, m, linear, u, h, pb, ub, T);
-  if (!linear) hipLaunchKernelGGL(k_psi_vjp_cell, grid_for(m.N), dim3(kBlock), 0, st, m, (const double*)T, hb);
+                    double* hb, double* T, const PsiRange& r, hipStream_t st) {
+  if (r.ne > 0)
+    hipLaunchKernelGGL(k_psi_vjp_edge, grid_for(r.ne), dim3(kBlock), 0, st, m, r.ne, linear, u, h, pb, ub, T);
+  if (!linear && r.nc > 0)
+    hipLaunchKernelGGL(k_psi_vjp_cell, grid_for(r.nc), dim3(kBlock), 0, st, m, r.nc, (const double*)T, hb);
 }
 
 // Scratch: G, R, HD, CDB, HE, QB (edges), BB (cells), ZA, HV (vertices).
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
                     const double* P, const double* cd, const double* fb, double* ub, double* hsb,
                     double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
-                    double* ZA, double* HV, hipStream_t st) {
-  hipLaunchKernelGGL(k_phi_vjp_e1, grid_for(m.E), dim3(kBlock), 0, st, m, drag, u, P, cd, fb, G, R, HD, CDB, ub);
-  hipLaunchKernelGGL(k_phi_vjp_c1, grid_for(m.N), dim3(kBlock), 0, st, m, g, (const double*)G, BB, hsb);
-  hipLaunchKernelGGL(k_phi_vjp_e2, grid_for(m.E), dim3(kBlock), 0, st, m, linear, drag, u, P, (const double*)G,
-                     (const double*)R, (const double*)HD, (const double*)BB, QB, HE, ub);
+                    double* ZA, double* HV, const VjpRange& r, hipStream_t st) {
+  if (r.e1 > 0)
+    hipLaunchKernelGGL(k_phi_vjp_e1, grid_for(r.e1), dim3(kBlock), 0, st, m, r.e1, drag, u, P, cd, fb, G, R, HD,
+                       CDB, ub);
+  if (r.c1 > 0)
+    hipLaunchKernelGGL(k_phi_vjp_c1, grid_for(r.c1), dim3(kBlock), 0, st, m, r.c1, g, (const double*)G, BB, hsb);
+  if (r.e2 > 0)
+    hipLaunchKernelGGL(k_phi_vjp_e2, grid_for(r.e2), dim3(kBlock), 0, st, m, r.e2, linear, drag, u, P,
+                       (const double*)G, (const double*)R, (const double*)HD, (const double*)BB, QB, HE, ub);
   if (!linear) {
-    hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(m.V), dim3(kBlock), 0, st, m, u, hs, (const double*)QB, ZA, HV);
-    hipLaunchKernelGGL(k_phi_vjp_ec, grid_for((long)m.E + m.N), dim3(kBlock), 0, st, m, drag, (const double*)ZA,
-                       (const double*)HE, (const double*)HV, (const double*)CDB, ub, hsb, cdb);
+    if (r.v1 > 0)
+      hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(r.v1), dim3(kBlock), 0, st, m, r.v1, u, hs, (const double*)QB, ZA,
+                         HV);
+    if (r.e3 + r.c3 > 0)
+      hipLaunchKernelGGL(k_phi_vjp_ec, grid_for((long)r.e3 + r.c3), dim3(kBlock), 0, st, m, r.e3, r.c3, drag,
+                         (const double*)ZA, (const double*)HE, (const double*)HV, (const double*)CDB, ub, hsb, cdb);
   }
 }
 

@@ -19,4 +19,18 @@ struct LinBatch {
   LinDesc d[kLinBatch];
 };
 
+// Index ranges of the transposed tendency kernels for a cotangent supported
+// on a prefix of the edges (Phi) or of the cells (Psi) of the region-
+// contiguous numbering.  Every item past a kernel's range would add or store
+// an exact zero, so the kernel stops there; the intermediates a later kernel
+// reads past the range of the kernel that writes them are zeroed first, from
+// that range's end to the z* bound.
+struct VjpRange {
+  int e1, c1, e2, v1, e3, c3, pe;   // Phi passes 1-6, and the edge records they read
+  int zG, zR, zHD, zCDB, zBB, zQB, zHE, zZA, zHV;
+};
+struct PsiRange {
+  int ne, nc, zT;                   // Psi edge and cell passes, and T's zero-fill bound
+};
+
 }  // namespace fblts

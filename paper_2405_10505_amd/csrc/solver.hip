@@ -1174,11 +1174,11 @@ void launch_lincomb_batch(const LinBatch& B, hipStream_t st);
 void launch_lincomb(double* y, double b, const double* x0, double a0, const double* x1, double a1, const double* x2,
                     double a2, int begin, int end, hipStream_t st);
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
-                    double* hb, double* T, hipStream_t st);
+                    double* hb, double* T, const PsiRange& r, hipStream_t st);
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
                     const double* P, const double* cd, const double* fb, double* ub, double* hsb,
                     double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
-                    double* ZA, double* HV, hipStream_t st);
+                    double* ZA, double* HV, const VjpRange& r, hipStream_t st);
 }  // namespace fblts
 
 namespace {
@@ -1214,6 +1214,10 @@ struct Rev {
   double* HV;
   double* P;
   hipStream_t st;
+  // transpose ranges: the whole mesh (coarse stages), and the fine stages'
+  // cotangent supports (stages 1-2: fine rows; stage 3: with the interfaces)
+  VjpRange phi_all, phi_f12, phi_f3;
+  PsiRange psi_all, psi_f12, psi_f3;
   // Inside a reverse step the elementwise combinations between two tendency
   // transposes are collected and launched as one batch (same arithmetic per
   // element, in the same order); elsewhere each launches at once.
@@ -1238,21 +1242,36 @@ struct Rev {
   void zero(double* y, int lo, int hi) { lin(y, 0.0, nullptr, 0, nullptr, 0, nullptr, 0, lo, hi); }
   void set(double* y, double a, const double* x, int lo, int hi) { lin(y, 0.0, x, a, nullptr, 0, nullptr, 0, lo, hi); }
   void axpy(double* y, double a, const double* x, int lo, int hi) { lin(y, 1.0, x, a, nullptr, 0, nullptr, 0, lo, hi); }
-  void psi_vjp(const double* u, const double* h, const double* pbar, double* ubar, double* hbar) {
+  // cotangent pbar of Psi(u, h) (zero past the range's support) -> ubar, hbar (accumulated)
+  void psi_vjp(const double* u, const double* h, const double* pbar, double* ubar, double* hbar,
+               const PsiRange& r) {
+    zero(Ed[Ta], r.ne, r.zT);
     flush();
-    launch_psi_vjp(*m, linear ? 1 : 0, u, h, pbar, ubar, hbar, Ed[Ta], st);
+    launch_psi_vjp(*m, linear ? 1 : 0, u, h, pbar, ubar, hbar, Ed[Ta], r, st);
   }
-  // cotangent fbar of Phi(u, hs) -> ubar (accumulated), hsbar (overwritten), C_D (accumulated)
-  void phi_vjp(const double* u, const double* hs, const double* fbar, double* ubar, double* hsbar) {
+  // cotangent fbar of Phi(u, hs) (zero past the range's support) -> ubar
+  // (accumulated), hsbar (overwritten), C_D (accumulated)
+  void phi_vjp(const double* u, const double* hs, const double* fbar, double* ubar, double* hsbar,
+               const VjpRange& r) {
     zero(hsbar, 0, N);
+    zero(Ed[Ga], r.e1, r.zG);
+    zero(Ed[Ra], r.e1, r.zR);
+    zero(Ed[HDa], r.e1, r.zHD);
+    zero(Ed[CDBa], r.e1, r.zCDB);
+    zero(C[BBa], r.c1, r.zBB);
+    zero(Ed[QBa], r.e2, r.zQB);
+    zero(Ed[HEa], r.e2, r.zHE);
+    zero(ZA, r.v1, r.zZA);
+    zero(HV, r.v1, r.zHV);
     flush();
-    // forward intermediates at the point: the edge record (q_v evaluated inside)
+    // forward intermediates at the point: the edge records the passes read
+    // (q_v evaluated inside)
     Launch<PrepSeg> pp{};
     pp.nseg = 1;
-    pp.seg[0] = PrepSeg{*m, 0, 0, E, linear ? 1 : 0, u, hs, linear ? m->v_q0 : nullptr, P};
+    pp.seg[0] = PrepSeg{*m, 0, 0, r.pe, linear ? 1 : 0, u, hs, linear ? m->v_q0 : nullptr, P};
     launch_prep(pp, !linear, kBlock, st);
     launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, cd, fbar, ubar, hsbar, C[cdb], Ed[Ga], Ed[Ra],
-                   Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, st);
+                   Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, r, st);
   }
   // One reverse step: (hNb, uNb) = cotangent of the step's output -> (hb, ub)
   // = cotangent of its input; C_D's cotangent accumulates.  tc / te: tape.
@@ -1300,7 +1319,7 @@ struct Rev {
       set(e[fb], 1.0, e[aub], nFE, if2ee);
       axpy(e[U0b], 1.0, e[U3Fb], 0, nFE);
       lin(c[hspt], 0.0, H3k, b3, H2k, 1.0 - 2.0 * b3, H0k, b3, 0, N);
-      phi_vjp(U2k, c[hspt], e[fb], e[U2b], c[hsb]);
+      phi_vjp(U2k, c[hspt], e[fb], e[U2b], c[hsb], phi_f3);
       lin(c[H3b], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
       lin(c[H2b], 1.0, c[hsb], 1.0 - 2.0 * b3, nullptr, 0, nullptr, 0, 0, N);
       lin(c[H0b], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
@@ -1310,14 +1329,14 @@ struct Rev {
       set(c[pb], 1.0, c[ahb], nF, if2e);
       axpy(c[H0b], 1.0, c[H3b], 0, nF);
       zero(c[H3b], 0, nF);
-      psi_vjp(U2k, H2k, c[pb], e[U2b], c[H2b]);
+      psi_vjp(U2k, H2k, c[pb], e[U2b], c[H2b], psi_f3);
       // stage 2, momentum: U2[Fe] = U0 + delta/2 Phi(U1, hs2)
       zero(e[fb], 0, E);
       set(e[fb], delta / 2, e[U2b], 0, nFE);
       axpy(e[U0b], 1.0, e[U2b], 0, nFE);
       zero(e[U2b], 0, nFE);
       lin(c[hspt], 0.0, H2k, b2, H0k, 1.0 - b2, nullptr, 0, 0, N);
-      phi_vjp(U1k, c[hspt], e[fb], e[U1b], c[hsb]);
+      phi_vjp(U1k, c[hspt], e[fb], e[U1b], c[hsb], phi_f12);
       lin(c[H2b], 1.0, c[hsb], b2, nullptr, 0, nullptr, 0, 0, N);
       lin(c[H0b], 1.0, c[hsb], 1.0 - b2, nullptr, 0, nullptr, 0, 0, N);
       // stage 2, thickness: H2[F] = H0 + delta/2 Psi(U1, H1)
@@ -1325,14 +1344,14 @@ struct Rev {
       set(c[pb], delta / 2, c[H2b], 0, nF);
       axpy(c[H0b], 1.0, c[H2b], 0, nF);
       zero(c[H2b], 0, nF);
-      psi_vjp(U1k, H1k, c[pb], e[U1b], c[H1b]);
+      psi_vjp(U1k, H1k, c[pb], e[U1b], c[H1b], psi_f12);
       // stage 1, momentum: U1[Fe] = U0 + delta/3 Phi(U0, hs1)
       zero(e[fb], 0, E);
       set(e[fb], delta / 3, e[U1b], 0, nFE);
       axpy(e[U0b], 1.0, e[U1b], 0, nFE);
       zero(e[U1b], 0, nFE);
       lin(c[hspt], 0.0, H1k, b1, H0k, 1.0 - b1, nullptr, 0, 0, N);
-      phi_vjp(U0k, c[hspt], e[fb], e[U0b], c[hsb]);
+      phi_vjp(U0k, c[hspt], e[fb], e[U0b], c[hsb], phi_f12);
       lin(c[H1b], 1.0, c[hsb], b1, nullptr, 0, nullptr, 0, 0, N);
       lin(c[H0b], 1.0, c[hsb], 1.0 - b1, nullptr, 0, nullptr, 0, 0, N);
       // stage 1, thickness: H1[F] = H0 + delta/3 Psi(U0, H0)
@@ -1340,7 +1359,7 @@ struct Rev {
       set(c[pb], delta / 3, c[H1b], 0, nF);
       axpy(c[H0b], 1.0, c[H1b], 0, nF);
       zero(c[H1b], 0, nF);
-      psi_vjp(U0k, H0k, c[pb], e[U0b], c[H0b]);
+      psi_vjp(U0k, H0k, c[pb], e[U0b], c[H0b], psi_f12);
       // interface-one prediction (eq. preds) of substep k
       const double a = (double)k / (double)M, oma = (double)(M - k) / (double)M;
       const double cc = (double)(M - k - 1) / (double)M, ap = (double)(k + 1) / (double)M, iM = 1.0 / M;
@@ -1369,31 +1388,31 @@ struct Rev {
     axpy(e[ub], 1.0, e[u3b], 0, E);
     set(e[fb], dt, e[u3b], 0, E);
     lin(c[hspt], 0.0, h3, b3, h2, 1.0 - 2.0 * b3, h, b3, 0, N);
-    phi_vjp(u2, c[hspt], e[fb], e[u2b], c[hsb]);
+    phi_vjp(u2, c[hspt], e[fb], e[u2b], c[hsb], phi_all);
     lin(c[h3b], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
     lin(c[h2b], 1.0, c[hsb], 1.0 - 2.0 * b3, nullptr, 0, nullptr, 0, 0, N);
     lin(c[hb], 1.0, c[hsb], b3, nullptr, 0, nullptr, 0, 0, N);
     axpy(c[hb], 1.0, c[h3b], 0, N);
     set(c[pb], dt, c[h3b], 0, N);
-    psi_vjp(u2, h2, c[pb], e[u2b], c[h2b]);
+    psi_vjp(u2, h2, c[pb], e[u2b], c[h2b], psi_all);
     axpy(e[ub], 1.0, e[u2b], 0, E);
     set(e[fb], dt / 2, e[u2b], 0, E);
     lin(c[hspt], 0.0, h2, b2, h, 1.0 - b2, nullptr, 0, 0, N);
-    phi_vjp(u1, c[hspt], e[fb], e[u1b], c[hsb]);
+    phi_vjp(u1, c[hspt], e[fb], e[u1b], c[hsb], phi_all);
     lin(c[h2b], 1.0, c[hsb], b2, nullptr, 0, nullptr, 0, 0, N);
     lin(c[hb], 1.0, c[hsb], 1.0 - b2, nullptr, 0, nullptr, 0, 0, N);
     axpy(c[hb], 1.0, c[h2b], 0, N);
     set(c[pb], dt / 2, c[h2b], 0, N);
-    psi_vjp(u1, h1, c[pb], e[u1b], c[h1b]);
+    psi_vjp(u1, h1, c[pb], e[u1b], c[h1b], psi_all);
     axpy(e[ub], 1.0, e[u1b], 0, E);
     set(e[fb], dt / 3, e[u1b], 0, E);
     lin(c[hspt], 0.0, h1, b1, h, 1.0 - b1, nullptr, 0, 0, N);
-    phi_vjp(u, c[hspt], e[fb], e[ub], c[hsb]);
+    phi_vjp(u, c[hspt], e[fb], e[ub], c[hsb], phi_all);
     lin(c[h1b], 1.0, c[hsb], b1, nullptr, 0, nullptr, 0, 0, N);
     lin(c[hb], 1.0, c[hsb], 1.0 - b1, nullptr, 0, nullptr, 0, 0, N);
     axpy(c[hb], 1.0, c[h1b], 0, N);
     set(c[pb], dt / 3, c[h1b], 0, N);
-    psi_vjp(u, h, c[pb], e[ub], c[hb]);
+    psi_vjp(u, h, c[pb], e[ub], c[hb], psi_all);
     flush();
     batching = false;
   }
@@ -2922,6 +2941,89 @@ static Rev make_rev(fblts_solver* s, AdjointState& A) {
   r.HV = r.ZA + r.V;
   r.P = A.Pf.as<double>();
   r.st = s->stream;
+  // Prefix closures through the permuted mesh's incidence lists: one past
+  // the largest index a range of entities reaches.
+  const PermMesh& pm = u.pm;
+  auto cells_of_edges = [&](int ne) {
+    int x = 0;
+    for (int e = 0; e < ne; ++e) x = std::max({x, pm.e_cell[e] + 1, pm.e_cell[(size_t)pm.es + e] + 1});
+    return x;
+  };
+  auto edges_of_cells = [&](int nc) {
+    int x = 0;
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < pm.c_nedge[i]; ++j) x = std::max(x, (pm.c_edge[(size_t)j * pm.cs + i] >> 1) + 1);
+    return x;
+  };
+  auto eoe_of_edges = [&](int ne) {
+    int x = ne;
+    for (int e = 0; e < ne; ++e)
+      for (int j = 0; j < pm.e_neoe[e]; ++j) x = std::max(x, pm.e_eoe[(size_t)j * pm.es + e] + 1);
+    return x;
+  };
+  auto verts_of_edges = [&](int ne) {
+    int x = 0;
+    for (int e = 0; e < ne; ++e) x = std::max({x, pm.e_vert[e] + 1, pm.e_vert[(size_t)pm.es + e] + 1});
+    return x;
+  };
+  auto edges_of_verts = [&](int nv) {
+    int x = 0;
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < 3; ++j) x = std::max(x, (pm.v_edge[(size_t)j * pm.vs + v] >> 1) + 1);
+    return x;
+  };
+  auto cells_of_verts = [&](int nv) {
+    int x = 0;
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < 3; ++j) x = std::max(x, pm.v_cell[(size_t)j * pm.vs + v] + 1);
+    return x;
+  };
+  auto verts_of_cells = [&](int nc) {
+    int x = 0;
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < pm.c_nedge[i]; ++j) x = std::max(x, pm.c_vert[(size_t)j * pm.cs + i] + 1);
+    return x;
+  };
+  // Phi with its cotangent on edges [0, fe): pass 1 forms G (and the drag
+  // terms) there; pass 2 sums G over cells; pass 3 gathers G, R and the
+  // records over edges_on_edge and B-bar at the edge's cells; pass 4 sums
+  // q-bar over vertices; passes 5-6 spread the vertex terms to edges and
+  // cells.  Each z bound is the reach of the readers of an intermediate.
+  auto phi_range = [&](int fe) {
+    VjpRange q;
+    q.e1 = fe;
+    q.c1 = cells_of_edges(fe);
+    q.e2 = std::max({fe, eoe_of_edges(fe), edges_of_cells(q.c1)});
+    q.v1 = verts_of_edges(q.e2);
+    q.e3 = edges_of_verts(q.v1);
+    q.c3 = std::max(cells_of_edges(q.e2), cells_of_verts(q.v1));
+    q.pe = eoe_of_edges(q.e2);
+    q.zG = std::max(edges_of_cells(q.c1), q.pe);
+    q.zR = q.pe;
+    q.zHD = q.e2;
+    q.zCDB = edges_of_cells(q.c3);
+    q.zBB = cells_of_edges(q.e2);
+    q.zQB = edges_of_verts(q.v1);
+    q.zHE = q.zCDB;
+    q.zZA = verts_of_edges(q.e3);
+    q.zHV = verts_of_cells(q.c3);
+    return q;
+  };
+  // Psi with its cotangent on cells [0, pc): the edge pass over the cells'
+  // edges, the cell pass over those edges' cells.
+  auto psi_range = [&](int pc) {
+    PsiRange q;
+    q.ne = edges_of_cells(pc);
+    q.nc = cells_of_edges(q.ne);
+    q.zT = edges_of_cells(q.nc);
+    return q;
+  };
+  r.phi_all = VjpRange{r.E, r.N, r.E, r.V, r.E, r.N, r.E, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  r.psi_all = PsiRange{r.E, r.N, 0};
+  r.phi_f12 = phi_range(r.nFE);
+  r.phi_f3 = phi_range(r.if2ee);
+  r.psi_f12 = psi_range(r.nF);
+  r.psi_f3 = psi_range(r.if2e);
   return r;
 }
 
@@ -3158,10 +3260,10 @@ int fblts_debug_vjp(fblts_solver* s, int32_t which, const double* h, const doubl
     r.zero(r.C[cdb], 0, N);
     if (which == 0) {
       launch_permute(r.C[pb], tc.as<double>(), U.dm.cell_n2o.as<int>(), N, 0, 0, 1, s->stream);
-      r.psi_vjp(r.Ed[U3Fb], r.C[hspt], r.C[pb], r.Ed[ub], r.C[hb]);
+      r.psi_vjp(r.Ed[U3Fb], r.C[hspt], r.C[pb], r.Ed[ub], r.C[hb], r.psi_all);
     } else {
       launch_permute(r.Ed[fb], tc.as<double>(), U.dm.edge_n2o.as<int>(), E, 0, 0, 1, s->stream);
-      r.phi_vjp(r.Ed[U3Fb], r.C[hspt], r.Ed[fb], r.Ed[ub], r.C[hb]);
+      r.phi_vjp(r.Ed[U3Fb], r.C[hspt], r.Ed[fb], r.Ed[ub], r.C[hb], r.phi_all);
     }
     launch_permute(dh.as<double>(), r.C[hb], U.dm.cell_n2o.as<int>(), N, 0, 0, 0, s->stream);
     launch_permute(du.as<double>(), r.Ed[ub], U.dm.edge_n2o.as<int>(), E, 0, 0, 0, s->stream);
