@@ -261,7 +261,8 @@ int fblts_step(fblts_solver* s, int32_t n_coarse_steps);
 int fblts_set_graph(fblts_solver* s, int32_t enable);
 
 /* Tuning options (same results bit for bit, different launch structure);
- * each drops any captured graph:
+ * each drops any captured graph.  FUSE_VERTEX, EDGE_CELLS and PIPELINE take
+ * 0 (off) or 1 (on):
  *   FBLTS_OPT_FUSE_VERTEX: 1 (default) evaluates the vertex PV q_v inside the
  *     per-edge prep pass, one launch fewer per stage; 0 runs a vertex pass.
  *   FBLTS_OPT_BLOCK: threads per block of the stencil passes, 64/128/256

@@ -18,6 +18,12 @@ constexpr int kBlock = 256;      // threads per block for the stencil passes
 // on Voronoi meshes, finish in a loop.
 constexpr int kUnrollCell = 7;
 constexpr int kUnrollEOE = 12;
+// Of those, the momentum pass fetches the weights of slots from kEOEFull on
+// only where the edge's list reaches them: a padded slot's load re-reads the
+// edge's slot-0 weight (a line already being fetched) and +0 replaces the
+// value.  On a mostly hexagonal mesh nearly every list fills 10 slots and few
+// fill 11, so most lines of those slots' weights are never fetched.
+constexpr int kEOEFull = 10;
 
 // Permuted mesh, device pointers.  Edge codes carry a sign bit:
 // code = 2*e + (sign < 0 ? 1 : 0).

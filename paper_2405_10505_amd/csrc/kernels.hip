@@ -498,15 +498,19 @@ __device__ __forceinline__ void edge_body(const Launch<EdgeSeg>& L, const int b)
     const int n = m.e_neoe[e];
     auto slot = [&](int j) {
       const int e2 = m.e_eoe[j * m.es + e];
-      const double w = m.e_w[j * m.es + e];
+      const bool real = j < kEOEFull || j < n;
+      const double w0 = m.e_w[(real ? j * m.es : 0) + e];
+      const double w = real ? w0 : 0.0;
       const long k2 = (long)e2 * nm + mem;
       const double2 p2 = rec_fq(P, k2);
       sq = fma(w * p2.x, pey + p2.y, sq);
       if (DRAG || WIND) su = fma(w, rec_lu(P, np, k2), su);
     };
     // the first kUnrollEOE slots exist for every edge (padded with the edge
-    // itself at weight 0, an exact no-op): their loads issue together; the
-    // loop covers the rare longer lists
+    // itself at weight 0, an exact no-op): their index loads issue together;
+    // a padded slot past kEOEFull loads the edge's slot-0 weight instead of
+    // its own and takes +0 (the stored value, so the same bits) with no line
+    // of padding fetched; the loop covers the rare longer lists
 #pragma unroll
     for (int j = 0; j < kUnrollEOE; ++j) slot(j);
     for (int j = kUnrollEOE; j < n; ++j) slot(j);

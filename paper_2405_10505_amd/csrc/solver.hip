@@ -2260,13 +2260,19 @@ int fblts_get_wind(fblts_solver* s, double* wn, double* wt, double* wc) {
   });
 }
 
+// An on/off option's value: 0 or 1, anything else is refused.
+static bool on_off(int32_t value, const char* name) {
+  if (value != 0 && value != 1) throw Err(FBLTS_EINVAL, std::string(name) + ": 0 (off) or 1 (on)");
+  return value == 1;
+}
+
 int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
   return guarded([&] {
     if (!s) throw Err(FBLTS_EINVAL, "solver is NULL");
     hip_check(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
     s->drop_graph();
     if (option == FBLTS_OPT_FUSE_VERTEX) {
-      s->opt.fuse_q = value != 0;
+      s->opt.fuse_q = on_off(value, "fuse_vertex");
     } else if (option == FBLTS_OPT_BLOCK) {
       if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
       s->opt.block = value;
@@ -2276,12 +2282,12 @@ int fblts_set_option(fblts_solver* s, int32_t option, int32_t value) {
     } else if (option == FBLTS_OPT_EDGE_CELLS) {
       if (value && (!s->have_regions || s->unit->pm.kite_weights == 0))
         throw Err(FBLTS_EINVAL, "edge-via-cells needs set_regions first and kite-derived TRiSK weights");
-      s->opt.edge_cells = value != 0;
+      s->opt.edge_cells = on_off(value, "edge_cells");
     } else if (option == FBLTS_OPT_PERSISTENT) {
       if (value < 0 || value > 16) throw Err(FBLTS_EINVAL, "persistent: 0 (off) or blocks per compute unit, 1..16");
       s->opt.persistent = value;
     } else if (option == FBLTS_OPT_PIPELINE) {
-      s->opt.pipeline = value != 0;
+      s->opt.pipeline = on_off(value, "pipeline");
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }
@@ -2708,7 +2714,7 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
     if (!e) throw Err(FBLTS_EINVAL, "ensemble is NULL");
     hip_check(hipStreamSynchronize(e->stream), "hipStreamSynchronize");
     if (option == FBLTS_OPT_FUSE_VERTEX) {
-      e->opt.fuse_q = value != 0;
+      e->opt.fuse_q = on_off(value, "fuse_vertex");
     } else if (option == FBLTS_OPT_BLOCK) {
       if (value != 64 && value != 128 && value != 256) throw Err(FBLTS_EINVAL, "block size must be 64, 128 or 256");
       e->opt.block = value;
@@ -2719,12 +2725,12 @@ int fblts_ensemble_set_option(fblts_ensemble* e, int32_t option, int32_t value) 
       for (auto& u : e->units)
         if (value && u->pm.kite_weights == 0)
           throw Err(FBLTS_EINVAL, "edge-via-cells needs kite-derived TRiSK weights on every mesh");
-      e->opt.edge_cells = value != 0;
+      e->opt.edge_cells = on_off(value, "edge_cells");
     } else if (option == FBLTS_OPT_PERSISTENT) {
       if (value < 0 || value > 16) throw Err(FBLTS_EINVAL, "persistent: 0 (off) or blocks per compute unit, 1..16");
       e->opt.persistent = value;
     } else if (option == FBLTS_OPT_PIPELINE) {
-      if (value != 0) throw Err(FBLTS_EINVAL, "ensembles run the sequential step (pipeline 0)");
+      if (on_off(value, "pipeline")) throw Err(FBLTS_EINVAL, "ensembles run the sequential step (pipeline 0)");
     } else {
       throw Err(FBLTS_EINVAL, "unknown option");
     }

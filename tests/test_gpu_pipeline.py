@@ -138,3 +138,16 @@ def test_ensembles_run_the_sequential_step():
     ens.set_option(F.OPT_PIPELINE, 0)
     with pytest.raises(F.FBLTSError):
         ens.set_option(F.OPT_PIPELINE, 1)
+
+
+def test_on_off_options_take_zero_or_one(cvt):
+    w, fm = cvt
+    s = _solver(fm, w, 1)
+    for opt in (F.OPT_PIPELINE, F.OPT_FUSE_VERTEX, F.OPT_EDGE_CELLS):
+        with pytest.raises(F.FBLTSError):
+            s.set_option(opt, 2)
+        with pytest.raises(F.FBLTSError):
+            s.set_option(opt, -1)
+    # a refused value leaves the solver's options as they were
+    s.step(2)
+    assert s.info()["launches_per_step"] == 9 * w.M + 3
