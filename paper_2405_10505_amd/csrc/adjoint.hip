@@ -12,8 +12,9 @@
 // F_e = h_e u_e.  Momentum tendency (eq. trisk_vorticity with eq.
 // nonlinear_swe and the quadratic drag of eq. hurricane_model):
 // Phi_e = (1/d_e) sum w_{e,e'} (lF)_e' (q_e+q_e')/2 - (B_c1-B_c0)/d_e - C_D |u| u / h_e.
-// The edge record at the point (lF, q_e, l u, h_e) comes from the forward prep
-// pass (q_v evaluated inside it); the vertex transpose forms q_v itself.
+// The edge records at the point (lF, q_e, l u, h_e) are computed as the
+// forward's prep pass computes them (q_v evaluated inside), in the first
+// launch of the Phi transpose; the vertex transpose forms q_v itself.
 #include <hip/hip_runtime.h>
 
 #include "fblts_internal.h"
@@ -92,32 +93,36 @@ __global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, int n_c, con
 
 // ------------------------------------------------------------ Phi transpose
 // Pass 1 (edges): G_e = fb_e/d_e; drag terms of d/du_e, d/du_perp_e, d/dh_e, d/dC_D.
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int n_e, int drag, const double* u,
-                                                       const double* P, const double* cd, const double* fb, double* G,
-                                                       double* R, double* HD, double* CDB, double* ub) {
-  const int e = tid_global();
-  if (e >= n_e) return;
+// h_e and the neighbours' l u are formed from u and h* as the edge records
+// form them (the same operations), so this pass does not wait for the records.
+__device__ __forceinline__ void phi_vjp_e1(const MeshDev& m, int e, bool linear, int drag, const double* u,
+                                           const double* hs, const double* cd, const double* fb, double* G,
+                                           double* R, double* HD, double* CDB, double* ub) {
   const double g = fb[e] * m.e_invdc[e];
   G[e] = g;
   if (!drag) return;
   const int n = m.e_neoe[e];
   // the edge's own operands first, then every slot's loads together
   const double ue = u[e];
-  const double he = rec_he(P, m.E, e);
   const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
+  const double he = linear ? m.e_He[e] : 0.5 * (hs[c0] + hs[c1]);
   const double cde = 0.5 * (cd[c0] + cd[c1]);
   const double ub0 = ub[e];
   double w[kUnrollEOE], lu[kUnrollEOE];
 #pragma unroll
   for (int j = 0; j < kUnrollEOE; ++j) {
+    const int e2 = m.e_eoe[j * m.es + e];
     w[j] = m.e_w[j * m.es + e];
-    lu[j] = rec_lu(P, m.E, m.e_eoe[j * m.es + e]);
+    lu[j] = m.e_dv[e2] * u[e2];
   }
   double su = 0.0;
 #pragma unroll
   for (int j = 0; j < kUnrollEOE; ++j)
     if (j < n) su = fma(w[j], lu[j], su);
-  for (int j = kUnrollEOE; j < n; ++j) su = fma(m.e_w[j * m.es + e], rec_lu(P, m.E, m.e_eoe[j * m.es + e]), su);
+  for (int j = kUnrollEOE; j < n; ++j) {
+    const int e2 = m.e_eoe[j * m.es + e];
+    su = fma(m.e_w[j * m.es + e], m.e_dv[e2] * u[e2], su);
+  }
   const double up = su * m.e_invdc[e];
   const double sp = sqrt(ue * ue + up * up);
   // D = C_D |u| u / h_e, Phi -= D; |u| u is C^1 with zero derivative at |u| = 0
@@ -129,11 +134,10 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_e1(MeshDev m, int n_e, int d
   CDB[e] = -fb[e] * sp * ue / he;
 }
 
-// Pass 2 (cells): Bbar_i = sum n_{e,i} G_e; hsb_i += g Bbar_i.
-__global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, int n_c, double g, const double* G, double* BB,
-                                                       double* hsb) {
-  const int i = tid_global();
-  if (i >= n_c) return;
+// Pass 2 (cells): Bbar_i = sum n_{e,i} G_e; hsb_i += g Bbar_i (G_e formed
+// from fb as pass 1 forms it, so this pass does not wait for pass 1).
+__device__ __forceinline__ void phi_vjp_c1(const MeshDev& m, int i, double g, const double* fb, double* BB,
+                                           double* hsb) {
   const int n = m.c_nedge[i];
   const double hsb0 = hsb[i];
   int code[kUnrollCell];
@@ -141,7 +145,8 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, int n_c, doubl
 #pragma unroll
   for (int j = 0; j < kUnrollCell; ++j) {
     code[j] = m.c_edge[j * m.cs + i];
-    x[j] = G[code[j] >> 1];
+    const int e = code[j] >> 1;
+    x[j] = fb[e] * m.e_invdc[e];
   }
   double s = 0.0;
 #pragma unroll
@@ -149,11 +154,29 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_c1(MeshDev m, int n_c, doubl
     if (j < n) s = (code[j] & 1) ? s - x[j] : s + x[j];
   for (int j = kUnrollCell; j < n; ++j) {
     const int c = m.c_edge[j * m.cs + i];
-    const double y = G[c >> 1];
+    const double y = fb[c >> 1] * m.e_invdc[c >> 1];
     s = (c & 1) ? s - y : s + y;
   }
   BB[i] = s;
   hsb[i] = fma(g, s, hsb0);
+}
+
+// The edge records at the point (the forward's prep pass, q_v evaluated
+// inside unless LINEAR) and passes 1 and 2, independent of each other, in one
+// launch: threads [0, n_p) take the records of edges [0, n_p), the next n_e
+// threads pass 1 on edges [0, n_e), the next n_c pass 2 on cells [0, n_c).
+template <bool LINEAR>
+__global__ void __launch_bounds__(kBlock) k_phi_vjp_a(MeshDev m, int n_p, int n_e, int n_c, int drag, double g,
+                                                      const double* u, const double* hs, double* P,
+                                                      const double* cd, const double* fb, double* G, double* R,
+                                                      double* HD, double* CDB, double* ub, double* BB, double* hsb) {
+  const int t = tid_global();
+  if (t < n_p)
+    prep_record<LINEAR, !LINEAR>(m, t, 0, 1, m.E, u, hs, m.v_q0, P);
+  else if (t < n_p + n_e)
+    phi_vjp_e1(m, t - n_p, LINEAR, drag, u, hs, cd, fb, G, R, HD, CDB, ub);
+  else if (t < n_p + n_e + n_c)
+    phi_vjp_c1(m, t - n_p - n_e, g, fb, BB, hsb);
 }
 
 // Pass 3 (edges, edges_on_edge gathers): PV-flux transpose, drag perp transpose,
@@ -325,19 +348,24 @@ void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double*
     hipLaunchKernelGGL(k_psi_vjp_cell, grid_for(r.nc), dim3(kBlock), 0, st, m, r.nc, (const double*)T, hb);
 }
 
-// Scratch: G, R, HD, CDB, HE, QB (edges), BB (cells), ZA, HV (vertices).
+// Scratch: P (edge records), G, R, HD, CDB, HE, QB (edges), BB (cells), ZA, HV (vertices).
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
-                    const double* P, const double* cd, const double* fb, double* ub, double* hsb,
+                    double* P, const double* cd, const double* fb, double* ub, double* hsb,
                     double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
                     double* ZA, double* HV, const VjpRange& r, hipStream_t st) {
-  if (r.e1 > 0)
-    hipLaunchKernelGGL(k_phi_vjp_e1, grid_for(r.e1), dim3(kBlock), 0, st, m, r.e1, drag, u, P, cd, fb, G, R, HD,
-                       CDB, ub);
-  if (r.c1 > 0)
-    hipLaunchKernelGGL(k_phi_vjp_c1, grid_for(r.c1), dim3(kBlock), 0, st, m, r.c1, g, (const double*)G, BB, hsb);
+  const long na = (long)r.pe + r.e1 + r.c1;
+  if (na > 0) {
+    if (linear)
+      hipLaunchKernelGGL(k_phi_vjp_a<true>, grid_for(na), dim3(kBlock), 0, st, m, r.pe, r.e1, r.c1, drag, g, u, hs,
+                         P, cd, fb, G, R, HD, CDB, ub, BB, hsb);
+    else
+      hipLaunchKernelGGL(k_phi_vjp_a<false>, grid_for(na), dim3(kBlock), 0, st, m, r.pe, r.e1, r.c1, drag, g, u, hs,
+                         P, cd, fb, G, R, HD, CDB, ub, BB, hsb);
+  }
   if (r.e2 > 0)
-    hipLaunchKernelGGL(k_phi_vjp_e2, grid_for(r.e2), dim3(kBlock), 0, st, m, r.e2, linear, drag, u, P,
-                       (const double*)G, (const double*)R, (const double*)HD, (const double*)BB, QB, HE, ub);
+    hipLaunchKernelGGL(k_phi_vjp_e2, grid_for(r.e2), dim3(kBlock), 0, st, m, r.e2, linear, drag, u,
+                       (const double*)P, (const double*)G, (const double*)R, (const double*)HD, (const double*)BB, QB,
+                       HE, ub);
   if (!linear) {
     if (r.v1 > 0)
       hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(r.v1), dim3(kBlock), 0, st, m, r.v1, u, hs, (const double*)QB, ZA,

@@ -285,37 +285,6 @@ __global__ void __launch_bounds__(kBlock) k_vertex(const Launch<VertSeg> L) {
   vertex_body<ONE>(L, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-// q at an edge's two vertices v0, v1 from the per-edge copies of their lists:
-// the same operations, in the same order, as vertex_q.
-__device__ __forceinline__ void edge_vertices_q(const MeshDev& m, int e, int v0, int v1, const double* __restrict__ Usrc,
-                                                const double* __restrict__ hs, int nm, int mem, double& q0,
-                                                double& q1) {
-  int code[6], cell[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    code[k] = m.e_vq_edge[k * m.es + e];
-    cell[k] = m.e_vq_cell[k * m.es + e];
-  }
-  double q[2];
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const int v = side ? v1 : v0;
-    double circ = 0.0, hv = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int k = 3 * side + j;
-      const int ed = code[k] >> 1;
-      const double c = m.e_dc[ed] * Usrc[(long)ed * nm + mem];
-      circ = (code[k] & 1) ? circ - c : circ + c;
-      hv = fma(m.v_kite[j * m.vs + v], hs[(long)cell[k] * nm + mem], hv);
-    }
-    const double ia = m.v_invA[v];
-    q[side] = (circ * ia + m.v_f[v]) / (hv * ia);
-  }
-  q0 = q[0];
-  q1 = q[1];
-}
-
 // ---------------------------------------------------------------- prep pass
 // FUSE_Q: evaluate q at the edge's two vertices here instead of reading the
 // vertex pass's output (one launch fewer per stage, each vertex evaluated by
@@ -335,28 +304,7 @@ __device__ __forceinline__ void prep_body(const Launch<PrepSeg>& L, const int b)
   const int mem = (int)(item & ((1 << nm_log2) - 1));
   const int nm = 1 << nm_log2;
   const MeshDev& m = S.m;
-  const int c0 = m.e_cell[e], c1 = m.e_cell[m.es + e];
-  const int v0 = m.e_vert[e], v1 = m.e_vert[m.es + e];
-  const double u = S.Usrc[(long)e * nm + mem];
-  const double dv = m.e_dv[e];
-  double he, qe;
-  if constexpr (LINEAR) {
-    he = m.e_He[e];
-    qe = 0.5 * (S.q[v0] + S.q[v1]);
-  } else {
-    he = 0.5 * (S.hs[(long)c0 * nm + mem] + S.hs[(long)c1 * nm + mem]);
-    if (FUSE_Q) {
-      double q0, q1;
-      edge_vertices_q(m, e, v0, v1, S.Usrc, S.hs, nm, mem, q0, q1);
-      qe = 0.5 * (q0 + q1);
-    } else {
-      qe = 0.5 * (S.q[(long)v0 * nm + mem] + S.q[(long)v1 * nm + mem]);
-    }
-  }
-  const long k = (long)e * nm + mem, np = (long)m.E << nm_log2;
-  reinterpret_cast<double2*>(S.P)[k] = make_double2(dv * (he * u), qe);
-  S.P[2 * np + k] = dv * u;
-  S.P[3 * np + k] = he;
+  prep_record<LINEAR, FUSE_Q>(m, e, mem, nm, (long)m.E << nm_log2, S.Usrc, S.hs, S.q, S.P);
 }
 
 template <bool LINEAR, bool FUSE_Q, bool ONE>

@@ -1176,7 +1176,7 @@ void launch_lincomb(double* y, double b, const double* x0, double a0, const doub
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
                     double* hb, double* T, const PsiRange& r, hipStream_t st);
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
-                    const double* P, const double* cd, const double* fb, double* ub, double* hsb,
+                    double* P, const double* cd, const double* fb, double* ub, double* hsb,
                     double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
                     double* ZA, double* HV, const VjpRange& r, hipStream_t st);
 }  // namespace fblts
@@ -1264,12 +1264,8 @@ struct Rev {
     zero(ZA, r.v1, r.zZA);
     zero(HV, r.v1, r.zHV);
     flush();
-    // forward intermediates at the point: the edge records the passes read
-    // (q_v evaluated inside)
-    Launch<PrepSeg> pp{};
-    pp.nseg = 1;
-    pp.seg[0] = PrepSeg{*m, 0, 0, r.pe, linear ? 1 : 0, u, hs, linear ? m->v_q0 : nullptr, P};
-    launch_prep(pp, !linear, kBlock, st);
+    // the first launch also writes the forward intermediates at the point:
+    // the edge records the later passes read (q_v evaluated inside)
     launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, cd, fbar, ubar, hsbar, C[cdb], Ed[Ga], Ed[Ra],
                    Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, r, st);
   }
