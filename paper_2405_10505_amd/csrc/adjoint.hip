@@ -17,6 +17,8 @@
 // launch of the Phi transpose; the vertex transpose forms q_v itself.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fblts_internal.h"
 #include "lincomb.h"
 #include "prep_record.h"
@@ -41,11 +43,11 @@ __global__ void __launch_bounds__(kBlock) k_lincomb(double* y, double b, const d
   y[i] = v;
 }
 
-// A run of elementwise combinations in one launch: thread i applies every
-// descriptor whose range holds i, in order.  Each combination reads and writes
-// only index i of its arrays, so this equals launching them one after another.
-__global__ void __launch_bounds__(kBlock) k_lincomb_batch(const LinBatch B) {
-  const int i = tid_global();
+// A run of elementwise combinations: index i of every descriptor whose range
+// holds i, in order.  Each combination reads and writes only index i of its
+// arrays, so applying the run index by index equals launching the
+// combinations one after another.
+__device__ __forceinline__ void lin_apply(const LinBatch& B, int i) {
   for (int k = 0; k < B.n; ++k) {
     const LinDesc& D = B.d[k];
     if (i < D.begin || i >= D.end) continue;
@@ -56,6 +58,8 @@ __global__ void __launch_bounds__(kBlock) k_lincomb_batch(const LinBatch B) {
     D.y[i] = v;
   }
 }
+
+__global__ void __launch_bounds__(kBlock) k_lincomb_batch(const LinBatch B) { lin_apply(B, tid_global()); }
 
 // Cell-slot loops: the first kUnrollCell slots exist for every cell (padded
 // lists), so their loads issue together; slots past the cell's degree are
@@ -75,9 +79,7 @@ __global__ void __launch_bounds__(kBlock) k_psi_vjp_edge(MeshDev m, int n_e, int
 }
 
 // hb_i += (1/2) sum_{e in E_i} T_e.
-__global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, int n_c, const double* T, double* hb) {
-  const int i = tid_global();
-  if (i >= n_c) return;
+__device__ __forceinline__ void psi_vjp_cell(const MeshDev& m, int i, const double* T, double* hb) {
   const int n = m.c_nedge[i];
   const double hb0 = hb[i];
   double t[kUnrollCell];
@@ -89,6 +91,16 @@ __global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, int n_c, con
     if (j < n) s += t[j];
   for (int j = kUnrollCell; j < n; ++j) s += T[m.c_edge[j * m.cs + i] >> 1];
   hb[i] = fma(0.5, s, hb0);
+}
+
+// The Psi transpose's cell pass on cells [0, n_c), thread i on cell i, then
+// the combinations B at index i (an epilogue: the caller folds in only runs
+// that leave T alone, so no thread's epilogue touches what another reads).
+__global__ void __launch_bounds__(kBlock) k_psi_vjp_cell(MeshDev m, int n_c, const double* T, double* hb,
+                                                         const LinBatch B) {
+  const int i = tid_global();
+  if (i < n_c) psi_vjp_cell(m, i, T, hb);
+  lin_apply(B, i);
 }
 
 // ------------------------------------------------------------ Phi transpose
@@ -274,8 +286,11 @@ __global__ void __launch_bounds__(kBlock) k_phi_vjp_v1(MeshDev m, int n_v, const
   HV[v] = -qb * q / hvv * ia;
 }
 
-// Passes 5 and 6, independent of each other, in one launch: threads [0, n_e)
-// take the edges [0, n_e), threads [n_e, n_e + n_c) the cells [0, n_c).
+// Passes 5 and 6, independent of each other, in one launch: threads [0, n_c)
+// take the cells [0, n_c), threads [n_c, n_c + n_e) the edges [0, n_e); then
+// every thread i applies the combinations B at index i (an epilogue: the
+// caller folds in only runs that leave ZA, HE, HV, CDB and ub alone, so no
+// thread's epilogue touches what another thread reads or writes).
 // Edges: ub_e += d_e (ZA_{v1} - ZA_{v0})  (circulation sign +1 at v1).
 // Cells: hsb_i += (1/2) sum_{e in E_i} HE_e + sum_{v in V_i} kite_{i,v} HV_v;
 // cdb_i += (1/2) sum_{e in E_i} CDB_e.
@@ -318,12 +333,13 @@ __device__ __forceinline__ void phi_vjp_c2(const MeshDev& m, int i, int drag, co
 
 __global__ void __launch_bounds__(kBlock) k_phi_vjp_ec(MeshDev m, int n_e, int n_c, int drag, const double* ZA,
                                                        const double* HE, const double* HV, const double* CDB,
-                                                       double* ub, double* hsb, double* cdb) {
+                                                       double* ub, double* hsb, double* cdb, const LinBatch B) {
   const int t = tid_global();
-  if (t < n_e)
-    phi_vjp_e3(m, t, ZA, ub);
-  else if (t < n_e + n_c)
-    phi_vjp_c2(m, t - n_e, drag, HE, HV, CDB, hsb, cdb);
+  if (t < n_c)
+    phi_vjp_c2(m, t, drag, HE, HV, CDB, hsb, cdb);
+  else if (t < n_c + n_e)
+    phi_vjp_e3(m, t - n_c, ZA, ub);
+  lin_apply(B, t);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -340,19 +356,26 @@ void launch_lincomb_batch(const LinBatch& B, hipStream_t st) {
   hipLaunchKernelGGL(k_lincomb_batch, grid_for(B.end_max), dim3(kBlock), 0, st, B);
 }
 
+// The Psi transpose up to its cell pass, which launch_psi_vjp_cells runs.
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
-                    double* hb, double* T, const PsiRange& r, hipStream_t st) {
+                    double* T, const PsiRange& r, hipStream_t st) {
   if (r.ne > 0)
     hipLaunchKernelGGL(k_psi_vjp_edge, grid_for(r.ne), dim3(kBlock), 0, st, m, r.ne, linear, u, h, pb, ub, T);
-  if (!linear && r.nc > 0)
-    hipLaunchKernelGGL(k_psi_vjp_cell, grid_for(r.nc), dim3(kBlock), 0, st, m, r.nc, (const double*)T, hb);
 }
 
+// The cell pass (nonlinear only) with the combinations B as its epilogue.
+void launch_psi_vjp_cells(const MeshDev& m, int n_c, const double* T, double* hb, const LinBatch& B,
+                          hipStream_t st) {
+  const long n = std::max<long>(n_c, B.n > 0 ? B.end_max : 0);
+  if (n > 0) hipLaunchKernelGGL(k_psi_vjp_cell, grid_for(n), dim3(kBlock), 0, st, m, n_c, T, hb, B);
+}
+
+// Passes 0-4 of the Phi transpose (passes 5 and 6: launch_phi_vjp_ec).
 // Scratch: P (edge records), G, R, HD, CDB, HE, QB (edges), BB (cells), ZA, HV (vertices).
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
-                    double* P, const double* cd, const double* fb, double* ub, double* hsb,
-                    double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
-                    double* ZA, double* HV, const VjpRange& r, hipStream_t st) {
+                    double* P, const double* cd, const double* fb, double* ub, double* hsb, double* G, double* R,
+                    double* HD, double* CDB, double* HE, double* QB, double* BB, double* ZA, double* HV,
+                    const VjpRange& r, hipStream_t st) {
   const long na = (long)r.pe + r.e1 + r.c1;
   if (na > 0) {
     if (linear)
@@ -366,14 +389,18 @@ void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const doub
     hipLaunchKernelGGL(k_phi_vjp_e2, grid_for(r.e2), dim3(kBlock), 0, st, m, r.e2, linear, drag, u,
                        (const double*)P, (const double*)G, (const double*)R, (const double*)HD, (const double*)BB, QB,
                        HE, ub);
-  if (!linear) {
-    if (r.v1 > 0)
-      hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(r.v1), dim3(kBlock), 0, st, m, r.v1, u, hs, (const double*)QB, ZA,
-                         HV);
-    if (r.e3 + r.c3 > 0)
-      hipLaunchKernelGGL(k_phi_vjp_ec, grid_for((long)r.e3 + r.c3), dim3(kBlock), 0, st, m, r.e3, r.c3, drag,
-                         (const double*)ZA, (const double*)HE, (const double*)HV, (const double*)CDB, ub, hsb, cdb);
-  }
+  if (!linear && r.v1 > 0)
+    hipLaunchKernelGGL(k_phi_vjp_v1, grid_for(r.v1), dim3(kBlock), 0, st, m, r.v1, u, hs, (const double*)QB, ZA, HV);
+}
+
+// Passes 5 and 6 (nonlinear only) with the combinations B as their epilogue.
+void launch_phi_vjp_ec(const MeshDev& m, int n_e, int n_c, int drag, const double* ZA, const double* HE,
+                       const double* HV, const double* CDB, double* ub, double* hsb, double* cdb, const LinBatch& B,
+                       hipStream_t st) {
+  const long n = std::max<long>((long)n_e + n_c, B.n > 0 ? B.end_max : 0);
+  if (n > 0)
+    hipLaunchKernelGGL(k_phi_vjp_ec, grid_for(n), dim3(kBlock), 0, st, m, n_e, n_c, drag, ZA, HE, HV, CDB, ub, hsb,
+                       cdb, B);
 }
 
 }  // namespace fblts

@@ -1174,11 +1174,16 @@ void launch_lincomb_batch(const LinBatch& B, hipStream_t st);
 void launch_lincomb(double* y, double b, const double* x0, double a0, const double* x1, double a1, const double* x2,
                     double a2, int begin, int end, hipStream_t st);
 void launch_psi_vjp(const MeshDev& m, int linear, const double* u, const double* h, const double* pb, double* ub,
-                    double* hb, double* T, const PsiRange& r, hipStream_t st);
+                    double* T, const PsiRange& r, hipStream_t st);
+void launch_psi_vjp_cells(const MeshDev& m, int n_c, const double* T, double* hb, const LinBatch& B,
+                          hipStream_t st);
 void launch_phi_vjp(const MeshDev& m, int linear, int drag, double g, const double* u, const double* hs,
-                    double* P, const double* cd, const double* fb, double* ub, double* hsb,
-                    double* cdb, double* G, double* R, double* HD, double* CDB, double* HE, double* QB, double* BB,
-                    double* ZA, double* HV, const VjpRange& r, hipStream_t st);
+                    double* P, const double* cd, const double* fb, double* ub, double* hsb, double* G, double* R,
+                    double* HD, double* CDB, double* HE, double* QB, double* BB, double* ZA, double* HV,
+                    const VjpRange& r, hipStream_t st);
+void launch_phi_vjp_ec(const MeshDev& m, int n_e, int n_c, int drag, const double* ZA, const double* HE,
+                       const double* HV, const double* CDB, double* ub, double* hsb, double* cdb, const LinBatch& B,
+                       hipStream_t st);
 }  // namespace fblts
 
 namespace {
@@ -1220,10 +1225,64 @@ struct Rev {
   PsiRange psi_all, psi_f12, psi_f3;
   // Inside a reverse step the elementwise combinations between two tendency
   // transposes are collected and launched as one batch (same arithmetic per
-  // element, in the same order); elsewhere each launches at once.
+  // element, in the same order); elsewhere each launches at once.  The last
+  // kernel of a transpose (Psi's cell pass, Phi's passes 5-6) waits for the
+  // next flush, which hands it the collected batch as an epilogue (thread i
+  // applies the batch at index i after its own item) when no combination
+  // writes an array that kernel reads at other indices or reads or writes
+  // one it writes from another thread; otherwise the batch follows it.
   bool batching = false;
   LinBatch pending;
+  struct Tail {
+    int kind = 0;   // 0 none, 1 Psi cell pass, 2 Phi passes 5-6
+    int n_e = 0, n_c = 0;
+    const double* T = nullptr;   // Psi: gathered
+    double* hb = nullptr;        // Psi: written by thread i at index i
+    // Phi: ZA, HE, HV, CDB gathered; hsb, cdb written by thread i at index i
+    // (cells first); ub written by thread n_c + e at index e
+    const double *ZA = nullptr, *HE = nullptr, *HV = nullptr, *CDB = nullptr;
+    double *ub = nullptr, *hsb = nullptr, *cdb = nullptr;
+  } tail;
+  bool foldable() const {
+    const void* gathered[4] = {tail.T, nullptr, nullptr, nullptr};
+    const void* other = nullptr;   // written from another thread than its index
+    if (tail.kind == 2) {
+      gathered[0] = tail.ZA;
+      gathered[1] = tail.HE;
+      gathered[2] = tail.HV;
+      gathered[3] = tail.CDB;
+      other = tail.ub;
+    }
+    auto in = [&](const void* p) {
+      if (!p) return false;
+      for (const void* q : gathered)
+        if (q == p) return true;
+      return p == other;
+    };
+    for (int k = 0; k < pending.n; ++k) {
+      const LinDesc& d = pending.d[k];
+      if (in(d.y)) return false;
+      for (const void* x : {(const void*)d.x0, (const void*)d.x1, (const void*)d.x2})
+        if (x && x == other) return false;
+    }
+    return true;
+  }
+  void launch_tail(const LinBatch& B) {
+    if (tail.kind == 1) launch_psi_vjp_cells(*m, tail.n_c, tail.T, tail.hb, B, st);
+    else launch_phi_vjp_ec(*m, tail.n_e, tail.n_c, drag ? 1 : 0, tail.ZA, tail.HE, tail.HV, tail.CDB, tail.ub,
+                           tail.hsb, tail.cdb, B, st);
+    tail.kind = 0;
+  }
   void flush() {
+    if (tail.kind != 0) {
+      if (pending.n > 0 && foldable()) {
+        launch_tail(pending);
+        pending.n = 0;
+        pending.end_max = 0;
+        return;
+      }
+      launch_tail(LinBatch{});
+    }
     launch_lincomb_batch(pending, st);
     pending.n = 0;
     pending.end_max = 0;
@@ -1247,7 +1306,15 @@ struct Rev {
                const PsiRange& r) {
     zero(Ed[Ta], r.ne, r.zT);
     flush();
-    launch_psi_vjp(*m, linear ? 1 : 0, u, h, pbar, ubar, hbar, Ed[Ta], r, st);
+    launch_psi_vjp(*m, linear ? 1 : 0, u, h, pbar, ubar, Ed[Ta], r, st);
+    if (!linear && r.nc > 0) {
+      tail = Tail{};
+      tail.kind = 1;
+      tail.n_c = r.nc;
+      tail.T = Ed[Ta];
+      tail.hb = hbar;
+      if (!batching) flush();
+    }
   }
   // cotangent fbar of Phi(u, hs) (zero past the range's support) -> ubar
   // (accumulated), hsbar (overwritten), C_D (accumulated)
@@ -1266,8 +1333,22 @@ struct Rev {
     flush();
     // the first launch also writes the forward intermediates at the point:
     // the edge records the later passes read (q_v evaluated inside)
-    launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, cd, fbar, ubar, hsbar, C[cdb], Ed[Ga], Ed[Ra],
-                   Ed[HDa], Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, r, st);
+    launch_phi_vjp(*m, linear ? 1 : 0, drag ? 1 : 0, g, u, hs, P, cd, fbar, ubar, hsbar, Ed[Ga], Ed[Ra], Ed[HDa],
+                   Ed[CDBa], Ed[HEa], Ed[QBa], C[BBa], ZA, HV, r, st);
+    if (!linear && r.e3 + r.c3 > 0) {
+      tail = Tail{};
+      tail.kind = 2;
+      tail.n_e = r.e3;
+      tail.n_c = r.c3;
+      tail.ZA = ZA;
+      tail.HE = Ed[HEa];
+      tail.HV = HV;
+      tail.CDB = Ed[CDBa];
+      tail.ub = ubar;
+      tail.hsb = hsbar;
+      tail.cdb = C[cdb];
+      if (!batching) flush();
+    }
   }
   // One reverse step: (hNb, uNb) = cotangent of the step's output -> (hb, ub)
   // = cotangent of its input; C_D's cotangent accumulates.  tc / te: tape.
