@@ -425,19 +425,25 @@ __device__ __forceinline__ void edge_body(const Launch<EdgeSeg>& L, const int b)
     walk_cell<DRAG || WIND>(m, P, np, m.e_cell[m.es + e], (w >> 8) & 0xff, pey, nm, mem, sq, su);
   } else if (GROUP) {
     const int lane = threadIdx.x & 63, base = lane & ~15, r = lane & 15;
+    const int n = m.e_neoe[e];
     int idx_r = e;
     double w_r = 0.0;
     if (r < m.maxEOE) {
       idx_r = m.e_eoe[r * m.es + e];
       w_r = m.e_w[r * m.es + e];
     }
+    // a padded slot (past the edge's list) only takes part in the permutes:
+    // its term would add an exact zero (sq and su are never -0), so its
+    // gathers are not issued
     auto slot = [&](int j) {
       const int e2 = __shfl(idx_r, base + j);
       const double w = __shfl(w_r, base + j);
-      const long k2 = (long)e2 * nm + mem;
-      const double2 p2 = rec_fq(P, k2);
-      sq = fma(w * p2.x, pey + p2.y, sq);
-      if (DRAG || WIND) su = fma(w, rec_lu(P, np, k2), su);
+      if (j < kEOEFull || j < n) {
+        const long k2 = (long)e2 * nm + mem;
+        const double2 p2 = rec_fq(P, k2);
+        sq = fma(w * p2.x, pey + p2.y, sq);
+        if (DRAG || WIND) su = fma(w, rec_lu(P, np, k2), su);
+      }
     };
 #pragma unroll
     for (int j = 0; j < kUnrollEOE; ++j) slot(j);
